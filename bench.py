@@ -1,0 +1,159 @@
+"""Benchmark: likelihood evaluations per second on one MI355X.
+
+A step is one plain single-point evaluation of the whole path (device
+E-integral, weights, HBM-streaming fold of the 16384 x 4096 FP32 response,
+Poisson -2lnL) at a fresh parameter point, with every input resident in HBM.
+The K timed steps are one HIP-graph replay of K evaluations.
+
+Prints one JSON line (see the design doc for the field definitions).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = ("likelihood evals/s at |Δ(−2lnL)|≤1e-3 vs FP64: "
+          "plain vs batched/grad/surrogate")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def build_plain(cfg_id=1):
+    import synth
+    import paper_2607_00488_amd as nr
+    c = synth.CONFIGS[cfg_id]
+    s = c.seeds(0)
+    t0 = time.time()
+    src = synth.source_nodes(c.n_e)
+    rsp = synth.response_mc(c.n_t, c.n_reco, c.n_mc, seed=s["response"],
+                            keep_counts=False)
+    log(f"[bench] response MC {c.n_mc:.0e} events in {time.time() - t0:.1f}s")
+    b = np.full(c.n_reco, c.bkg)
+    ctx = nr.Context(0)
+    ctx.set_sources(src, c.n_t)
+    ctx.set_response(rsp.R, n_sig=c.n_sig)
+    # toy data drawn from the library's own SM expectation
+    ctx.set_data(b, b)
+    mu_sm = ctx.eval_mu(synth.theta_sm())[0]
+    n = synth.poisson_data(mu_sm, s["data"])
+    ctx.set_data(n, b)
+    return dict(cfg=c, seeds=s, src=src, R=rsp.R, b=b, n=n, ctx=ctx)
+
+
+def cpu_baseline(p, n_eval, gpu_ctx):
+    """The FP64 oracle on the host cores for a bounded sample of points, and
+    the GPU's -2lnL on the same inputs for the |Delta| column."""
+    import oracle
+    import synth
+    c = p["cfg"]
+    o = oracle.Oracle()
+    o.set_sources(p["src"], c.n_t)
+    o.set_response(p["R"], n_sig=c.n_sig)
+    sig = o.mu(oracle.THETA_SM)
+    n = synth.poisson_data(sig + p["b"], p["seeds"]["data"])
+    o.set_data(n, p["b"])
+    th = synth.theta_prior(n_eval, p["seeds"]["theta"] + 17)
+    o.nll(th[0])  # warm-up (page-in of the response)
+    t0 = time.perf_counter()
+    ref = [o.nll(t) for t in th]
+    dt = time.perf_counter() - t0
+    gpu_ctx.set_data(n, p["b"])
+    got = gpu_ctx.eval_nll(th)
+    gpu_ctx.set_data(p["n"], p["b"])
+    return dict(value=n_eval / dt, unit="evals/s", cores=oracle.get_threads(),
+                kind="oracle",
+                sample=f"{n_eval} plain evaluations at the same 16384x4096 "
+                       f"workload (prior-box points), FP64, OpenMP over bins",
+                seconds=dt), float(np.max(np.abs(np.array(got) - ref)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--cpu-evals", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU "
+              "path (a parameter scan shards by points with no collective; "
+              "see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    p = build_plain(1)
+    ctx, c = p["ctx"], p["cfg"]
+    K, W = args.steps, args.warmup
+    th = synth.theta_prior(K, p["seeds"]["theta"])
+    tt = torch.tensor(th, dtype=torch.float64, device=dev)
+    out = torch.empty(K, dtype=torch.float64, device=dev)
+    thw = torch.tensor(synth.theta_prior(max(W, 1), p["seeds"]["theta"] + 1),
+                       dtype=torch.float64, device=dev)
+    outw = torch.empty(max(W, 1), dtype=torch.float64, device=dev)
+    stream = torch.cuda.Stream(device=dev)
+    # warm-up: captures the K-point and W-point graphs and runs them once
+    ctx.eval_nll_dev(thw, outw, stream=stream)
+    ctx.eval_nll_dev(tt, out, stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.eval_nll_dev(tt, out, stream=stream)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt * 1e3 / K
+    evals_s = K / dt
+    log(f"[bench] plain: {ms_step * 1e3:.2f} us/eval, {evals_s:.0f} evals/s")
+
+    # host-visible synchronous latency (paper protocol: 10 calls, drop 1st)
+    lat = []
+    for i in range(10):
+        t1 = time.perf_counter()
+        ctx.eval_nll(th[i])
+        lat.append(time.perf_counter() - t1)
+    lat = np.array(lat[1:]) * 1e3
+
+    # roofline of the dominant kernel (fold + likelihood), HIP events on the
+    # context stream around back-to-back launches
+    fold_ms = ctx.time_stage(2, 200)
+    eint_ms = ctx.time_stage(1, 200)
+    alg_bytes = 4 * c.n_t * c.n_reco + 4 * c.n_t + 16 * c.n_reco
+    achieved = alg_bytes / (fold_ms * 1e-3) / 1e9
+    roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=None, kernel="k_fold",
+                avg_kernel_us=round(fold_ms * 1e3, 2),
+                algorithmic_bytes=alg_bytes)
+    res = dict(metric=METRIC, value=round(evals_s, 1), unit="evals/s",
+               n_gpus=1, steps=K, warmup=W, ms_per_step=round(ms_step, 5),
+               higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="f32", data="synthetic",
+               config=dict(workload="plain single-point eval: N_T=16384 "
+                           "recoil bins, N_reco=4096, N_E=2048 per continuum "
+                           "(5 solar sources), dense FP32 response 256 MiB "
+                           "from 1e8 seeded MC events",
+                           n_t=c.n_t, n_reco=c.n_reco, n_e=c.n_e),
+               roofline=roof,
+               detail=dict(sync_latency_ms_mean=round(float(lat.mean()), 4),
+                           sync_latency_ms_std=round(float(lat.std()), 4),
+                           eint_kernel_us=round(eint_ms * 1e3, 2)))
+    if not args.no_cpu_baseline:
+        cb, dmax = cpu_baseline(p, args.cpu_evals, ctx)
+        res["cpu_baseline"] = cb
+        res["detail"]["max_abs_dnll_vs_oracle"] = dmax
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

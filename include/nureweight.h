@@ -1,0 +1,156 @@
+/*
+ * nureweight -- spectrum-reweighting likelihood for solar neutrino-electron
+ * scattering on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  One context = one analysis (a set
+ * of solar sources on a recoil grid, one detector response, one binned data
+ * set) bound to one device and one HIP stream.
+ *
+ * The method (arXiv:2607.00488):
+ *   - NSI-shifted chiral couplings, Sec. II.B, Eq. (g_tilde);
+ *   - weak dsigma/dT, Sec. II.A, Eq. (sm_cross_section), with Eq. (xs_nsi);
+ *   - magnetic-moment term summed incoherently, Sec. II.C, Eqs. (xs_mm),
+ *     (xs_total);
+ *   - recoil spectrum S_theta(T_l), Sec. III.A, Eq. (fT), flavour sum as in
+ *     Eq. (rate_sm); the kinematic limit T <= 2E^2/(m_e+2E);
+ *   - weights w_l = S_theta(T_l) / S_SM(T_l), Eqs. (fT_norm),
+ *     (reweight_factor), with w_l := 1 where S_SM(T_l) = 0;
+ *   - fold mu_j = f_bkg b_j + sum_l m_l R_lj w_l, Eqs. (Rij),
+ *     (fNp_reweight), (mu_total) (matrix form Eq. (matrix_reweight));
+ *   - -2lnL = 2 sum_j [mu_j - n_j ln mu_j + lnGamma(n_j+1)]
+ *             + sum_m (theta_m - mean_m)^2 / sigma_m^2,  Eq. (logL).
+ *
+ * Parameter point: 7 doubles,
+ *   theta = [eps_eL, eps_eR, eps_tauL, eps_tauR, m2, f_8B, f_bkg],
+ * eps_ee^{L,R} and eps_tautau^{L,R} of Eq. (g_tilde) (eps_mumu = 0),
+ * m2 = (mu_nu / 1e-11 mu_B)^2 (the square of the moment of Eq. (xs_mm)),
+ * f_8B scales every source with group = 1, f_bkg scales the background b.
+ *
+ * Status codes: 0 ok; NR_EINVAL (-1) bad argument (null pointer, size <= 0,
+ * non-finite value, negative counts, size mismatch between the set_* calls);
+ * NR_ESTATE (-2) an eval before set_sources, set_response and set_data;
+ * NR_EHIP (-3) a HIP runtime error; NR_ENOMEM (-4) allocation failure.
+ * On a non-zero return nr_last_error() gives a message (thread-local).
+ * A point whose expectation mu_j <= 0 in a bin with n_j > 0 returns
+ * -2lnL = +inf with status 0.
+ *
+ * Ownership: every set_* call copies what it is given before returning; the
+ * caller keeps its arrays.  Outputs are caller-allocated.  The _dev entry
+ * points borrow device pointers, enqueue on the given stream (NULL = the
+ * context's stream) and do not synchronise.  A context is not thread-safe.
+ */
+#ifndef NUREWEIGHT_H
+#define NUREWEIGHT_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NR_OK 0
+#define NR_EINVAL (-1)
+#define NR_ESTATE (-2)
+#define NR_EHIP (-3)
+#define NR_ENOMEM (-4)
+
+#define NR_NTHETA 7
+
+typedef struct nr_ctx nr_ctx;
+
+/* One solar source (Sec. III.A).  kind 1: tabulated continuum whose node
+ * weights are phi(E_j) * dE (Eq. (fT)); kind 0: a line, whose single node
+ * carries the line flux.  p_ee: nu_e survival probability at each node
+ * (the nu_mu and nu_tau shares of 1 - p_ee are set by tau_frac).  group 1:
+ * scaled by f_8B.  Node order is free. */
+typedef struct {
+    int kind;
+    int n;
+    const double *E;       /* [n] MeV, > 0 */
+    const double *weight;  /* [n] >= 0; only ratios between nodes matter */
+    const double *p_ee;    /* [n] in [0, 1] */
+    int group;             /* 0 fixed, 1 scaled by f_8B */
+} nr_source;
+
+/* Physical constants; NULL in nr_set_sources selects the defaults
+ * m_e = 0.51099895 MeV, G_F = 1.1663788e-11 MeV^-2, sin^2 theta_W = 0.23122
+ * (tree level, Sec. II.A), alpha_em = 1/137.035999084, tau_frac = 0.5. */
+typedef struct {
+    double me, gf, sw2, alpha_em, tau_frac;
+} nr_physics;
+
+/* Create a context on HIP device `device`.  *out receives the handle. */
+int nr_create(int device, nr_ctx **out);
+void nr_destroy(nr_ctx *ctx);
+
+/* Sources and the recoil grid: n_t bins on [t_lo, t_hi], bin l represented
+ * by its centre (Sec. V.A, the single representative energy per bin).
+ * Computes the SM reference S_SM(T_l) on the device (Eq. (fT) at theta_SM,
+ * Sec. III.A last paragraph) and every theta-independent table. */
+int nr_set_sources(nr_ctx *ctx, const nr_source *src, int n_src, int n_t,
+                   double t_lo, double t_hi, const nr_physics *phys);
+
+/* Detector response R[l][j] (row-major, l = true recoil bin, j = observed
+ * bin; float32, n_t * n_reco values) and the row factors m_l of the fold
+ * (Eq. (Rij) with the joint response written as m_l R_lj).  m == NULL
+ * selects m_l = n_sig * S_SM(T_l) / sum_l' S_SM(T_l') -- R is then the
+ * conditional response P(E_vis,j | T_l) of Eq. (visible_spectrum) and the
+ * SM prediction holds n_sig * efficiency signal counts; this needs
+ * nr_set_sources first.  Copies R to device memory. */
+int nr_set_response(nr_ctx *ctx, const float *R, int n_t, int n_reco,
+                    const double *m, double n_sig);
+
+/* Binned data n_j >= 0 (real values allowed: Asimov data), background
+ * template b_j >= 0 (scaled by f_bkg), and optional Gaussian pulls on the
+ * seven parameters (pull_sigma[i] <= 0: no pull on i; both NULL: none). */
+int nr_set_data(nr_ctx *ctx, const double *n, const double *b, int n_reco,
+                const double *pull_mean, const double *pull_sigma);
+
+/* -2lnL for n_pts points (theta: [n_pts][7], host), one plain single-point
+ * evaluation per point: device E-integral, weights, HBM-streaming fold and
+ * likelihood reduction.  nll: [n_pts] host.  Synchronous. */
+int nr_eval_nll(nr_ctx *ctx, const double *theta, int n_pts, double *nll);
+
+/* -2lnL and its gradient d(-2lnL)/d theta ([n_pts][7]) per point, through
+ * the adjoint of the fold (a second pass over R).  Synchronous. */
+int nr_eval_nll_grad(nr_ctx *ctx, const double *theta, int n_pts,
+                     double *nll, double *grad);
+
+/* Expected spectrum mu ([n_pts][n_reco], host) per point.  Synchronous. */
+int nr_eval_mu(nr_ctx *ctx, const double *theta, int n_pts, double *mu);
+
+/* Device-pointer variant of nr_eval_nll / nr_eval_nll_grad: d_theta
+ * [n_pts][7] double, d_nll [n_pts] double, d_grad [n_pts][7] double or
+ * NULL.  Enqueued on `stream` (hipStream_t, NULL = the context stream);
+ * returns without waiting.  Replays a cached HIP graph for repeated
+ * (pointer, n_pts) combinations. */
+int nr_eval_nll_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
+                    double *d_nll, double *d_grad, void *stream);
+
+/* Weights w_l = S_theta(T_l) / S_SM(T_l) ([n_pts][n_t], host) as the
+ * single-point path forms them before the fold.  Synchronous. */
+int nr_eval_weights(nr_ctx *ctx, const double *theta, int n_pts, double *w);
+
+/* Copies the recoil spectra the context holds: S_SM [n_t] (device FP64
+ * E-integral at theta_SM) and the row factors m [n_t] in use. */
+int nr_get_reference(nr_ctx *ctx, double *s_sm, double *m);
+
+/* The context's HIP stream (hipStream_t), for callers that order their own
+ * work against it. */
+void *nr_stream(nr_ctx *ctx);
+
+/* Average device time in milliseconds of one kernel of the single-point
+ * path, launched `iters` times back to back on the context stream between
+ * HIP events (stage 1: E-integral, 2: fold + likelihood, 3: adjoint).  The
+ * last evaluated point's inputs are reused.  For roofline measurements. */
+int nr_time_stage(nr_ctx *ctx, int stage, int iters, double *avg_ms);
+
+/* Tuning knobs of the fold kernel (0 keeps the current value): rows per
+ * work-group and column chunks; for sweeps. */
+int nr_set_fold_tiling(nr_ctx *ctx, int rows_per_wg, int use_graph);
+
+/* Message for the last non-zero status on this thread. */
+const char *nr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

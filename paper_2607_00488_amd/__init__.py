@@ -1,0 +1,287 @@
+"""MI355X-native spectrum-reweighting likelihood (arXiv:2607.00488).
+
+Thin ctypes binding over ``libnureweight.so``.  The functions ``nr_*`` carry
+the names and arguments of the C ABI declared in ``include/nureweight.h``;
+:class:`Context` wraps them for numpy and torch callers.  Every step of the
+likelihood runs in the library's HIP kernels; this module only marshals
+arguments.  Importing works without a GPU; any call that needs the library
+raises if it has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from ._build import LIB as _LIB_PATH
+
+NR_NTHETA = 7
+NR_OK, NR_EINVAL, NR_ESTATE, NR_EHIP, NR_ENOMEM = 0, -1, -2, -3, -4
+
+# Exported symbols of include/nureweight.h.
+EXPORTS = (
+    "nr_create", "nr_destroy", "nr_set_sources", "nr_set_response",
+    "nr_set_data", "nr_eval_nll", "nr_eval_nll_grad", "nr_eval_mu",
+    "nr_eval_nll_dev", "nr_eval_weights", "nr_get_reference", "nr_stream",
+    "nr_time_stage", "nr_set_fold_tiling", "nr_last_error",
+)
+
+
+class NrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nureweight error {code}: {msg}")
+        self.code = code
+
+
+class nr_source(C.Structure):
+    _fields_ = [("kind", C.c_int), ("n", C.c_int),
+                ("E", C.POINTER(C.c_double)),
+                ("weight", C.POINTER(C.c_double)),
+                ("p_ee", C.POINTER(C.c_double)), ("group", C.c_int)]
+
+
+class nr_physics(C.Structure):
+    _fields_ = [("me", C.c_double), ("gf", C.c_double), ("sw2", C.c_double),
+                ("alpha_em", C.c_double), ("tau_frac", C.c_double)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load the built library; raises if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # One HIP runtime per process: when PyTorch is importable, let its
+    # bundled runtime be the one the library binds to (same soname).
+    try:
+        import torch  # noqa: F401
+    except Exception:
+        pass
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(
+            f"{_LIB_PATH} is not built; run __graft_entry__.build() or "
+            "python -m paper_2607_00488_amd._build")
+    L = C.CDLL(_LIB_PATH)
+    P, I, D = C.c_void_p, C.c_int, C.c_double
+    pD = C.POINTER(C.c_double)
+    L.nr_create.argtypes = [I, C.POINTER(P)]
+    L.nr_destroy.argtypes = [P]
+    L.nr_destroy.restype = None
+    L.nr_set_sources.argtypes = [P, C.POINTER(nr_source), I, I, D, D,
+                                 C.POINTER(nr_physics)]
+    L.nr_set_response.argtypes = [P, C.POINTER(C.c_float), I, I, pD, D]
+    L.nr_set_data.argtypes = [P, pD, pD, I, pD, pD]
+    L.nr_eval_nll.argtypes = [P, pD, I, pD]
+    L.nr_eval_nll_grad.argtypes = [P, pD, I, pD, pD]
+    L.nr_eval_mu.argtypes = [P, pD, I, pD]
+    L.nr_eval_weights.argtypes = [P, pD, I, pD]
+    L.nr_eval_nll_dev.argtypes = [P, P, I, P, P, P]
+    L.nr_get_reference.argtypes = [P, pD, pD]
+    L.nr_stream.argtypes = [P]
+    L.nr_stream.restype = P
+    L.nr_time_stage.argtypes = [P, I, I, pD]
+    L.nr_set_fold_tiling.argtypes = [P, I, I]
+    L.nr_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if name not in ("nr_destroy", "nr_stream", "nr_last_error"):
+            fn.restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise NrError(rc, load().nr_last_error().decode())
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+# ----------------------------------------------------------- C-ABI names
+def nr_create(device: int = 0):
+    h = C.c_void_p()
+    _check(load().nr_create(int(device), C.byref(h)))
+    return h
+
+
+def nr_destroy(h):
+    load().nr_destroy(h)
+
+
+def nr_set_sources(h, sources, n_t, t_lo=0.0, t_hi=16.0, physics=None):
+    keep = []
+    arr = (nr_source * len(sources))()
+    for i, s in enumerate(sources):
+        E, w, p = (_f64(s["E"]), _f64(s["weight"]), _f64(s["p_ee"]))
+        keep += [E, w, p]
+        arr[i] = nr_source(int(s["kind"]), len(E), _dp(E), _dp(w), _dp(p),
+                           int(s["group"]))
+    ph = None
+    if physics is not None:
+        ph = C.byref(nr_physics(*[float(x) for x in physics]))
+    _check(load().nr_set_sources(h, arr, len(sources), int(n_t), float(t_lo),
+                                 float(t_hi), ph))
+
+
+def nr_set_response(h, R, m=None, n_sig=1.0e4):
+    R = np.ascontiguousarray(R, dtype=np.float32)
+    pm = None
+    if m is not None:
+        m = _f64(m)
+        pm = _dp(m)
+    _check(load().nr_set_response(h, R.ctypes.data_as(C.POINTER(C.c_float)),
+                                  R.shape[0], R.shape[1], pm, float(n_sig)))
+
+
+def nr_set_data(h, n, b, pull_mean=None, pull_sigma=None):
+    n, b = _f64(n), _f64(b)
+    pm = ps = None
+    if pull_mean is not None:
+        pmv, psv = _f64(pull_mean), _f64(pull_sigma)
+        pm, ps = _dp(pmv), _dp(psv)
+    _check(load().nr_set_data(h, _dp(n), _dp(b), len(n), pm, ps))
+
+
+def nr_eval_nll(h, theta):
+    th = _f64(theta, (-1, NR_NTHETA))
+    out = np.empty(th.shape[0])
+    _check(load().nr_eval_nll(h, _dp(th), th.shape[0], _dp(out)))
+    return out
+
+
+def nr_eval_nll_grad(h, theta):
+    th = _f64(theta, (-1, NR_NTHETA))
+    out = np.empty(th.shape[0])
+    g = np.empty((th.shape[0], NR_NTHETA))
+    _check(load().nr_eval_nll_grad(h, _dp(th), th.shape[0], _dp(out), _dp(g)))
+    return out, g
+
+
+def nr_eval_mu(h, theta, n_reco):
+    th = _f64(theta, (-1, NR_NTHETA))
+    out = np.empty((th.shape[0], n_reco))
+    _check(load().nr_eval_mu(h, _dp(th), th.shape[0], _dp(out)))
+    return out
+
+
+def nr_eval_weights(h, theta, n_t):
+    th = _f64(theta, (-1, NR_NTHETA))
+    out = np.empty((th.shape[0], n_t))
+    _check(load().nr_eval_weights(h, _dp(th), th.shape[0], _dp(out)))
+    return out
+
+
+def nr_eval_nll_dev(h, d_theta_ptr, n_pts, d_nll_ptr, d_grad_ptr=None,
+                    stream_ptr=None):
+    _check(load().nr_eval_nll_dev(h, C.c_void_p(d_theta_ptr), int(n_pts),
+                                  C.c_void_p(d_nll_ptr),
+                                  C.c_void_p(d_grad_ptr or 0),
+                                  C.c_void_p(stream_ptr or 0)))
+
+
+def nr_get_reference(h, n_t):
+    s = np.empty(n_t)
+    m = np.empty(n_t)
+    _check(load().nr_get_reference(h, _dp(s), _dp(m)))
+    return s, m
+
+
+def nr_stream(h):
+    return load().nr_stream(h)
+
+
+def nr_time_stage(h, stage, iters):
+    v = C.c_double()
+    _check(load().nr_time_stage(h, int(stage), int(iters), C.byref(v)))
+    return v.value
+
+
+def nr_set_fold_tiling(h, rows_per_wg=0, use_graph=-1):
+    _check(load().nr_set_fold_tiling(h, int(rows_per_wg), int(use_graph)))
+
+
+def nr_last_error():
+    return load().nr_last_error().decode()
+
+
+# --------------------------------------------------------------- wrapper
+class Context:
+    """One analysis bound to one device (numpy / torch convenience)."""
+
+    def __init__(self, device: int = 0):
+        self.h = nr_create(device)
+        self.device = device
+        self.n_t = self.n_reco = None
+
+    def close(self):
+        if self.h is not None:
+            nr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_sources(self, sources, n_t, t_lo=0.0, t_hi=16.0, physics=None):
+        nr_set_sources(self.h, sources, n_t, t_lo, t_hi, physics)
+        self.n_t = int(n_t)
+
+    def set_response(self, R, m=None, n_sig=1.0e4):
+        nr_set_response(self.h, R, m, n_sig)
+        self.n_t, self.n_reco = int(R.shape[0]), int(R.shape[1])
+
+    def set_data(self, n, b, pull_mean=None, pull_sigma=None):
+        nr_set_data(self.h, n, b, pull_mean, pull_sigma)
+
+    def eval_nll(self, theta):
+        return nr_eval_nll(self.h, theta)
+
+    def eval_nll_grad(self, theta):
+        return nr_eval_nll_grad(self.h, theta)
+
+    def eval_mu(self, theta):
+        return nr_eval_mu(self.h, theta, self.n_reco)
+
+    def eval_weights(self, theta):
+        return nr_eval_weights(self.h, theta, self.n_t)
+
+    def reference(self):
+        return nr_get_reference(self.h, self.n_t)
+
+    def stream(self):
+        return nr_stream(self.h)
+
+    def time_stage(self, stage, iters=100):
+        return nr_time_stage(self.h, stage, iters)
+
+    def set_fold_tiling(self, rows_per_wg=0, use_graph=-1):
+        nr_set_fold_tiling(self.h, rows_per_wg, use_graph)
+
+    def eval_nll_dev(self, theta_t, nll_t, grad_t=None, stream=None):
+        """torch tensors on this device: theta [P,7] f64, nll [P] f64,
+        grad [P,7] f64 or None; enqueued on `stream` (torch stream or None
+        for the context stream)."""
+        assert theta_t.dtype == nll_t.dtype and str(theta_t.dtype).endswith("float64")
+        assert theta_t.is_contiguous() and nll_t.is_contiguous()
+        sp = None if stream is None else stream.cuda_stream
+        nr_eval_nll_dev(self.h, theta_t.data_ptr(), theta_t.shape[0],
+                        nll_t.data_ptr(),
+                        None if grad_t is None else grad_t.data_ptr(), sp)

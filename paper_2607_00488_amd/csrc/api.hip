@@ -1,0 +1,758 @@
+// C-ABI context: validation, theta-independent setup (Sec. III.A last
+// paragraph and Sec. III.B: the SM reference and the response are built once
+// and kept resident), stream-ordered launches, HIP-graph replay, errors.
+#include "common.h"
+#include "../../include/nureweight.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                        \
+    do {                                                                    \
+        hipError_t e_ = (expr);                                             \
+        if (e_ != hipSuccess)                                               \
+            return fail(NR_EHIP, "%s: %s (%s:%d)", #expr,                   \
+                        hipGetErrorString(e_), __FILE__, __LINE__);         \
+    } while (0)
+
+template <class T>
+int dalloc(T** p, size_t n) {
+    if (*p) { (void)hipFree(*p); *p = nullptr; }
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(NR_ENOMEM, "hipMalloc(%zu bytes): %s", n * sizeof(T),
+                    hipGetErrorString(e));
+    }
+    return 0;
+}
+
+template <class T>
+void dfree(T** p) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+}
+
+bool finite_all(const double* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+using GraphKey = std::tuple<const void*, int, void*, void*, void*, void*>;
+
+}  // namespace
+
+struct nr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    nr::Phys ph{};
+    // sources and grid
+    bool have_src = false, have_rsp = false, have_data = false;
+    int n_src = 0, n_t = 0, n_nodes = 0, n_blocks = 0;
+    double t_lo = 0, t_hi = 0;
+    std::vector<int> src_off, src_n, src_group;
+    std::vector<double> hE, hW, hPe, tc;
+    std::vector<int> jmin;
+    std::vector<nr::EUnit> units;
+    std::vector<int> ustart;
+    std::vector<double> ssm, basis;
+    double*d_E = nullptr, *d_W = nullptr, *d_Pe = nullptr, *d_tc = nullptr;
+    double *d_ssm = nullptr, *d_basis = nullptr, *d_part = nullptr;
+    int *d_group = nullptr, *d_jmin = nullptr, *d_ustart = nullptr;
+    nr::EUnit* d_units = nullptr;
+    // response
+    int n_reco = 0, ldr = 0;
+    float* d_R = nullptr;
+    bool m_user = false;
+    double n_sig = 0;
+    std::vector<double> mrow;
+    double* d_mrow = nullptr;
+    // data
+    double *d_n = nullptr, *d_b = nullptr;
+    double cdata = 0;
+    double pull_mean[NR_NTHETA] = {0}, pull_sigma[NR_NTHETA] = {0};
+    // fold / adjoint scratch
+    int rows_per_wg = 0, n_rb = 0, n_cc = 0, adj_grid = 0;
+    double *d_colpart = nullptr, *d_chunk_dev = nullptr, *d_chunk_gb = nullptr;
+    unsigned* d_ctr = nullptr;  // [n_cc + 1] fold, [1] adjoint after that
+    float* d_a = nullptr;
+    double *d_gb = nullptr, *d_jpart = nullptr;
+    // staging for the synchronous entry points
+    double *d_th = nullptr, *d_out = nullptr, *d_grad = nullptr;
+    double *d_mu = nullptr, *d_w = nullptr;
+    size_t cap_pts = 0, cap_mu = 0, cap_w = 0;
+    double* d_thsm = nullptr;
+    // graphs
+    bool use_graph = true;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    // last launch arguments (for nr_time_stage)
+    nr::EintArgs last_e{};
+    nr::FoldArgs last_f{};
+    nr::AdjArgs last_a{};
+    bool have_last = false, have_last_adj = false;
+};
+
+namespace {
+
+void clear_graphs(nr_ctx* c) {
+    for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+    c->graphs.clear();
+}
+
+int set_device(nr_ctx* c) {
+    HIPCHK(hipSetDevice(c->device));
+    return 0;
+}
+
+nr::Phys make_phys(const nr_physics* p) {
+    nr_physics d{0.51099895, 1.1663788e-11, 0.23122, 1.0 / 137.035999084, 0.5};
+    if (p) d = *p;
+    const double pi = 3.14159265358979323846;
+    nr::Phys ph;
+    ph.me = d.me;
+    ph.sw2 = d.sw2;
+    ph.tau_frac = d.tau_frac;
+    // ratio of the magnetic prefactor pi alpha^2/m_e^2 (Eq. (xs_mm)) with
+    // (mu_nu/mu_B)^2 = 1e-22 m2 to the weak prefactor 2 G_F^2 m_e / pi
+    ph.cmm = pi * pi * d.alpha_em * d.alpha_em * 1e-22 /
+             (2.0 * d.gf * d.gf * d.me * d.me * d.me);
+    ph.gLe = 0.5 + d.sw2;   // Sec. II.A tree-level couplings
+    ph.gLm = -0.5 + d.sw2;
+    ph.gR = d.sw2;
+    return ph;
+}
+
+// Two-body kinematics: recoil T is reachable from neutrino energy E iff
+// T <= 2E^2 / (m_e + 2E).
+inline bool reach(double me, double E, double T) {
+    return T <= 2.0 * E * E / (me + 2.0 * E);
+}
+
+void recompute_mrow(nr_ctx* c) {
+    if (c->m_user || !c->have_src) return;
+    double tot = 0;
+    for (int l = 0; l < c->n_t; ++l) tot += c->ssm[l];
+    c->mrow.assign(c->n_t, 0.0);
+    for (int l = 0; l < c->n_t; ++l)
+        c->mrow[l] = tot > 0 ? c->n_sig * c->ssm[l] / tot : 0.0;
+}
+
+int upload_mrow(nr_ctx* c) {
+    if (!c->have_rsp) return 0;
+    HIPCHK(hipMemcpy(c->d_mrow, c->mrow.data(), sizeof(double) * c->n_t,
+                     hipMemcpyHostToDevice));
+    return 0;
+}
+
+int choose_tiling(nr_ctx* c, int rows_req) {
+    c->n_cc = (c->ldr / 4 + 63) / 64;
+    int rows;
+    if (rows_req > 0) {
+        rows = rows_req;
+    } else {
+        int target_rb = std::max(1, 1024 / c->n_cc);
+        rows = (c->n_t + target_rb - 1) / target_rb;
+        rows = ((rows + 63) / 64) * 64;
+    }
+    rows = std::max(8, std::min(rows, 2048));
+    c->rows_per_wg = rows;
+    c->n_rb = (c->n_t + rows - 1) / rows;
+    int rc;
+    if ((rc = dalloc(&c->d_colpart, (size_t)c->n_rb * c->ldr))) return rc;
+    if ((rc = dalloc(&c->d_chunk_dev, (size_t)c->n_cc))) return rc;
+    if ((rc = dalloc(&c->d_chunk_gb, (size_t)c->n_cc))) return rc;
+    if ((rc = dalloc(&c->d_ctr, (size_t)c->n_cc + 2))) return rc;
+    HIPCHK(hipMemset(c->d_ctr, 0, sizeof(unsigned) * (c->n_cc + 2)));
+    c->adj_grid = nr::adjoint_grid(c->n_t);
+    if ((rc = dalloc(&c->d_jpart, (size_t)c->adj_grid * nr::kNBasis))) return rc;
+    clear_graphs(c);
+    return 0;
+}
+
+int ensure_stage(nr_ctx* c, size_t pts, size_t mu_elems, size_t w_elems) {
+    int rc;
+    if (pts > c->cap_pts) {
+        size_t n = std::max(pts, (size_t)64);
+        if ((rc = dalloc(&c->d_th, n * NR_NTHETA))) return rc;
+        if ((rc = dalloc(&c->d_out, n))) return rc;
+        if ((rc = dalloc(&c->d_grad, n * NR_NTHETA))) return rc;
+        c->cap_pts = n;
+        clear_graphs(c);
+    }
+    if (mu_elems > c->cap_mu) {
+        if ((rc = dalloc(&c->d_mu, mu_elems))) return rc;
+        c->cap_mu = mu_elems;
+        clear_graphs(c);
+    }
+    if (w_elems > c->cap_w) {
+        if ((rc = dalloc(&c->d_w, w_elems))) return rc;
+        c->cap_w = w_elems;
+    }
+    return 0;
+}
+
+nr::EintArgs eint_args(nr_ctx* c, const double* d_theta) {
+    nr::EintArgs a{};
+    a.units = c->d_units;
+    a.n_units = (int)c->units.size();
+    a.nodeE = c->d_E;
+    a.nodeW = c->d_W;
+    a.nodePe = c->d_Pe;
+    a.srcGroup = c->d_group;
+    a.jmin = c->d_jmin;
+    a.tc = c->d_tc;
+    a.n_t = c->n_t;
+    a.theta = d_theta;
+    a.ph = c->ph;
+    a.part = c->d_part;
+    return a;
+}
+
+// One single-point evaluation: a1 (E-integral), a2-a5 (weights, fold,
+// likelihood) and, with a gradient, the adjoint pass.
+int enqueue_point(nr_ctx* c, const double* th, double* nll, double* grad,
+                  double* mu, double* w, hipStream_t s) {
+    nr::EintArgs ea = eint_args(c, th);
+    HIPCHK(nr::launch_eint(ea, s));
+    nr::FoldArgs fa{};
+    fa.R = c->d_R;
+    fa.ldr = c->ldr;
+    fa.n_t = c->n_t;
+    fa.n_reco = c->n_reco;
+    fa.part = c->d_part;
+    fa.ustart = c->d_ustart;
+    fa.ssm = c->d_ssm;
+    fa.mrow = c->d_mrow;
+    fa.n = c->d_n;
+    fa.b = c->d_b;
+    fa.theta = th;
+    fa.colpart = c->d_colpart;
+    fa.ctr = c->d_ctr;
+    fa.chunk_dev = c->d_chunk_dev;
+    fa.chunk_gb = c->d_chunk_gb;
+    fa.out_nll = nll;
+    fa.out_mu = mu;
+    fa.out_a = grad ? c->d_a : nullptr;
+    fa.out_gb = grad ? c->d_gb : nullptr;
+    fa.out_w = w;
+    fa.cdata = c->cdata;
+    for (int i = 0; i < NR_NTHETA; ++i) {
+        fa.pull_mean[i] = c->pull_mean[i];
+        fa.pull_sigma[i] = c->pull_sigma[i];
+    }
+    fa.rows_per_wg = c->rows_per_wg;
+    fa.n_rb = c->n_rb;
+    fa.n_cc = c->n_cc;
+    HIPCHK(nr::launch_fold(fa, s));
+    c->last_e = ea;
+    c->last_f = fa;
+    c->have_last = true;
+    if (grad) {
+        nr::AdjArgs aa{};
+        aa.R = c->d_R;
+        aa.ldr = c->ldr;
+        aa.n_t = c->n_t;
+        aa.n_reco = c->n_reco;
+        aa.a = c->d_a;
+        aa.ssm = c->d_ssm;
+        aa.mrow = c->d_mrow;
+        aa.basis = c->d_basis;
+        aa.theta = th;
+        aa.gb = c->d_gb;
+        aa.jpart = c->d_jpart;
+        aa.ctr = c->d_ctr + c->n_cc + 1;
+        aa.out_grad = grad;
+        for (int i = 0; i < NR_NTHETA; ++i) {
+            aa.pull_mean[i] = c->pull_mean[i];
+            aa.pull_sigma[i] = c->pull_sigma[i];
+        }
+        aa.ph = c->ph;
+        HIPCHK(nr::launch_adjoint(aa, c->adj_grid, s));
+        c->last_a = aa;
+        c->have_last_adj = true;
+    }
+    return 0;
+}
+
+int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
+                   double* grad, double* mu, double* w, hipStream_t s) {
+    for (int p = 0; p < n_pts; ++p) {
+        int rc = enqueue_point(c, th + (size_t)p * NR_NTHETA, nll ? nll + p : nullptr,
+                               grad ? grad + (size_t)p * NR_NTHETA : nullptr,
+                               mu ? mu + (size_t)p * c->n_reco : nullptr,
+                               w ? w + (size_t)p * c->n_t : nullptr, s);
+        if (rc) return rc;
+    }
+    return 0;
+}
+
+// Replays a cached graph of the per-point launches when the same buffers and
+// point count come back (the common case in fits and scans).
+int run_points(nr_ctx* c, const double* th, int n_pts, double* nll,
+               double* grad, double* mu, double* w, hipStream_t s) {
+    if (!c->use_graph || n_pts > 4096 || w)
+        return enqueue_points(c, th, n_pts, nll, grad, mu, w, s);
+    GraphKey key{th, n_pts, nll, grad, mu, (void*)s};
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        if (c->graphs.size() >= 16) clear_graphs(c);
+        hipGraph_t g;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_points(c, th, n_pts, nll, grad, mu, w, s);
+        hipError_t e = hipStreamEndCapture(s, &g);
+        if (rc) return rc;
+        if (e != hipSuccess)
+            return fail(NR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        hipGraphExec_t ex;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess)
+            return fail(NR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        it = c->graphs.emplace(key, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, s));
+    return 0;
+}
+
+int check_ready(nr_ctx* c) {
+    if (!c) return fail(NR_EINVAL, "null context");
+    if (!c->have_src || !c->have_rsp || !c->have_data)
+        return fail(NR_ESTATE,
+                    "evaluation before set_sources, set_response and set_data");
+    return 0;
+}
+
+int check_theta(const double* th, int n_pts) {
+    if (!th || n_pts <= 0) return fail(NR_EINVAL, "theta null or n_pts <= 0");
+    if (!finite_all(th, (size_t)n_pts * NR_NTHETA))
+        return fail(NR_EINVAL, "non-finite theta");
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* nr_last_error(void) { return g_err.c_str(); }
+
+int nr_create(int device, nr_ctx** out) {
+    if (!out) return fail(NR_EINVAL, "out is null");
+    *out = nullptr;
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev)
+        return fail(NR_EINVAL, "device %d out of range (%d devices)", device, ndev);
+    nr_ctx* c = new (std::nothrow) nr_ctx();
+    if (!c) return fail(NR_ENOMEM, "context allocation");
+    c->device = device;
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(NR_EHIP, "stream creation: %s", hipGetErrorString(e));
+    }
+    if (dalloc(&c->d_a, 1) || dalloc(&c->d_gb, 1) || dalloc(&c->d_thsm, NR_NTHETA)) {
+        delete c;
+        return NR_ENOMEM;
+    }
+    const double sm[NR_NTHETA] = {0, 0, 0, 0, 0, 1, 1};
+    (void)hipMemcpy(c->d_thsm, sm, sizeof(sm), hipMemcpyHostToDevice);
+    *out = c;
+    return 0;
+}
+
+void nr_destroy(nr_ctx* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    clear_graphs(c);
+    dfree(&c->d_E); dfree(&c->d_W); dfree(&c->d_Pe); dfree(&c->d_tc);
+    dfree(&c->d_ssm); dfree(&c->d_basis); dfree(&c->d_part);
+    dfree(&c->d_group); dfree(&c->d_jmin); dfree(&c->d_ustart);
+    dfree(&c->d_units); dfree(&c->d_R); dfree(&c->d_mrow);
+    dfree(&c->d_n); dfree(&c->d_b); dfree(&c->d_colpart);
+    dfree(&c->d_chunk_dev); dfree(&c->d_chunk_gb); dfree(&c->d_ctr);
+    dfree(&c->d_a); dfree(&c->d_gb); dfree(&c->d_jpart);
+    dfree(&c->d_th); dfree(&c->d_out); dfree(&c->d_grad);
+    dfree(&c->d_mu); dfree(&c->d_w); dfree(&c->d_thsm);
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+void* nr_stream(nr_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
+                   double t_lo, double t_hi, const nr_physics* phys) {
+    if (!c || !src || n_src <= 0 || n_t <= 0)
+        return fail(NR_EINVAL, "null argument or non-positive size");
+    if (!(std::isfinite(t_lo) && std::isfinite(t_hi) && t_hi > t_lo && t_lo >= 0))
+        return fail(NR_EINVAL, "recoil range must satisfy 0 <= t_lo < t_hi");
+    if (c->have_rsp && n_t != c->n_t)
+        return fail(NR_EINVAL, "n_t %d differs from the response (%d)", n_t, c->n_t);
+    if (phys && !(phys->me > 0 && phys->gf > 0 && phys->alpha_em > 0 &&
+                  phys->tau_frac >= 0 && phys->tau_frac <= 1))
+        return fail(NR_EINVAL, "invalid physical constants");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    c->ph = make_phys(phys);
+    // copy, validate and sort the node tables (summation order is free)
+    c->src_off.assign(n_src + 1, 0);
+    c->src_n.assign(n_src, 0);
+    c->src_group.assign(n_src, 0);
+    c->hE.clear(); c->hW.clear(); c->hPe.clear();
+    double wmax = 0;
+    for (int k = 0; k < n_src; ++k) {
+        const nr_source& s = src[k];
+        if (s.n <= 0 || !s.E || !s.weight || !s.p_ee)
+            return fail(NR_EINVAL, "source %d: empty or null arrays", k);
+        if (s.kind == 0 && s.n != 1)
+            return fail(NR_EINVAL, "source %d: a line has exactly one node", k);
+        if (s.group != 0 && s.group != 1)
+            return fail(NR_EINVAL, "source %d: group must be 0 or 1", k);
+        std::vector<int> idx(s.n);
+        for (int j = 0; j < s.n; ++j) {
+            idx[j] = j;
+            if (!(std::isfinite(s.E[j]) && s.E[j] > 0 && std::isfinite(s.weight[j])
+                  && s.weight[j] >= 0 && s.p_ee[j] >= 0 && s.p_ee[j] <= 1))
+                return fail(NR_EINVAL, "source %d node %d: invalid E/weight/p_ee", k, j);
+            wmax = std::max(wmax, s.weight[j]);
+        }
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](int a, int b) { return s.E[a] < s.E[b]; });
+        c->src_off[k] = (int)c->hE.size();
+        c->src_n[k] = s.n;
+        c->src_group[k] = s.group;
+        for (int j : idx) {
+            c->hE.push_back(s.E[j]);
+            c->hW.push_back(s.weight[j]);
+            c->hPe.push_back(s.p_ee[j]);
+        }
+    }
+    if (!(wmax > 0)) return fail(NR_EINVAL, "all source weights are zero");
+    // S is linear in the weights and only ratios enter w; scale to O(1).
+    for (double& w : c->hW) w /= wmax;
+    c->n_src = n_src;
+    c->n_nodes = (int)c->hE.size();
+    c->src_off[n_src] = c->n_nodes;
+    c->n_t = n_t;
+    c->t_lo = t_lo;
+    c->t_hi = t_hi;
+    c->tc.resize(n_t);
+    const double dt = (t_hi - t_lo) / n_t;
+    for (int l = 0; l < n_t; ++l) c->tc[l] = t_lo + (l + 0.5) * dt;
+    // first reachable node of every (source, row); rows are increasing in T
+    // and T_max(E) is increasing in E, so the reachable nodes are a suffix.
+    c->jmin.assign((size_t)n_src * n_t, 0);
+    for (int k = 0; k < n_src; ++k) {
+        const int off = c->src_off[k], n = c->src_n[k];
+        for (int l = 0; l < n_t; ++l) {
+            int lo = 0, hi = n;
+            while (lo < hi) {
+                int mid = (lo + hi) / 2;
+                if (reach(c->ph.me, c->hE[off + mid], c->tc[l])) hi = mid;
+                else lo = mid + 1;
+            }
+            c->jmin[(size_t)k * n_t + l] = off + lo;
+        }
+    }
+    // work units: 64 rows x <= 64 nodes of one source
+    c->n_blocks = (n_t + nr::kRowsPerBlock - 1) / nr::kRowsPerBlock;
+    c->units.clear();
+    c->ustart.assign(c->n_blocks + 1, 0);
+    for (int b = 0; b < c->n_blocks; ++b) {
+        c->ustart[b] = (int)c->units.size();
+        const int l0 = b * nr::kRowsPerBlock;
+        const int l1 = std::min(n_t, l0 + nr::kRowsPerBlock) - 1;
+        for (int k = 0; k < n_src; ++k) {
+            const int lo = c->jmin[(size_t)k * n_t + l0];
+            const int full = c->jmin[(size_t)k * n_t + l1];
+            const int hi = c->src_off[k] + c->src_n[k];
+            for (int j = lo; j < hi; j += nr::kUnitNodes) {
+                nr::EUnit u{};
+                u.block = b;
+                u.src = k;
+                u.j0 = j;
+                u.cnt = std::min(nr::kUnitNodes, hi - j);
+                u.jfull = full;
+                c->units.push_back(u);
+            }
+        }
+    }
+    c->ustart[c->n_blocks] = (int)c->units.size();
+    const size_t nu = std::max<size_t>(1, c->units.size());
+    // theta-independent basis spectra (FP64), used by the adjoint
+    c->basis.assign((size_t)nr::kNBasis * n_t, 0.0);
+    for (int l = 0; l < n_t; ++l) {
+        const double T = c->tc[l];
+        for (int k = 0; k < n_src; ++k) {
+            const int g = c->src_group[k] ? 10 : 0;
+            const int hi = c->src_off[k] + c->src_n[k];
+            double acc[10] = {0};
+            for (int j = c->jmin[(size_t)k * n_t + l]; j < hi; ++j) {
+                const double E = c->hE[j], nu = c->hW[j], pe = c->hPe[j];
+                const double P[3] = {pe, (1 - pe) * (1 - c->ph.tau_frac),
+                                     (1 - pe) * c->ph.tau_frac};
+                const double y = 1.0 - T / E, x = c->ph.me * T / (E * E);
+                for (int a = 0; a < 3; ++a) {
+                    acc[3 * a + 0] += nu * P[a];
+                    acc[3 * a + 1] += nu * P[a] * y * y;
+                    acc[3 * a + 2] += nu * P[a] * x;
+                }
+                acc[9] += nu * (P[0] + P[1] + P[2]) * (1.0 / T - 1.0 / E);
+            }
+            for (int q = 0; q < 10; ++q)
+                c->basis[(size_t)(g + q) * n_t + l] += acc[q];
+        }
+    }
+    // upload
+    if ((rc = dalloc(&c->d_E, c->n_nodes)) || (rc = dalloc(&c->d_W, c->n_nodes)) ||
+        (rc = dalloc(&c->d_Pe, c->n_nodes)) || (rc = dalloc(&c->d_tc, n_t)) ||
+        (rc = dalloc(&c->d_ssm, n_t)) || (rc = dalloc(&c->d_group, n_src)) ||
+        (rc = dalloc(&c->d_jmin, (size_t)n_src * n_t)) ||
+        (rc = dalloc(&c->d_ustart, c->n_blocks + 1)) ||
+        (rc = dalloc(&c->d_units, nu)) ||
+        (rc = dalloc(&c->d_part, nu * nr::kRowsPerBlock)) ||
+        (rc = dalloc(&c->d_basis, (size_t)nr::kNBasis * n_t)))
+        return rc;
+    HIPCHK(hipMemcpy(c->d_E, c->hE.data(), sizeof(double) * c->n_nodes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_W, c->hW.data(), sizeof(double) * c->n_nodes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_Pe, c->hPe.data(), sizeof(double) * c->n_nodes, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_tc, c->tc.data(), sizeof(double) * n_t, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_group, c->src_group.data(), sizeof(int) * n_src, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_jmin, c->jmin.data(), sizeof(int) * c->jmin.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_ustart, c->ustart.data(), sizeof(int) * (c->n_blocks + 1), hipMemcpyHostToDevice));
+    if (!c->units.empty())
+        HIPCHK(hipMemcpy(c->d_units, c->units.data(), sizeof(nr::EUnit) * c->units.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_basis, c->basis.data(), sizeof(double) * c->basis.size(), hipMemcpyHostToDevice));
+    // SM reference on the device with the same E-integral kernel the
+    // evaluations use, so that w = S_theta / S_SM is exactly 1 at theta_SM.
+    if (!c->units.empty()) {
+        HIPCHK(nr::launch_eint(eint_args(c, c->d_thsm), c->stream));
+        HIPCHK(nr::launch_spectrum_reduce(c->d_part, c->d_ustart, n_t, c->d_ssm, c->stream));
+    } else {
+        HIPCHK(hipMemsetAsync(c->d_ssm, 0, sizeof(double) * n_t, c->stream));
+    }
+    c->ssm.resize(n_t);
+    HIPCHK(hipMemcpyAsync(c->ssm.data(), c->d_ssm, sizeof(double) * n_t,
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->have_src = true;
+    clear_graphs(c);
+    recompute_mrow(c);
+    if ((rc = upload_mrow(c))) return rc;
+    return 0;
+}
+
+int nr_set_response(nr_ctx* c, const float* R, int n_t, int n_reco,
+                    const double* m, double n_sig) {
+    if (!c || !R || n_t <= 0 || n_reco <= 0)
+        return fail(NR_EINVAL, "null argument or non-positive size");
+    if (c->have_src && n_t != c->n_t)
+        return fail(NR_EINVAL, "n_t %d differs from the sources (%d)", n_t, c->n_t);
+    if (c->have_data && n_reco != c->n_reco)
+        return fail(NR_EINVAL, "n_reco %d differs from the data (%d)", n_reco, c->n_reco);
+    if (!m && !c->have_src)
+        return fail(NR_ESTATE, "m == NULL needs set_sources first");
+    if (!m && !(std::isfinite(n_sig) && n_sig >= 0))
+        return fail(NR_EINVAL, "n_sig must be finite and >= 0");
+    if (m && !finite_all(m, n_t)) return fail(NR_EINVAL, "non-finite m");
+    const size_t nel = (size_t)n_t * n_reco;
+    for (size_t i = 0; i < nel; ++i)
+        if (!std::isfinite(R[i])) return fail(NR_EINVAL, "non-finite R at %zu", i);
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    c->n_t = n_t;
+    c->n_reco = n_reco;
+    c->ldr = (n_reco + 3) / 4 * 4;
+    if ((rc = dalloc(&c->d_R, (size_t)n_t * c->ldr))) return rc;
+    if (c->ldr != n_reco)
+        HIPCHK(hipMemset(c->d_R, 0, sizeof(float) * (size_t)n_t * c->ldr));
+    HIPCHK(hipMemcpy2D(c->d_R, sizeof(float) * c->ldr, R, sizeof(float) * n_reco,
+                       sizeof(float) * n_reco, n_t, hipMemcpyHostToDevice));
+    if ((rc = dalloc(&c->d_mrow, n_t))) return rc;
+    if ((rc = dalloc(&c->d_a, c->ldr))) return rc;
+    c->m_user = m != nullptr;
+    c->n_sig = n_sig;
+    if (m) c->mrow.assign(m, m + n_t);
+    c->have_rsp = true;
+    recompute_mrow(c);
+    if ((rc = upload_mrow(c))) return rc;
+    if ((rc = choose_tiling(c, 0))) return rc;
+    return 0;
+}
+
+int nr_set_data(nr_ctx* c, const double* n, const double* b, int n_reco,
+                const double* pull_mean, const double* pull_sigma) {
+    if (!c || !n || !b || n_reco <= 0) return fail(NR_EINVAL, "null argument or n_reco <= 0");
+    if (c->have_rsp && n_reco != c->n_reco)
+        return fail(NR_EINVAL, "n_reco %d differs from the response (%d)", n_reco, c->n_reco);
+    if ((pull_mean == nullptr) != (pull_sigma == nullptr))
+        return fail(NR_EINVAL, "pull_mean and pull_sigma must both be given or both NULL");
+    for (int j = 0; j < n_reco; ++j) {
+        if (!(std::isfinite(n[j]) && n[j] >= 0)) return fail(NR_EINVAL, "n[%d] must be finite and >= 0", j);
+        if (!(std::isfinite(b[j]) && b[j] >= 0)) return fail(NR_EINVAL, "b[%d] must be finite and >= 0", j);
+    }
+    if (pull_mean && (!finite_all(pull_mean, NR_NTHETA) || !finite_all(pull_sigma, NR_NTHETA)))
+        return fail(NR_EINVAL, "non-finite pulls");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    if ((rc = dalloc(&c->d_n, n_reco)) || (rc = dalloc(&c->d_b, n_reco))) return rc;
+    HIPCHK(hipMemcpy(c->d_n, n, sizeof(double) * n_reco, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_b, b, sizeof(double) * n_reco, hipMemcpyHostToDevice));
+    // data-only constant of Eq. (logL): the device reduces the deviance
+    // mu - n + n ln(n/mu); -2lnL = 2 (deviance + C_data) + pulls.
+    double cd = 0;
+    for (int j = 0; j < n_reco; ++j)
+        cd += n[j] - (n[j] > 0 ? n[j] * std::log(n[j]) : 0.0) + std::lgamma(n[j] + 1.0);
+    c->cdata = cd;
+    for (int i = 0; i < NR_NTHETA; ++i) {
+        c->pull_mean[i] = pull_mean ? pull_mean[i] : 0.0;
+        c->pull_sigma[i] = pull_sigma ? pull_sigma[i] : 0.0;
+    }
+    c->n_reco = n_reco;
+    c->have_data = true;
+    clear_graphs(c);
+    return 0;
+}
+
+int nr_eval_nll_dev(nr_ctx* c, const double* d_theta, int n_pts, double* d_nll,
+                    double* d_grad, void* stream) {
+    int rc;
+    if ((rc = check_ready(c))) return rc;
+    if (!d_theta || !d_nll || n_pts <= 0)
+        return fail(NR_EINVAL, "null device pointer or n_pts <= 0");
+    if ((rc = set_device(c))) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    return run_points(c, d_theta, n_pts, d_nll, d_grad, nullptr, nullptr, s);
+}
+
+static int eval_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
+                     double* grad, double* mu, double* w) {
+    int rc;
+    if ((rc = check_ready(c))) return rc;
+    if ((rc = check_theta(theta, n_pts))) return rc;
+    if ((rc = set_device(c))) return rc;
+    if ((rc = ensure_stage(c, n_pts, mu ? (size_t)n_pts * c->n_reco : 0,
+                           w ? (size_t)n_pts * c->n_t : 0)))
+        return rc;
+    HIPCHK(hipMemcpyAsync(c->d_th, theta, sizeof(double) * n_pts * NR_NTHETA,
+                          hipMemcpyHostToDevice, c->stream));
+    rc = run_points(c, c->d_th, n_pts, c->d_out, grad ? c->d_grad : nullptr,
+                    mu ? c->d_mu : nullptr, w ? c->d_w : nullptr, c->stream);
+    if (rc) return rc;
+    if (nll)
+        HIPCHK(hipMemcpyAsync(nll, c->d_out, sizeof(double) * n_pts,
+                              hipMemcpyDeviceToHost, c->stream));
+    if (grad)
+        HIPCHK(hipMemcpyAsync(grad, c->d_grad, sizeof(double) * n_pts * NR_NTHETA,
+                              hipMemcpyDeviceToHost, c->stream));
+    if (mu)
+        HIPCHK(hipMemcpyAsync(mu, c->d_mu, sizeof(double) * n_pts * c->n_reco,
+                              hipMemcpyDeviceToHost, c->stream));
+    if (w)
+        HIPCHK(hipMemcpyAsync(w, c->d_w, sizeof(double) * n_pts * c->n_t,
+                              hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+int nr_eval_nll(nr_ctx* c, const double* theta, int n_pts, double* nll) {
+    if (!nll) return fail(NR_EINVAL, "nll is null");
+    return eval_sync(c, theta, n_pts, nll, nullptr, nullptr, nullptr);
+}
+
+int nr_eval_nll_grad(nr_ctx* c, const double* theta, int n_pts, double* nll,
+                     double* grad) {
+    if (!nll || !grad) return fail(NR_EINVAL, "nll or grad is null");
+    return eval_sync(c, theta, n_pts, nll, grad, nullptr, nullptr);
+}
+
+int nr_eval_mu(nr_ctx* c, const double* theta, int n_pts, double* mu) {
+    if (!mu) return fail(NR_EINVAL, "mu is null");
+    return eval_sync(c, theta, n_pts, nullptr, nullptr, mu, nullptr);
+}
+
+int nr_eval_weights(nr_ctx* c, const double* theta, int n_pts, double* w) {
+    if (!w) return fail(NR_EINVAL, "w is null");
+    return eval_sync(c, theta, n_pts, nullptr, nullptr, nullptr, w);
+}
+
+int nr_get_reference(nr_ctx* c, double* s_sm, double* m) {
+    if (!c) return fail(NR_EINVAL, "null context");
+    if (s_sm) {
+        if (!c->have_src) return fail(NR_ESTATE, "no sources set");
+        std::memcpy(s_sm, c->ssm.data(), sizeof(double) * c->n_t);
+    }
+    if (m) {
+        if (!c->have_rsp) return fail(NR_ESTATE, "no response set");
+        std::memcpy(m, c->mrow.data(), sizeof(double) * c->n_t);
+    }
+    return 0;
+}
+
+int nr_set_fold_tiling(nr_ctx* c, int rows_per_wg, int use_graph) {
+    if (!c) return fail(NR_EINVAL, "null context");
+    if (use_graph >= 0) c->use_graph = use_graph != 0;
+    clear_graphs(c);
+    if (rows_per_wg > 0) {
+        if (!c->have_rsp) return fail(NR_ESTATE, "no response set");
+        if (rows_per_wg > 2048 || rows_per_wg % 8)
+            return fail(NR_EINVAL, "rows_per_wg must be a multiple of 8 and <= 2048");
+        int rc;
+        if ((rc = set_device(c))) return rc;
+        HIPCHK(hipStreamSynchronize(c->stream));
+        return choose_tiling(c, rows_per_wg);
+    }
+    return 0;
+}
+
+int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
+    if (!c || !avg_ms || iters <= 0) return fail(NR_EINVAL, "bad argument");
+    if (!c->have_last || (stage == 3 && !c->have_last_adj))
+        return fail(NR_ESTATE, "no previous evaluation to time");
+    if (stage < 1 || stage > 3) return fail(NR_EINVAL, "stage must be 1, 2 or 3");
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, c->stream));
+    for (int i = 0; i < iters; ++i) {
+        if (stage == 1) HIPCHK(nr::launch_eint(c->last_e, c->stream));
+        if (stage == 2) HIPCHK(nr::launch_fold(c->last_f, c->stream));
+        if (stage == 3) HIPCHK(nr::launch_adjoint(c->last_a, c->adj_grid, c->stream));
+    }
+    HIPCHK(hipEventRecord(e1, c->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = ms / iters;
+    return 0;
+}
+
+}  // extern "C"

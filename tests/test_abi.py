@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every symbol the header declares
+(no compute calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(nr_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("nr_set_sources", "nr_set_response", "nr_set_data",
+              "nr_eval_nll", "nr_eval_nll_grad"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2607_00488_amd as nr
+    path = nr.library_path()
+    if not os.path.exists(path):
+        pytest.fail(f"{path} is not built (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    missing = [n for n in sorted(declared_functions()) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(nr.EXPORTS) <= declared_functions()
+    assert declared_functions() <= set(nr.EXPORTS)
+
+
+def test_binding_has_the_same_names():
+    import paper_2607_00488_amd as nr
+    for n in declared_functions():
+        assert hasattr(nr, n), n

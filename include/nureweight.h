@@ -125,6 +125,41 @@ int nr_eval_mu(nr_ctx *ctx, const double *theta, int n_pts, double *mu);
 int nr_eval_nll_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
                     double *d_nll, double *d_grad, void *stream);
 
+/* Batched form: n_pts points of one analysis at once.  The weights of all
+ * points (from the theta-independent recoil basis, exact for Eq. (fT)) form
+ * a matrix W[p][l] = m_l w_l(theta_p), and the fold of Eq. (mu_total)
+ * becomes the dense product W R on FP32 matrix cores with the Poisson
+ * reduction of Eq. (logL) fused into its epilogue.  Synchronous; theta and
+ * nll are host arrays as in nr_eval_nll. */
+int nr_eval_nll_batched(nr_ctx *ctx, const double *theta, int n_pts,
+                        double *nll);
+
+/* Batched likelihood and gradient: the adjoint a = d(-2lnL)/d mu is
+ * propagated back through R as a second matrix product (U = A R^T) and
+ * contracted with the weight derivatives.  grad: [n_pts][7] host. */
+int nr_eval_nll_grad_batched(nr_ctx *ctx, const double *theta, int n_pts,
+                             double *nll, double *grad);
+
+/* Expected spectra of the batched form ([n_pts][n_reco], host). */
+int nr_eval_mu_batched(nr_ctx *ctx, const double *theta, int n_pts,
+                       double *mu);
+
+/* Several analyses (datasets with their own binning and response, all on
+ * one device) in one grouped persistent launch: theta[d] ([n_pts[d]][7],
+ * host), nll[d] ([n_pts[d]], host).  The stream of ctx[0] is used. */
+int nr_eval_nll_multi(nr_ctx *const *ctx, int n_ctx,
+                      const double *const *theta, const int *n_pts,
+                      double *const *nll);
+
+/* Device-pointer variant of nr_eval_nll_multi (and of the batched gradient
+ * when d_grad is not NULL: d_grad[d] is [n_pts[d]][7]).  Enqueued on
+ * `stream` (NULL = ctx[0]'s stream); a cached HIP graph of the whole grouped
+ * evaluation is replayed for repeated pointer sets. */
+int nr_eval_nll_multi_dev(nr_ctx *const *ctx, int n_ctx,
+                          const double *const *d_theta, const int *n_pts,
+                          double *const *d_nll, double *const *d_grad,
+                          void *stream);
+
 /* Weights w_l = S_theta(T_l) / S_SM(T_l) ([n_pts][n_t], host) as the
  * single-point path forms them before the fold.  Synchronous. */
 int nr_eval_weights(nr_ctx *ctx, const double *theta, int n_pts, double *w);

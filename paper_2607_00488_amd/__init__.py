@@ -25,6 +25,8 @@ EXPORTS = (
     "nr_set_data", "nr_eval_nll", "nr_eval_nll_grad", "nr_eval_mu",
     "nr_eval_nll_dev", "nr_eval_weights", "nr_get_reference", "nr_stream",
     "nr_time_stage", "nr_set_fold_tiling", "nr_last_error",
+    "nr_eval_nll_batched", "nr_eval_nll_grad_batched", "nr_eval_mu_batched",
+    "nr_eval_nll_multi", "nr_eval_nll_multi_dev",
 )
 
 
@@ -89,6 +91,14 @@ def load():
     L.nr_time_stage.argtypes = [P, I, I, pD]
     L.nr_set_fold_tiling.argtypes = [P, I, I]
     L.nr_last_error.restype = C.c_char_p
+    L.nr_eval_nll_batched.argtypes = [P, pD, I, pD]
+    L.nr_eval_nll_grad_batched.argtypes = [P, pD, I, pD, pD]
+    L.nr_eval_mu_batched.argtypes = [P, pD, I, pD]
+    L.nr_eval_nll_multi.argtypes = [C.POINTER(P), I, C.POINTER(pD),
+                                    C.POINTER(I), C.POINTER(pD)]
+    L.nr_eval_nll_multi_dev.argtypes = [C.POINTER(P), I, C.POINTER(P),
+                                        C.POINTER(I), C.POINTER(P),
+                                        C.POINTER(P), P]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("nr_destroy", "nr_stream", "nr_last_error"):
@@ -216,6 +226,56 @@ def nr_set_fold_tiling(h, rows_per_wg=0, use_graph=-1):
     _check(load().nr_set_fold_tiling(h, int(rows_per_wg), int(use_graph)))
 
 
+def nr_eval_nll_batched(h, theta):
+    th = _f64(theta, (-1, NR_NTHETA))
+    out = np.empty(th.shape[0])
+    _check(load().nr_eval_nll_batched(h, _dp(th), th.shape[0], _dp(out)))
+    return out
+
+
+def nr_eval_nll_grad_batched(h, theta):
+    th = _f64(theta, (-1, NR_NTHETA))
+    out = np.empty(th.shape[0])
+    g = np.empty((th.shape[0], NR_NTHETA))
+    _check(load().nr_eval_nll_grad_batched(h, _dp(th), th.shape[0], _dp(out),
+                                           _dp(g)))
+    return out, g
+
+
+def nr_eval_mu_batched(h, theta, n_reco):
+    th = _f64(theta, (-1, NR_NTHETA))
+    out = np.empty((th.shape[0], n_reco))
+    _check(load().nr_eval_mu_batched(h, _dp(th), th.shape[0], _dp(out)))
+    return out
+
+
+def nr_eval_nll_multi(handles, thetas):
+    n = len(handles)
+    ths = [_f64(t, (-1, NR_NTHETA)) for t in thetas]
+    outs = [np.empty(t.shape[0]) for t in ths]
+    H = (C.c_void_p * n)(*[h.value if hasattr(h, "value") else h
+                            for h in handles])
+    pD = C.POINTER(C.c_double)
+    TH = (pD * n)(*[_dp(t) for t in ths])
+    NP = (C.c_int * n)(*[t.shape[0] for t in ths])
+    OUT = (pD * n)(*[_dp(o) for o in outs])
+    _check(load().nr_eval_nll_multi(H, n, TH, NP, OUT))
+    return outs
+
+
+def nr_eval_nll_multi_dev(handles, theta_ptrs, n_pts, nll_ptrs,
+                          grad_ptrs=None, stream_ptr=None):
+    n = len(handles)
+    H = (C.c_void_p * n)(*[h.value if hasattr(h, "value") else h
+                            for h in handles])
+    TH = (C.c_void_p * n)(*theta_ptrs)
+    NP = (C.c_int * n)(*[int(x) for x in n_pts])
+    OUT = (C.c_void_p * n)(*nll_ptrs)
+    GR = None if grad_ptrs is None else (C.c_void_p * n)(*grad_ptrs)
+    _check(load().nr_eval_nll_multi_dev(H, n, TH, NP, OUT, GR,
+                                        C.c_void_p(stream_ptr or 0)))
+
+
 def nr_last_error():
     return load().nr_last_error().decode()
 
@@ -275,6 +335,15 @@ class Context:
     def set_fold_tiling(self, rows_per_wg=0, use_graph=-1):
         nr_set_fold_tiling(self.h, rows_per_wg, use_graph)
 
+    def eval_nll_batched(self, theta):
+        return nr_eval_nll_batched(self.h, theta)
+
+    def eval_nll_grad_batched(self, theta):
+        return nr_eval_nll_grad_batched(self.h, theta)
+
+    def eval_mu_batched(self, theta):
+        return nr_eval_mu_batched(self.h, theta, self.n_reco)
+
     def eval_nll_dev(self, theta_t, nll_t, grad_t=None, stream=None):
         """torch tensors on this device: theta [P,7] f64, nll [P] f64,
         grad [P,7] f64 or None; enqueued on `stream` (torch stream or None
@@ -285,3 +354,17 @@ class Context:
         nr_eval_nll_dev(self.h, theta_t.data_ptr(), theta_t.shape[0],
                         nll_t.data_ptr(),
                         None if grad_t is None else grad_t.data_ptr(), sp)
+
+
+def eval_nll_multi(contexts, thetas):
+    """Grouped batched evaluation over several Contexts (host arrays)."""
+    return nr_eval_nll_multi([c.h for c in contexts], thetas)
+
+
+def eval_nll_multi_dev(contexts, theta_ts, nll_ts, grad_ts=None, stream=None):
+    """Grouped batched evaluation on torch tensors (one per context)."""
+    nr_eval_nll_multi_dev(
+        [c.h for c in contexts], [t.data_ptr() for t in theta_ts],
+        [t.shape[0] for t in theta_ts], [t.data_ptr() for t in nll_ts],
+        None if grad_ts is None else [g.data_ptr() for g in grad_ts],
+        None if stream is None else stream.cuda_stream)

@@ -1,7 +1,7 @@
 // C-ABI context: validation, theta-independent setup (Sec. III.A last
 // paragraph and Sec. III.B: the SM reference and the response are built once
 // and kept resident), stream-ordered launches, HIP-graph replay, errors.
-#include "common.h"
+#include "batched.h"
 #include "../../include/nureweight.h"
 
 #include <algorithm>
@@ -63,6 +63,22 @@ bool finite_all(const double* p, size_t n) {
 
 using GraphKey = std::tuple<const void*, int, void*, void*, void*, void*>;
 
+// Incremented whenever a context's device buffers may have moved; cached
+// grouped-launch plans built under an older epoch are rebuilt.
+unsigned long g_epoch = 1;
+
+// One grouped launch over several analyses: GEMM problem tables, tile lists
+// and the captured graph of the whole batched evaluation.
+struct BatchPlan {
+    nr::GemmProb* d_probs_f = nullptr;
+    nr::GemmTile* d_tiles_f = nullptr;
+    nr::GemmProb* d_probs_a = nullptr;
+    nr::GemmTile* d_tiles_a = nullptr;
+    int n_tiles_f = 0, n_tiles_a = 0, grid_f = 1, grid_a = 1;
+    hipGraphExec_t graph = nullptr;
+    unsigned long epoch = 0;
+};
+
 }  // namespace
 
 struct nr_ctx {
@@ -98,7 +114,7 @@ struct nr_ctx {
     int rows_per_wg = 0, n_rb = 0, n_cc = 0, adj_grid = 0;
     double *d_colpart = nullptr, *d_chunk_dev = nullptr, *d_chunk_gb = nullptr;
     unsigned* d_ctr = nullptr;  // [n_cc + 1] fold, [1] adjoint after that
-    float* d_a = nullptr;
+    double* d_a = nullptr;
     double *d_gb = nullptr, *d_jpart = nullptr;
     // staging for the synchronous entry points
     double *d_th = nullptr, *d_out = nullptr, *d_grad = nullptr;
@@ -113,13 +129,38 @@ struct nr_ctx {
     nr::FoldArgs last_f{};
     nr::AdjArgs last_a{};
     bool have_last = false, have_last_adj = false;
+    // batched (GEMM) path workspace
+    int b_cap = 0, b_ldw = 0, b_nnt = 0;
+    bool b_grad = false;
+    float* d_wt = nullptr;      // [n_t][ldw]   weights, K-major
+    double* d_bpart = nullptr;  // [cap][n_nt]  deviance partials
+    double* d_bpgb = nullptr;   // [cap][n_nt]  sum a b partials
+    float* d_bat = nullptr;     // [ldr][ldw]   d(-2lnL)/d mu, j-major
+    float* d_bu = nullptr;      // [cap][n_t]   adjoint rows
+    double *d_bth = nullptr, *d_bnll = nullptr, *d_bgrad = nullptr, *d_bmu = nullptr;
+    size_t b_cap_mu = 0;
+    unsigned* d_gctr = nullptr;  // [4] tile counters (forward, adjoint)
+    std::map<std::vector<const void*>, BatchPlan*> plans;
 };
 
 namespace {
 
+void free_plan(BatchPlan* p) {
+    if (!p) return;
+    if (p->graph) (void)hipGraphExecDestroy(p->graph);
+    if (p->d_probs_f) (void)hipFree(p->d_probs_f);
+    if (p->d_tiles_f) (void)hipFree(p->d_tiles_f);
+    if (p->d_probs_a) (void)hipFree(p->d_probs_a);
+    if (p->d_tiles_a) (void)hipFree(p->d_tiles_a);
+    delete p;
+}
+
 void clear_graphs(nr_ctx* c) {
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
+    for (auto& kv : c->plans) free_plan(kv.second);
+    c->plans.clear();
+    ++g_epoch;
 }
 
 int set_device(nr_ctx* c) {
@@ -354,6 +395,283 @@ int check_theta(const double* th, int n_pts) {
 
 }  // namespace
 
+namespace {
+
+// ------------------------------------------------------------ batched path
+int ensure_batch(nr_ctx* c, int n_pts, bool grad, size_t mu_elems) {
+    const int ldw = (n_pts + 3) / 4 * 4;
+    const int nnt = (c->n_reco + nr::kGemmBN - 1) / nr::kGemmBN;
+    int rc;
+    bool moved = false;
+    if (n_pts > c->b_cap || ldw > c->b_ldw || nnt != c->b_nnt) {
+        const int cap = std::max(n_pts, 64);
+        const int ldc = (cap + 3) / 4 * 4;
+        if ((rc = dalloc(&c->d_wt, (size_t)c->n_t * ldc))) return rc;
+        HIPCHK(hipMemset(c->d_wt, 0, sizeof(float) * (size_t)c->n_t * ldc));
+        if ((rc = dalloc(&c->d_bpart, (size_t)cap * nnt))) return rc;
+        if ((rc = dalloc(&c->d_bpgb, (size_t)cap * nnt))) return rc;
+        if ((rc = dalloc(&c->d_bth, (size_t)cap * NR_NTHETA))) return rc;
+        if ((rc = dalloc(&c->d_bnll, (size_t)cap))) return rc;
+        if ((rc = dalloc(&c->d_bgrad, (size_t)cap * NR_NTHETA))) return rc;
+        c->b_cap = cap;
+        c->b_ldw = ldc;
+        c->b_nnt = nnt;
+        c->b_grad = false;
+        moved = true;
+    }
+    if (grad && !c->b_grad) {
+        if ((rc = dalloc(&c->d_bat, (size_t)c->ldr * c->b_ldw))) return rc;
+        HIPCHK(hipMemset(c->d_bat, 0, sizeof(float) * (size_t)c->ldr * c->b_ldw));
+        if ((rc = dalloc(&c->d_bu, (size_t)c->b_cap * c->n_t))) return rc;
+        c->b_grad = true;
+        moved = true;
+    }
+    if (mu_elems > c->b_cap_mu) {
+        if ((rc = dalloc(&c->d_bmu, mu_elems))) return rc;
+        c->b_cap_mu = mu_elems;
+        moved = true;
+    }
+    if (moved) ++g_epoch;
+    return 0;
+}
+
+struct MultiCall {
+    nr_ctx* const* ctx;
+    int n;
+    const double* const* theta;  // device
+    const int* n_pts;
+    double* const* nll;          // device
+    double* const* grad;         // device or null (array may be null)
+    double* const* mu;           // device or null (array may be null)
+};
+
+nr::WgenArgs wgen_args(nr_ctx* c, const double* th, int P) {
+    nr::WgenArgs w{};
+    w.theta = th;
+    w.n_pts = P;
+    w.ldw = c->b_ldw;
+    w.n_t = c->n_t;
+    w.basis = c->d_basis;
+    w.ssm = c->d_ssm;
+    w.mrow = c->d_mrow;
+    w.ph = c->ph;
+    w.wt = c->d_wt;
+    return w;
+}
+
+int build_plan(const MultiCall& mc, bool grad, BatchPlan* pl) {
+    std::vector<nr::GemmProb> pf(mc.n), pa(mc.n);
+    std::vector<nr::GemmTile> tf, ta;
+    for (int d = 0; d < mc.n; ++d) {
+        nr_ctx* c = mc.ctx[d];
+        const int P = mc.n_pts[d];
+        nr::GemmProb f{};
+        f.At = c->d_wt;
+        f.lda = c->b_ldw;
+        f.B = c->d_R;
+        f.ldb = c->ldr;
+        f.M = P;
+        f.N = c->n_reco;
+        f.K = c->n_t;
+        f.n = c->d_n;
+        f.b = c->d_b;
+        f.theta = mc.theta[d];
+        f.part = c->d_bpart;
+        f.part_gb = c->d_bpgb;
+        f.n_nt = c->b_nnt;
+        f.aout = grad ? c->d_bat : nullptr;
+        f.lda_out = c->b_ldw;
+        f.mu = mc.mu ? mc.mu[d] : nullptr;
+        pf[d] = f;
+        const int mt = (P + nr::kGemmBM - 1) / nr::kGemmBM;
+        for (int i = 0; i < mt; ++i)
+            for (int j = 0; j < c->b_nnt; ++j) tf.push_back({d, i, j, c->n_t});
+        if (grad) {
+            nr::GemmProb a{};
+            a.At = c->d_bat;
+            a.lda = c->b_ldw;
+            a.B = c->d_R;
+            a.ldb = c->ldr;
+            a.M = P;
+            a.N = c->n_t;
+            a.K = c->n_reco;
+            a.C = c->d_bu;
+            a.ldc = c->n_t;
+            pa[d] = a;
+            const int nt = (c->n_t + nr::kGemmBN - 1) / nr::kGemmBN;
+            for (int i = 0; i < mt; ++i)
+                for (int j = 0; j < nt; ++j) ta.push_back({d, i, j, c->n_reco});
+        }
+    }
+    // longest tiles first: the persistent work-groups pull from this list
+    auto by_cost = [](const nr::GemmTile& x, const nr::GemmTile& y) { return x.cost > y.cost; };
+    std::stable_sort(tf.begin(), tf.end(), by_cost);
+    std::stable_sort(ta.begin(), ta.end(), by_cost);
+    int rc;
+    if ((rc = dalloc(&pl->d_probs_f, pf.size())) || (rc = dalloc(&pl->d_tiles_f, tf.size())))
+        return rc;
+    HIPCHK(hipMemcpy(pl->d_probs_f, pf.data(), sizeof(nr::GemmProb) * pf.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(pl->d_tiles_f, tf.data(), sizeof(nr::GemmTile) * tf.size(), hipMemcpyHostToDevice));
+    pl->n_tiles_f = (int)tf.size();
+    pl->grid_f = nr::gemm_grid(nr::kModeNll, pl->n_tiles_f);
+    if (grad) {
+        if ((rc = dalloc(&pl->d_probs_a, pa.size())) || (rc = dalloc(&pl->d_tiles_a, ta.size())))
+            return rc;
+        HIPCHK(hipMemcpy(pl->d_probs_a, pa.data(), sizeof(nr::GemmProb) * pa.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(pl->d_tiles_a, ta.data(), sizeof(nr::GemmTile) * ta.size(), hipMemcpyHostToDevice));
+        pl->n_tiles_a = (int)ta.size();
+        pl->grid_a = nr::gemm_grid(nr::kModeAdj, pl->n_tiles_a);
+    }
+    pl->epoch = g_epoch;
+    return 0;
+}
+
+int enqueue_plan(const MultiCall& mc, bool grad, BatchPlan* pl, unsigned* ctr,
+                 hipStream_t s) {
+    for (int d = 0; d < mc.n; ++d)
+        HIPCHK(nr::launch_wgen(wgen_args(mc.ctx[d], mc.theta[d], mc.n_pts[d]), s));
+    HIPCHK(nr::launch_gemm(nr::kModeNll, pl->d_probs_f, pl->d_tiles_f, pl->n_tiles_f,
+                           ctr, pl->grid_f, s));
+    for (int d = 0; d < mc.n; ++d) {
+        nr_ctx* c = mc.ctx[d];
+        nr::FinalArgs f{};
+        f.part = c->d_bpart;
+        f.theta = mc.theta[d];
+        f.n_pts = mc.n_pts[d];
+        f.n_nt = c->b_nnt;
+        f.cdata = c->cdata;
+        for (int i = 0; i < NR_NTHETA; ++i) {
+            f.pull_mean[i] = c->pull_mean[i];
+            f.pull_sigma[i] = c->pull_sigma[i];
+        }
+        f.nll = mc.nll[d];
+        HIPCHK(nr::launch_finalize(f, s));
+    }
+    if (grad) {
+        HIPCHK(nr::launch_gemm(nr::kModeAdj, pl->d_probs_a, pl->d_tiles_a, pl->n_tiles_a,
+                               ctr + 2, pl->grid_a, s));
+        for (int d = 0; d < mc.n; ++d) {
+            nr_ctx* c = mc.ctx[d];
+            nr::ContractArgs a{};
+            a.U = c->d_bu;
+            a.ldu = c->n_t;
+            a.n_t = c->n_t;
+            a.n_pts = mc.n_pts[d];
+            a.n_nt = c->b_nnt;
+            a.ssm = c->d_ssm;
+            a.mrow = c->d_mrow;
+            a.basis = c->d_basis;
+            a.theta = mc.theta[d];
+            a.part_gb = c->d_bpgb;
+            for (int i = 0; i < NR_NTHETA; ++i) {
+                a.pull_mean[i] = c->pull_mean[i];
+                a.pull_sigma[i] = c->pull_sigma[i];
+            }
+            a.ph = c->ph;
+            a.grad = mc.grad[d];
+            HIPCHK(nr::launch_adj_contract(a, s));
+        }
+    }
+    return 0;
+}
+
+int run_multi(const MultiCall& mc, hipStream_t s) {
+    nr_ctx* owner = mc.ctx[0];
+    const bool grad = mc.grad != nullptr;
+    std::vector<const void*> key;
+    key.push_back((const void*)s);
+    key.push_back((const void*)(size_t)grad);
+    key.push_back((const void*)(size_t)(mc.mu != nullptr));
+    for (int d = 0; d < mc.n; ++d) {
+        key.push_back(mc.ctx[d]);
+        key.push_back(mc.theta[d]);
+        key.push_back((const void*)(size_t)mc.n_pts[d]);
+        key.push_back(mc.nll[d]);
+        if (grad) key.push_back(mc.grad[d]);
+        if (mc.mu) key.push_back(mc.mu[d]);
+    }
+    BatchPlan*& pl = owner->plans[key];
+    if (pl && pl->epoch != g_epoch) {
+        free_plan(pl);
+        pl = nullptr;
+    }
+    if (!pl) {
+        if (owner->plans.size() > 16) {
+            for (auto& kv : owner->plans)
+                if (kv.second && kv.first != key) free_plan(kv.second);
+            owner->plans.clear();
+        }
+        BatchPlan*& np = owner->plans[key];
+        np = new BatchPlan();
+        int rc = build_plan(mc, grad, np);
+        if (rc) { free_plan(np); owner->plans.erase(key); return rc; }
+        if (owner->use_graph) {
+            hipGraph_t g;
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            rc = enqueue_plan(mc, grad, np, owner->d_gctr, s);
+            hipError_t e = hipStreamEndCapture(s, &g);
+            if (rc) return rc;
+            if (e != hipSuccess)
+                return fail(NR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&np->graph, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess)
+                return fail(NR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        np->epoch = g_epoch;
+        BatchPlan* use = np;
+        if (use->graph) HIPCHK(hipGraphLaunch(use->graph, s));
+        else return enqueue_plan(mc, grad, use, owner->d_gctr, s);
+        return 0;
+    }
+    if (pl->graph) HIPCHK(hipGraphLaunch(pl->graph, s));
+    else return enqueue_plan(mc, grad, pl, owner->d_gctr, s);
+    return 0;
+}
+
+int check_multi(nr_ctx* const* ctx, int n_ctx, const int* n_pts) {
+    if (!ctx || n_ctx <= 0 || !n_pts) return fail(NR_EINVAL, "null argument or n_ctx <= 0");
+    for (int d = 0; d < n_ctx; ++d) {
+        int rc;
+        if ((rc = check_ready(ctx[d]))) return rc;
+        if (n_pts[d] <= 0) return fail(NR_EINVAL, "n_pts[%d] <= 0", d);
+        if (ctx[d]->device != ctx[0]->device)
+            return fail(NR_EINVAL, "all contexts of a grouped call share one device");
+    }
+    return 0;
+}
+
+int batched_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
+                 double* grad, double* mu) {
+    int rc;
+    if ((rc = check_ready(c))) return rc;
+    if ((rc = check_theta(theta, n_pts))) return rc;
+    if ((rc = set_device(c))) return rc;
+    if ((rc = ensure_batch(c, n_pts, grad != nullptr, mu ? (size_t)n_pts * c->n_reco : 0)))
+        return rc;
+    HIPCHK(hipMemcpyAsync(c->d_bth, theta, sizeof(double) * n_pts * NR_NTHETA,
+                          hipMemcpyHostToDevice, c->stream));
+    nr_ctx* cs[1] = {c};
+    const double* ths[1] = {c->d_bth};
+    double* nls[1] = {c->d_bnll};
+    double* grs[1] = {c->d_bgrad};
+    double* mus[1] = {c->d_bmu};
+    MultiCall mc{cs, 1, ths, &n_pts, nls, grad ? grs : nullptr, mu ? mus : nullptr};
+    if ((rc = run_multi(mc, c->stream))) return rc;
+    if (nll)
+        HIPCHK(hipMemcpyAsync(nll, c->d_bnll, sizeof(double) * n_pts, hipMemcpyDeviceToHost, c->stream));
+    if (grad)
+        HIPCHK(hipMemcpyAsync(grad, c->d_bgrad, sizeof(double) * n_pts * NR_NTHETA,
+                              hipMemcpyDeviceToHost, c->stream));
+    if (mu)
+        HIPCHK(hipMemcpyAsync(mu, c->d_bmu, sizeof(double) * n_pts * c->n_reco,
+                              hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* nr_last_error(void) { return g_err.c_str(); }
@@ -374,10 +692,12 @@ int nr_create(int device, nr_ctx** out) {
         delete c;
         return fail(NR_EHIP, "stream creation: %s", hipGetErrorString(e));
     }
-    if (dalloc(&c->d_a, 1) || dalloc(&c->d_gb, 1) || dalloc(&c->d_thsm, NR_NTHETA)) {
+    if (dalloc(&c->d_a, 1) || dalloc(&c->d_gb, 1) || dalloc(&c->d_thsm, NR_NTHETA) ||
+        dalloc(&c->d_gctr, 4)) {
         delete c;
         return NR_ENOMEM;
     }
+    (void)hipMemset(c->d_gctr, 0, 4 * sizeof(unsigned));
     const double sm[NR_NTHETA] = {0, 0, 0, 0, 0, 1, 1};
     (void)hipMemcpy(c->d_thsm, sm, sizeof(sm), hipMemcpyHostToDevice);
     *out = c;
@@ -398,6 +718,9 @@ void nr_destroy(nr_ctx* c) {
     dfree(&c->d_a); dfree(&c->d_gb); dfree(&c->d_jpart);
     dfree(&c->d_th); dfree(&c->d_out); dfree(&c->d_grad);
     dfree(&c->d_mu); dfree(&c->d_w); dfree(&c->d_thsm);
+    dfree(&c->d_wt); dfree(&c->d_bpart); dfree(&c->d_bpgb); dfree(&c->d_bat);
+    dfree(&c->d_bu); dfree(&c->d_bth); dfree(&c->d_bnll); dfree(&c->d_bgrad);
+    dfree(&c->d_bmu); dfree(&c->d_gctr);
     (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -752,6 +1075,74 @@ int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     *avg_ms = ms / iters;
+    return 0;
+}
+
+int nr_eval_nll_batched(nr_ctx* c, const double* theta, int n_pts, double* nll) {
+    if (!nll) return fail(NR_EINVAL, "nll is null");
+    return batched_sync(c, theta, n_pts, nll, nullptr, nullptr);
+}
+
+int nr_eval_nll_grad_batched(nr_ctx* c, const double* theta, int n_pts,
+                             double* nll, double* grad) {
+    if (!nll || !grad) return fail(NR_EINVAL, "nll or grad is null");
+    return batched_sync(c, theta, n_pts, nll, grad, nullptr);
+}
+
+int nr_eval_mu_batched(nr_ctx* c, const double* theta, int n_pts, double* mu) {
+    if (!mu) return fail(NR_EINVAL, "mu is null");
+    return batched_sync(c, theta, n_pts, nullptr, nullptr, mu);
+}
+
+int nr_eval_nll_multi_dev(nr_ctx* const* ctx, int n_ctx,
+                          const double* const* d_theta, const int* n_pts,
+                          double* const* d_nll, double* const* d_grad,
+                          void* stream) {
+    int rc;
+    if ((rc = check_multi(ctx, n_ctx, n_pts))) return rc;
+    if (!d_theta || !d_nll) return fail(NR_EINVAL, "null theta or nll array");
+    for (int d = 0; d < n_ctx; ++d) {
+        if (!d_theta[d] || !d_nll[d] || (d_grad && !d_grad[d]))
+            return fail(NR_EINVAL, "null device pointer for dataset %d", d);
+    }
+    if ((rc = set_device(ctx[0]))) return rc;
+    for (int d = 0; d < n_ctx; ++d)
+        if ((rc = ensure_batch(ctx[d], n_pts[d], d_grad != nullptr, 0))) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : ctx[0]->stream;
+    MultiCall mc{ctx, n_ctx, d_theta, n_pts, d_nll, d_grad, nullptr};
+    return run_multi(mc, s);
+}
+
+int nr_eval_nll_multi(nr_ctx* const* ctx, int n_ctx, const double* const* theta,
+                      const int* n_pts, double* const* nll) {
+    int rc;
+    if ((rc = check_multi(ctx, n_ctx, n_pts))) return rc;
+    if (!theta || !nll) return fail(NR_EINVAL, "null theta or nll array");
+    for (int d = 0; d < n_ctx; ++d) {
+        if (!nll[d]) return fail(NR_EINVAL, "nll[%d] is null", d);
+        if ((rc = check_theta(theta[d], n_pts[d]))) return rc;
+    }
+    if ((rc = set_device(ctx[0]))) return rc;
+    std::vector<const double*> ths(n_ctx);
+    std::vector<double*> nls(n_ctx);
+    hipStream_t s = ctx[0]->stream;
+    for (int d = 0; d < n_ctx; ++d) {
+        nr_ctx* c = ctx[d];
+        if ((rc = ensure_batch(c, n_pts[d], false, 0))) return rc;
+    }
+    for (int d = 0; d < n_ctx; ++d) {
+        nr_ctx* c = ctx[d];
+        HIPCHK(hipMemcpyAsync(c->d_bth, theta[d], sizeof(double) * n_pts[d] * NR_NTHETA,
+                              hipMemcpyHostToDevice, s));
+        ths[d] = c->d_bth;
+        nls[d] = c->d_bnll;
+    }
+    MultiCall mc{ctx, n_ctx, ths.data(), n_pts, nls.data(), nullptr, nullptr};
+    if ((rc = run_multi(mc, s))) return rc;
+    for (int d = 0; d < n_ctx; ++d)
+        HIPCHK(hipMemcpyAsync(nll[d], ctx[d]->d_bnll, sizeof(double) * n_pts[d],
+                              hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
     return 0;
 }
 

@@ -1,0 +1,81 @@
+// Internal declarations of the batched (GEMM) path.
+#pragma once
+#include "common.h"
+
+namespace nr {
+
+constexpr int kModeNll = 0;  // forward: fused Poisson epilogue
+constexpr int kModeAdj = 1;  // adjoint: C = A R^T written as FP32
+
+struct WgenArgs {
+    const double* theta;  // [n_pts][7]
+    int n_pts, ldw, n_t;
+    const double* basis;  // [kNBasis][n_t]
+    const double* ssm;    // [n_t]
+    const double* mrow;   // [n_t]
+    Phys ph;
+    float* wt;            // [n_t][ldw]
+};
+
+// One GEMM problem of the grouped launch (one dataset / analysis).
+// Forward: C[M=n_pts][N=n_reco] = A[M][K=n_t] B[K][N] with A given as its
+// transpose At[K][lda] (M contiguous) and B = R[K][ldb].
+// Adjoint: C[M][N=n_t] = A[M][K=n_reco] R^T with At[K][lda] and R[N][ldb].
+struct GemmProb {
+    const float* At;
+    const float* B;
+    int lda, ldb, M, N, K;
+    // forward epilogue
+    const double* n;
+    const double* b;
+    const double* theta;  // [M][7]
+    double* part;         // [M][n_nt] deviance partials
+    double* part_gb;      // [M][n_nt] sum_j a_j b_j partials (with aout)
+    int n_nt;
+    float* aout;          // [N][lda_out] d(-2lnL)/d mu, or null
+    int lda_out;
+    double* mu;           // [M][N] or null
+    // adjoint output
+    float* C;
+    int ldc;
+    int pad;
+};
+
+struct GemmTile {
+    int prob, mt, nt, cost;
+};
+
+struct FinalArgs {
+    const double* part;
+    const double* theta;
+    int n_pts, n_nt;
+    double cdata;
+    double pull_mean[kNTheta];
+    double pull_sigma[kNTheta];
+    double* nll;
+};
+
+struct ContractArgs {
+    const float* U;  // [n_pts][ldu]
+    int ldu, n_t, n_pts, n_nt;
+    const double* ssm;
+    const double* mrow;
+    const double* basis;
+    const double* theta;
+    const double* part_gb;
+    double pull_mean[kNTheta];
+    double pull_sigma[kNTheta];
+    Phys ph;
+    double* grad;    // [n_pts][7]
+};
+
+constexpr int kGemmBM = 128, kGemmBN = 128;
+
+hipError_t launch_wgen(const WgenArgs& a, hipStream_t s);
+hipError_t launch_gemm(int mode, const GemmProb* probs, const GemmTile* tiles,
+                       int n_tiles, unsigned* ctr, int grid, hipStream_t s);
+hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
+hipError_t launch_adj_contract(const ContractArgs& a, hipStream_t s);
+int gemm_grid(int mode, int n_tiles);
+
+}  // namespace nr

@@ -1,0 +1,407 @@
+// Batched path on gfx950: many parameter points (and many datasets of
+// uneven binning) at once.  The per-point weights turn the fold into a dense
+// GEMM  mu[p][j] = f_bkg b_j + sum_l W[p][l] R[l][j]  (Eq. (matrix_reweight)
+// applied to a batch), run on FP32 MFMA (v_mfma_f32_32x32x2_f32) in one
+// persistent grouped launch with a fused Poisson epilogue (Eq. (logL)).
+#include "batched.h"
+
+#include <cmath>
+
+namespace nr {
+
+namespace {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Basis coefficients c_b(theta) of S_theta = sum_b c_b I_b (the flavour sum
+// of Eq. (sm_cross_section) with Eq. (xs_nsi) couplings and the magnetic
+// term of Eq. (xs_mm), split by source group and by the coupling products).
+__device__ inline void basis_coef(const double* th, const Phys& ph,
+                                  double c[kNBasis]) {
+    const double gle = ph.gLe + th[0], gre = ph.gR + th[1];
+    const double glm = ph.gLm, grm = ph.gR;
+    const double glt = ph.gLm + th[2], grt = ph.gR + th[3];
+    for (int g = 0; g < 2; ++g) {
+        const double f = g ? th[5] : 1.0;
+        const int o = g * 10;
+        c[o + 0] = f * gle * gle;
+        c[o + 1] = f * gre * gre;
+        c[o + 2] = -f * gle * gre;
+        c[o + 3] = f * glm * glm;
+        c[o + 4] = f * grm * grm;
+        c[o + 5] = -f * glm * grm;
+        c[o + 6] = f * glt * glt;
+        c[o + 7] = f * grt * grt;
+        c[o + 8] = -f * glt * grt;
+        c[o + 9] = f * ph.cmm * th[4];
+    }
+}
+
+__device__ inline void basis_dcoef(const double* th, const Phys& ph,
+                                   double dc[kNTheta][kNBasis]) {
+    for (int i = 0; i < kNTheta; ++i)
+        for (int b = 0; b < kNBasis; ++b) dc[i][b] = 0.0;
+    const double gle = ph.gLe + th[0], gre = ph.gR + th[1];
+    const double glm = ph.gLm, grm = ph.gR;
+    const double glt = ph.gLm + th[2], grt = ph.gR + th[3];
+    for (int g = 0; g < 2; ++g) {
+        const double f = g ? th[5] : 1.0;
+        const int o = g * 10;
+        dc[0][o + 0] = f * 2.0 * gle;
+        dc[0][o + 2] = -f * gre;
+        dc[1][o + 1] = f * 2.0 * gre;
+        dc[1][o + 2] = -f * gle;
+        dc[2][o + 6] = f * 2.0 * glt;
+        dc[2][o + 8] = -f * grt;
+        dc[3][o + 7] = f * 2.0 * grt;
+        dc[3][o + 8] = -f * glt;
+        dc[4][o + 9] = f * ph.cmm;
+    }
+    dc[5][10] = gle * gle;
+    dc[5][11] = gre * gre;
+    dc[5][12] = -gle * gre;
+    dc[5][13] = glm * glm;
+    dc[5][14] = grm * grm;
+    dc[5][15] = -glm * grm;
+    dc[5][16] = glt * glt;
+    dc[5][17] = grt * grt;
+    dc[5][18] = -glt * grt;
+    dc[5][19] = ph.cmm * th[4];
+}
+
+// ------------------------------------------------------------ weights
+// W^T[l][p] = m_l * w_l(theta_p) with w_l = S_theta(T_l) / S_SM(T_l) and
+// S_theta(T_l) = sum_b c_b(theta_p) I_b(T_l) (FP64), stored as FP32 in the
+// K-major layout the GEMM streams.  One thread per point, a strip of rows
+// per work-group row; the basis row is wave-uniform.
+constexpr int kWgenRows = 32;
+
+__global__ __launch_bounds__(256) void k_wgen(WgenArgs a) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const int l0 = blockIdx.y * kWgenRows;
+    if (p >= a.ldw) return;
+    double c[kNBasis];
+    const bool ok = p < a.n_pts;
+    if (ok) {
+        double th[kNTheta];
+        for (int i = 0; i < kNTheta; ++i) th[i] = a.theta[(size_t)p * kNTheta + i];
+        basis_coef(th, a.ph, c);
+    } else {
+        for (int b = 0; b < kNBasis; ++b) c[b] = 0.0;
+    }
+    const int l1 = min(l0 + kWgenRows, a.n_t);
+    for (int l = l0; l < l1; ++l) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b < kNBasis; ++b)
+            s = fma(c[b], a.basis[(size_t)b * a.n_t + l], s);
+        const double ssm = a.ssm[l];
+        const double w = ssm > 0.0 ? s / ssm : 1.0;
+        a.wt[(size_t)l * a.ldw + p] = ok ? (float)(a.mrow[l] * w) : 0.f;
+    }
+}
+
+// --------------------------------------------------------------- GEMM
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int kGemmThreads = 256;  // 4 waves, 2 x 2, each 64 x 64
+constexpr int LDA_S = BM + 4;      // LDS row stride (floats)
+constexpr int LDB_S = BN + 4;
+
+template <int MODE>
+__global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
+                                                       const GemmTile* tiles,
+                                                       int n_tiles,
+                                                       unsigned* ctr) {
+    __shared__ float As[BK][LDA_S];
+    __shared__ float Bs[BK][LDB_S];
+    __shared__ float Cs[BM / 2][BN + 1];
+    __shared__ int s_tile;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int li = lane & 31, lk = lane >> 5;
+
+    for (;;) {
+        if (tid == 0) s_tile = (int)atomicAdd(&ctr[0], 1u);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();
+        if (t >= n_tiles) break;
+        const GemmTile tl = tiles[t];
+        const GemmProb pr = probs[tl.prob];
+        const int m0 = tl.mt * BM, n0 = tl.nt * BN;
+        const int K = pr.K;
+
+        v16f acc[2][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+        float4 ra[2], rb[2];
+        auto gload = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int q = tid + i * kGemmThreads;  // 0..511
+                {   // A^T tile: BK rows x BM floats, M contiguous
+                    const int kk = q >> 5, c4 = q & 31;
+                    const int k = k0 + kk, m = m0 + 4 * c4;
+                    ra[i] = (k < K && m < pr.lda)
+                                ? *reinterpret_cast<const float4*>(
+                                      pr.At + (size_t)k * pr.lda + m)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+                if (MODE != kModeAdj) {  // B[k][n], N contiguous
+                    const int kk = q >> 5, c4 = q & 31;
+                    const int k = k0 + kk, n = n0 + 4 * c4;
+                    rb[i] = (k < K && n < pr.ldb)
+                                ? *reinterpret_cast<const float4*>(
+                                      pr.B + (size_t)k * pr.ldb + n)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+                } else {  // B[k][n] = R[n][k], K contiguous
+                    const int nn = q >> 2, k4 = q & 3;
+                    const int n = n0 + nn, k = k0 + 4 * k4;
+                    rb[i] = (n < pr.N && k < pr.ldb)
+                                ? *reinterpret_cast<const float4*>(
+                                      pr.B + (size_t)n * pr.ldb + k)
+                                : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+        };
+        auto sstore = [&]() {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int q = tid + i * kGemmThreads;
+                {
+                    const int kk = q >> 5, c4 = q & 31;
+                    *reinterpret_cast<float4*>(&As[kk][4 * c4]) = ra[i];
+                }
+                if (MODE != kModeAdj) {
+                    const int kk = q >> 5, c4 = q & 31;
+                    *reinterpret_cast<float4*>(&Bs[kk][4 * c4]) = rb[i];
+                } else {
+                    const int nn = q >> 2, k4 = q & 3;
+                    Bs[4 * k4 + 0][nn] = rb[i].x;
+                    Bs[4 * k4 + 1][nn] = rb[i].y;
+                    Bs[4 * k4 + 2][nn] = rb[i].z;
+                    Bs[4 * k4 + 3][nn] = rb[i].w;
+                }
+            }
+        };
+
+        gload(0);
+        for (int k0 = 0; k0 < K; k0 += BK) {
+            __syncthreads();
+            sstore();
+            __syncthreads();
+            if (k0 + BK < K) gload(k0 + BK);
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 2) {
+                const float a0 = As[kk + lk][wm * 64 + li];
+                const float a1 = As[kk + lk][wm * 64 + 32 + li];
+                const float b0 = Bs[kk + lk][wn * 64 + li];
+                const float b1 = Bs[kk + lk][wn * 64 + 32 + li];
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        }
+
+        // ---- epilogue.  Output element (i, j) of a 32x32 block sits in
+        // lane j + 32 * ((i / 4) % 2), register (i / 8) * 4 + i % 4.
+        if (MODE == kModeAdj) {
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int i = wm * 64 + bi * 32 + (r >> 2) * 8 + lk * 4 + (r & 3);
+                        const int j = wn * 64 + bj * 32 + li;
+                        const int p = m0 + i, col = n0 + j;
+                        if (p < pr.M && col < pr.N)
+                            pr.C[(size_t)p * pr.ldc + col] = acc[bi][bj][r];
+                    }
+        } else {
+            // Accumulators go through LDS one 64-row half at a time; four
+            // threads share a row and walk 32 columns each.
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi) {
+                __syncthreads();
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        const int il = wm * 32 + (r >> 2) * 8 + lk * 4 + (r & 3);
+                        Cs[il][wn * 64 + bj * 32 + li] = acc[bi][bj][r];
+                    }
+                __syncthreads();
+                const int il = tid >> 2, cq = tid & 3;
+                const int i = (il >> 5) * 64 + bi * 32 + (il & 31);
+                const int p = m0 + i;
+                double dsum = 0.0, gsum = 0.0;
+                if (p < pr.M) {
+                    const double fb = pr.theta[(size_t)p * kNTheta + 6];
+                    for (int q = 0; q < 32; ++q) {
+                        const int j = cq * 32 + q;
+                        const int col = n0 + j;
+                        if (col >= pr.N) break;
+                        const double bj_ = pr.b[col];
+                        const double mu = fb * bj_ + (double)Cs[il][j];
+                        const double nj = pr.n[col];
+                        double d;
+                        if (nj > 0.0)
+                            d = mu > 0.0 ? (mu - nj + nj * log(nj / mu)) : INFINITY;
+                        else
+                            d = mu;
+                        dsum += d;
+                        if (pr.mu) pr.mu[(size_t)p * pr.N + col] = mu;
+                        if (pr.aout) {
+                            const double aj = 2.0 * (1.0 - nj / mu);
+                            pr.aout[(size_t)col * pr.lda_out + p] = (float)aj;
+                            gsum += aj * bj_;
+                        }
+                    }
+                }
+                dsum += __shfl_xor(dsum, 1, 64);
+                dsum += __shfl_xor(dsum, 2, 64);
+                gsum += __shfl_xor(gsum, 1, 64);
+                gsum += __shfl_xor(gsum, 2, 64);
+                if (cq == 0 && p < pr.M) {
+                    pr.part[(size_t)p * pr.n_nt + tl.nt] = dsum;
+                    if (pr.aout) pr.part_gb[(size_t)p * pr.n_nt + tl.nt] = gsum;
+                }
+            }
+        }
+    }
+    // the last work-group out resets the tile counter for the next launch
+    __syncthreads();
+    if (tid == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(&ctr[1], 1u);
+        if (prev == gridDim.x - 1) {
+            ctr[0] = 0u;
+            ctr[1] = 0u;
+        }
+    }
+}
+
+// -2lnL per point: sum of the column-tile deviance partials, data constant,
+// pulls (Eq. (logL)).
+__global__ void k_finalize(FinalArgs a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n_pts) return;
+    double d = 0.0;
+    for (int q = 0; q < a.n_nt; ++q) d += a.part[(size_t)p * a.n_nt + q];
+    double pulls = 0.0;
+    for (int i = 0; i < kNTheta; ++i)
+        if (a.pull_sigma[i] > 0.0) {
+            const double z = (a.theta[(size_t)p * kNTheta + i] - a.pull_mean[i]) / a.pull_sigma[i];
+            pulls += z * z;
+        }
+    a.nll[p] = 2.0 * d + 2.0 * a.cdata + pulls;
+}
+
+// Gradient per point from the adjoint U[p][l] = sum_j a_pj R_lj:
+// grad_i = sum_l U_pl (m_l / S_SM(T_l)) sum_b dc_ib I_b(T_l) + [i = f_bkg]
+// sum_j a_pj b_j + pull term.  One work-group per point.
+__global__ __launch_bounds__(256) void k_adj_contract(ContractArgs a) {
+    __shared__ double jsh[4][kNBasis];
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    double J[kNBasis];
+    for (int b = 0; b < kNBasis; ++b) J[b] = 0.0;
+    for (int l = tid; l < a.n_t; l += 256) {
+        const double ssm = a.ssm[l];
+        if (!(ssm > 0.0)) continue;
+        const double u = (double)a.U[(size_t)p * a.ldu + l] * (a.mrow[l] / ssm);
+#pragma unroll
+        for (int b = 0; b < kNBasis; ++b) J[b] = fma(u, a.basis[(size_t)b * a.n_t + l], J[b]);
+    }
+    for (int b = 0; b < kNBasis; ++b) {
+        const double s = wave_sum64(J[b]);
+        if (lane == 0) jsh[wave][b] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double Jt[kNBasis];
+        for (int b = 0; b < kNBasis; ++b)
+            Jt[b] = jsh[0][b] + jsh[1][b] + jsh[2][b] + jsh[3][b];
+        double th[kNTheta];
+        for (int i = 0; i < kNTheta; ++i) th[i] = a.theta[(size_t)p * kNTheta + i];
+        double dc[kNTheta][kNBasis];
+        basis_dcoef(th, a.ph, dc);
+        double gb = 0.0;
+        for (int q = 0; q < a.n_nt; ++q) gb += a.part_gb[(size_t)p * a.n_nt + q];
+        for (int i = 0; i < kNTheta; ++i) {
+            double g = 0.0;
+            for (int b = 0; b < kNBasis; ++b) g += dc[i][b] * Jt[b];
+            if (i == 6) g += gb;
+            if (a.pull_sigma[i] > 0.0)
+                g += 2.0 * (th[i] - a.pull_mean[i]) / (a.pull_sigma[i] * a.pull_sigma[i]);
+            a.grad[(size_t)p * kNTheta + i] = g;
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_wgen(const WgenArgs& a, hipStream_t s) {
+    dim3 grid((a.ldw + 255) / 256, (a.n_t + kWgenRows - 1) / kWgenRows);
+    hipLaunchKernelGGL(k_wgen, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(int mode, const GemmProb* probs, const GemmTile* tiles,
+                       int n_tiles, unsigned* ctr, int grid, hipStream_t s) {
+    if (mode == kModeAdj)
+        hipLaunchKernelGGL(k_gemm<kModeAdj>, dim3(grid), dim3(kGemmThreads), 0, s,
+                           probs, tiles, n_tiles, ctr);
+    else
+        hipLaunchKernelGGL(k_gemm<kModeNll>, dim3(grid), dim3(kGemmThreads), 0, s,
+                           probs, tiles, n_tiles, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3((a.n_pts + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_contract(const ContractArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_contract, dim3(a.n_pts), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace nr
+
+namespace nr {
+
+// Persistent grid: as many work-groups as can be resident at once.
+int gemm_grid(int mode, int n_tiles) {
+    int dev = 0, cus = 0, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (mode == kModeAdj)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm<kModeAdj>,
+                                                           kGemmThreads, 0);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm<kModeNll>,
+                                                           kGemmThreads, 0);
+    if (cus <= 0) cus = 256;
+    if (per_cu <= 0) per_cu = 1;
+    int g = cus * per_cu;
+    if (g > n_tiles) g = n_tiles;
+    return g < 1 ? 1 : g;
+}
+
+}  // namespace nr

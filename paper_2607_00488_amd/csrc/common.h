@@ -67,7 +67,7 @@ struct FoldArgs {
     double* chunk_gb;     // [n_cc]
     double* out_nll;      // [1]
     double* out_mu;       // [n_reco] or null
-    float* out_a;         // [ldr] or null: d(-2lnL)/d mu_j
+    double* out_a;        // [ldr] or null: d(-2lnL)/d mu_j
     double* out_gb;       // [1] or null: sum_j a_j b_j
     double* out_w;        // [n_t] or null: weights w_l
     double cdata;
@@ -79,7 +79,7 @@ struct FoldArgs {
 struct AdjArgs {
     const float* R;
     int ldr, n_t, n_reco;
-    const float* a;       // [ldr]
+    const double* a;      // [ldr]
     const double* ssm;
     const double* mrow;
     const double* basis;  // [kNBasis][n_t]

@@ -147,8 +147,8 @@ __device__ inline double block_sum_512(double v, double* sh) {
 // finisher sums the chunks and writes -2lnL.  Deterministic: no float
 // atomics.
 __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
-    __shared__ float vs[kFoldMaxRows];
-    __shared__ float4 red[kFoldWaves][64];
+    __shared__ double vs[kFoldMaxRows];
+    __shared__ double4 red[kFoldWaves][64];
     __shared__ double dred[kFoldWaves];
     __shared__ double dred2[kFoldWaves];
     __shared__ int s_last;
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
 
-    // weights for this work-group's rows
+    // weights for this work-group's rows (FP64, kept in LDS)
     for (int r = tid; r < nrows; r += kFoldThreads) {
         const int l = row0 + r;
         const int blk = l / kRowsPerBlock, ln = l % kRowsPerBlock;
@@ -169,17 +169,19 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
         const double ssm = a.ssm[l];
         const double w = ssm > 0.0 ? s / ssm : 1.0;
         if (a.out_w && cc == 0) a.out_w[l] = w;
-        vs[r] = (float)(a.mrow[l] * w);
+        vs[r] = a.mrow[l] * w;
     }
     __syncthreads();
 
-    // stream the row block
+    // Stream the row block.  R is FP32 in HBM; the products and sums are
+    // formed in FP64, which the full-rate FP64 vector units of gfx950 absorb
+    // at no cost to this bandwidth-bound loop.
     const int ld4 = a.ldr >> 2;
     const int c4 = cc * 64 + lane;
     const bool colok = c4 < ld4;
     const float4* __restrict__ Rp =
         reinterpret_cast<const float4*>(a.R) + (size_t)row0 * ld4 + c4;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     if (colok) {
         int r = wave;
         for (; r + kFoldWaves * (kFoldUnroll - 1) < nrows;
@@ -190,32 +192,32 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
                 x[q] = ld_stream(Rp + (size_t)(r + q * kFoldWaves) * ld4);
 #pragma unroll
             for (int q = 0; q < kFoldUnroll; ++q) {
-                const float v = vs[r + q * kFoldWaves];
-                acc.x = fmaf(x[q].x, v, acc.x);
-                acc.y = fmaf(x[q].y, v, acc.y);
-                acc.z = fmaf(x[q].z, v, acc.z);
-                acc.w = fmaf(x[q].w, v, acc.w);
+                const double v = vs[r + q * kFoldWaves];
+                acc0 = fma((double)x[q].x, v, acc0);
+                acc1 = fma((double)x[q].y, v, acc1);
+                acc2 = fma((double)x[q].z, v, acc2);
+                acc3 = fma((double)x[q].w, v, acc3);
             }
         }
         for (; r < nrows; r += kFoldWaves) {
             const float4 x = ld_stream(Rp + (size_t)r * ld4);
-            const float v = vs[r];
-            acc.x = fmaf(x.x, v, acc.x);
-            acc.y = fmaf(x.y, v, acc.y);
-            acc.z = fmaf(x.z, v, acc.z);
-            acc.w = fmaf(x.w, v, acc.w);
+            const double v = vs[r];
+            acc0 = fma((double)x.x, v, acc0);
+            acc1 = fma((double)x.y, v, acc1);
+            acc2 = fma((double)x.z, v, acc2);
+            acc3 = fma((double)x.w, v, acc3);
         }
     }
-    red[wave][lane] = acc;
+    red[wave][lane] = make_double4(acc0, acc1, acc2, acc3);
     __syncthreads();
     if (tid < kFoldCols) {
         const int col = cc * kFoldCols + tid;
         if (col < a.ldr) {
             double s = 0.0;
+            const int k = tid & 3;
             for (int w = 0; w < kFoldWaves; ++w) {
-                const float4 q = red[w][tid >> 2];
-                const int k = tid & 3;
-                s += (double)(k == 0 ? q.x : k == 1 ? q.y : k == 2 ? q.z : q.w);
+                const double4 q = red[w][tid >> 2];
+                s += k == 0 ? q.x : k == 1 ? q.y : k == 2 ? q.z : q.w;
             }
             a.colpart[(size_t)rb * a.ldr + col] = s;
         }
@@ -248,10 +250,10 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
                 dev = mu;
             }
             const double aj = 2.0 * (1.0 - nj / mu);
-            if (a.out_a) a.out_a[col] = (float)aj;
+            if (a.out_a) a.out_a[col] = aj;
             gb = aj * bj;
         } else if (col < a.ldr && a.out_a) {
-            a.out_a[col] = 0.f;
+            a.out_a[col] = 0.0;
         }
     }
     const double dsum = block_sum_512(dev, dred);
@@ -287,7 +289,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
 
 // ------------------------------------------------------------- adjoint
 constexpr int kAdjThreads = 256;
-constexpr int kAdjMaxLd = 8192;
+constexpr int kAdjMaxLd = 4096;
 
 // Coefficients of the 20 basis spectra and their theta-derivatives.  The
 // basis (per group g = non-8B / 8B, per flavour e, mu, tau) is
@@ -333,31 +335,30 @@ __device__ inline void basis_dcoef(const double* th, const Phys& ph,
 // contraction with the weight derivatives
 // d v_l / d theta_i = m_l / S_SM(T_l) * sum_b dc_ib I_b(T_l).
 __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
-    __shared__ float4 as4[kAdjMaxLd / 4];
+    __shared__ double as[kAdjMaxLd];
     __shared__ double jsh[kAdjThreads / 64][kNBasis];
     __shared__ int s_last;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ld4 = a.ldr >> 2;
     const bool lds = a.ldr <= kAdjMaxLd;
-    const float4* a4 = reinterpret_cast<const float4*>(a.a);
     if (lds)
-        for (int c = tid; c < ld4; c += kAdjThreads) as4[c] = a4[c];
+        for (int c = tid; c < a.ldr; c += kAdjThreads) as[c] = a.a[c];
     __syncthreads();
+    const double* av = lds ? as : a.a;
     double J = 0.0;  // lane b < kNBasis holds J_b of this wave
     const int nwaves = gridDim.x * (kAdjThreads / 64);
     for (int l = blockIdx.x * (kAdjThreads / 64) + wave; l < a.n_t;
          l += nwaves) {
         const float4* Rp = reinterpret_cast<const float4*>(a.R) + (size_t)l * ld4;
-        float s = 0.f;
+        double s = 0.0;
         for (int c = lane; c < ld4; c += 64) {
             const float4 x = ld_stream(Rp + c);
-            const float4 y = lds ? as4[c] : a4[c];
-            s = fmaf(x.x, y.x, s);
-            s = fmaf(x.y, y.y, s);
-            s = fmaf(x.z, y.z, s);
-            s = fmaf(x.w, y.w, s);
+            s = fma((double)x.x, av[4 * c + 0], s);
+            s = fma((double)x.y, av[4 * c + 1], s);
+            s = fma((double)x.z, av[4 * c + 2], s);
+            s = fma((double)x.w, av[4 * c + 3], s);
         }
-        const double u = wave_sum((double)s);
+        const double u = wave_sum(s);
         const double ssm = a.ssm[l];
         if (ssm > 0.0 && lane < kNBasis)
             J += u * (a.mrow[l] / ssm) * a.basis[(size_t)lane * a.n_t + l];

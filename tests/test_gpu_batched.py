@@ -1,0 +1,128 @@
+"""Parity of the batched (FP32-MFMA GEMM) path with the FP64 oracle and with
+the single-point path: one analysis, several analyses of uneven binning in
+one grouped launch, the batched gradient, and graph replays."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from problems import config_inputs, gpu_context, inputs, parity_thetas
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def mu_close(got, ref):
+    tol = 1e-5 * np.abs(ref) + 1e-9 * np.abs(ref).max()
+    return np.abs(got - ref) <= tol
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    p = config_inputs(0)
+    return p, gpu_context(p)
+
+
+def test_batched_mu_and_nll_config0(cfg0):
+    p, ctx = cfg0
+    o = p["oracle"]
+    th = parity_thetas(0, 1024)
+    log(f"[gpu] batched config-0 over {len(th)} points")
+    mu = ctx.eval_mu_batched(th)
+    nll = ctx.eval_nll_batched(th)
+    plain = ctx.eval_nll(th)
+    worst_mu = worst = 0.0
+    for i in range(len(th)):
+        ref_mu = o.mu(th[i])
+        ok = mu_close(mu[i], ref_mu)
+        assert ok.all(), (i, int(np.argmin(ok)))
+        worst_mu = max(worst_mu, float(np.max(np.abs(mu[i] - ref_mu) / ref_mu)))
+        ref = o.nll(th[i])
+        assert abs(nll[i] - ref) <= 1e-3, (i, nll[i], ref)
+        worst = max(worst, abs(nll[i] - ref))
+    assert np.max(np.abs(nll - plain)) <= 1e-3
+    log(f"[gpu] batched max rel dmu {worst_mu:.3e}, max |dnll| {worst:.3e}")
+
+
+def test_batched_gradient_config0(cfg0):
+    p, ctx = cfg0
+    o = p["oracle"]
+    th = parity_thetas(0, 64)
+    th[:, 5:7] = synth.rng(3).uniform(0.8, 1.2, (len(th), 2))
+    nll, g = ctx.eval_nll_grad_batched(th)
+    for i in range(len(th)):
+        v, ref = o.nll_grad(th[i])
+        assert abs(nll[i] - v) <= 1e-3
+        scale = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+        assert np.all(np.abs(g[i] - ref) <= 1e-4 * scale + 1e-6), (i, g[i], ref)
+
+
+SHAPES = [  # n_t, n_reco, n_e, n_pts: tile edges in every dimension
+    (256, 128, 64, 128),
+    (300, 77, 40, 131),
+    (512, 256, 32, 64),
+    (130, 300, 16, 7),
+    (2048, 512, 48, 257),
+    (64, 1, 8, 3),
+]
+
+
+@pytest.fixture(scope="module")
+def multi():
+    probs, ctxs, ths = [], [], []
+    for d, (n_t, n_reco, n_e, P) in enumerate(SHAPES):
+        p = inputs(n_t, n_reco, n_e, 100_000, 500 + d, 600 + d)
+        probs.append(p)
+        ctxs.append(gpu_context(p))
+        ths.append(synth.theta_prior(P, 700 + d))
+    return probs, ctxs, ths
+
+
+def test_grouped_uneven_datasets(multi):
+    import paper_2607_00488_amd as nr
+    probs, ctxs, ths = multi
+    log(f"[gpu] grouped launch over {len(ctxs)} datasets")
+    outs = nr.eval_nll_multi(ctxs, ths)
+    for d, (p, th, out) in enumerate(zip(probs, ths, outs)):
+        o = p["oracle"]
+        for i in range(0, len(th), max(1, len(th) // 16)):
+            ref = o.nll(th[i])
+            assert abs(out[i] - ref) <= 1e-3, (d, i, out[i], ref)
+        single = ctxs[d].eval_nll_batched(th)
+        assert np.max(np.abs(single - out)) <= 1e-9 * np.abs(out).max()
+
+
+def test_grouped_graph_replay_and_grad(multi):
+    """Device-pointer grouped launch, replayed as a cached graph with eager
+    work in between; every replay equals the first; gradients match."""
+    import torch
+    import paper_2607_00488_amd as nr
+    probs, ctxs, ths = multi
+    dev = torch.device("cuda:0")
+    tt = [torch.tensor(t, dtype=torch.float64, device=dev) for t in ths]
+    nl = [torch.empty(len(t), dtype=torch.float64, device=dev) for t in ths]
+    gr = [torch.empty(len(t), 7, dtype=torch.float64, device=dev) for t in ths]
+    s = torch.cuda.Stream(device=dev)
+    ref = None
+    for rep in range(3):
+        nr.eval_nll_multi_dev(ctxs, tt, nl, gr, stream=s)
+        s.synchronize()
+        got = [x.cpu().numpy().copy() for x in nl] + [x.cpu().numpy().copy() for x in gr]
+        if ref is None:
+            ref = got
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), rep
+        (torch.randn(1 << 18, device=dev) ** 2).sum().item()
+    for d, p in enumerate(probs):
+        o = p["oracle"]
+        g = ref[len(probs) + d]
+        for i in range(0, len(ths[d]), max(1, len(ths[d]) // 4)):
+            v, rg = o.nll_grad(ths[d][i])
+            assert abs(ref[d][i] - v) <= 1e-3
+            scale = np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())
+            assert np.all(np.abs(g[i] - rg) <= 1e-4 * scale + 1e-6), (d, i)

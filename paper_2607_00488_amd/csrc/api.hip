@@ -95,7 +95,7 @@ struct nr_ctx {
     std::vector<nr::EUnit> units;
     std::vector<int> ustart;
     std::vector<double> ssm, basis;
-    double*d_E = nullptr, *d_W = nullptr, *d_Pe = nullptr, *d_tc = nullptr;
+    double *d_E = nullptr /* 1/E per node */, *d_W = nullptr, *d_Pe = nullptr, *d_tc = nullptr;
     double *d_ssm = nullptr, *d_basis = nullptr, *d_part = nullptr;
     int *d_group = nullptr, *d_jmin = nullptr, *d_ustart = nullptr;
     nr::EUnit* d_units = nullptr;
@@ -132,11 +132,11 @@ struct nr_ctx {
     // batched (GEMM) path workspace
     int b_cap = 0, b_ldw = 0, b_nnt = 0;
     bool b_grad = false;
-    float* d_wt = nullptr;      // [n_t][ldw]   weights, K-major
+    double* d_wt = nullptr;     // [n_t][ldw]   weights, K-major
     double* d_bpart = nullptr;  // [cap][n_nt]  deviance partials
     double* d_bpgb = nullptr;   // [cap][n_nt]  sum a b partials
-    float* d_bat = nullptr;     // [ldr][ldw]   d(-2lnL)/d mu, j-major
-    float* d_bu = nullptr;      // [cap][n_t]   adjoint rows
+    double* d_bat = nullptr;    // [ldr][ldw]   d(-2lnL)/d mu, j-major
+    double* d_bu = nullptr;     // [cap][n_t]   adjoint rows
     double *d_bth = nullptr, *d_bnll = nullptr, *d_bgrad = nullptr, *d_bmu = nullptr;
     size_t b_cap_mu = 0;
     unsigned* d_gctr = nullptr;  // [4] tile counters (forward, adjoint)
@@ -259,7 +259,7 @@ nr::EintArgs eint_args(nr_ctx* c, const double* d_theta) {
     nr::EintArgs a{};
     a.units = c->d_units;
     a.n_units = (int)c->units.size();
-    a.nodeE = c->d_E;
+    a.nodeIE = c->d_E;
     a.nodeW = c->d_W;
     a.nodePe = c->d_Pe;
     a.srcGroup = c->d_group;
@@ -407,7 +407,7 @@ int ensure_batch(nr_ctx* c, int n_pts, bool grad, size_t mu_elems) {
         const int cap = std::max(n_pts, 64);
         const int ldc = (cap + 3) / 4 * 4;
         if ((rc = dalloc(&c->d_wt, (size_t)c->n_t * ldc))) return rc;
-        HIPCHK(hipMemset(c->d_wt, 0, sizeof(float) * (size_t)c->n_t * ldc));
+        HIPCHK(hipMemset(c->d_wt, 0, sizeof(double) * (size_t)c->n_t * ldc));
         if ((rc = dalloc(&c->d_bpart, (size_t)cap * nnt))) return rc;
         if ((rc = dalloc(&c->d_bpgb, (size_t)cap * nnt))) return rc;
         if ((rc = dalloc(&c->d_bth, (size_t)cap * NR_NTHETA))) return rc;
@@ -421,7 +421,7 @@ int ensure_batch(nr_ctx* c, int n_pts, bool grad, size_t mu_elems) {
     }
     if (grad && !c->b_grad) {
         if ((rc = dalloc(&c->d_bat, (size_t)c->ldr * c->b_ldw))) return rc;
-        HIPCHK(hipMemset(c->d_bat, 0, sizeof(float) * (size_t)c->ldr * c->b_ldw));
+        HIPCHK(hipMemset(c->d_bat, 0, sizeof(double) * (size_t)c->ldr * c->b_ldw));
         if ((rc = dalloc(&c->d_bu, (size_t)c->b_cap * c->n_t))) return rc;
         c->b_grad = true;
         moved = true;
@@ -860,7 +860,11 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
         (rc = dalloc(&c->d_part, nu * nr::kRowsPerBlock)) ||
         (rc = dalloc(&c->d_basis, (size_t)nr::kNBasis * n_t)))
         return rc;
-    HIPCHK(hipMemcpy(c->d_E, c->hE.data(), sizeof(double) * c->n_nodes, hipMemcpyHostToDevice));
+    {
+        std::vector<double> ie(c->n_nodes);
+        for (int j = 0; j < c->n_nodes; ++j) ie[j] = 1.0 / c->hE[j];
+        HIPCHK(hipMemcpy(c->d_E, ie.data(), sizeof(double) * c->n_nodes, hipMemcpyHostToDevice));
+    }
     HIPCHK(hipMemcpy(c->d_W, c->hW.data(), sizeof(double) * c->n_nodes, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_Pe, c->hPe.data(), sizeof(double) * c->n_nodes, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_tc, c->tc.data(), sizeof(double) * n_t, hipMemcpyHostToDevice));

@@ -14,15 +14,16 @@ struct WgenArgs {
     const double* ssm;    // [n_t]
     const double* mrow;   // [n_t]
     Phys ph;
-    float* wt;            // [n_t][ldw]
+    double* wt;           // [n_t][ldw]
 };
 
 // One GEMM problem of the grouped launch (one dataset / analysis).
 // Forward: C[M=n_pts][N=n_reco] = A[M][K=n_t] B[K][N] with A given as its
 // transpose At[K][lda] (M contiguous) and B = R[K][ldb].
 // Adjoint: C[M][N=n_t] = A[M][K=n_reco] R^T with At[K][lda] and R[N][ldb].
+// A is FP64, R FP32 (widened on the way into LDS), products/sums FP64.
 struct GemmProb {
-    const float* At;
+    const double* At;
     const float* B;
     int lda, ldb, M, N, K;
     // forward epilogue
@@ -32,11 +33,11 @@ struct GemmProb {
     double* part;         // [M][n_nt] deviance partials
     double* part_gb;      // [M][n_nt] sum_j a_j b_j partials (with aout)
     int n_nt;
-    float* aout;          // [N][lda_out] d(-2lnL)/d mu, or null
+    double* aout;         // [N][lda_out] d(-2lnL)/d mu, or null
     int lda_out;
     double* mu;           // [M][N] or null
     // adjoint output
-    float* C;
+    double* C;
     int ldc;
     int pad;
 };
@@ -56,7 +57,7 @@ struct FinalArgs {
 };
 
 struct ContractArgs {
-    const float* U;  // [n_pts][ldu]
+    const double* U; // [n_pts][ldu]
     int ldu, n_t, n_pts, n_nt;
     const double* ssm;
     const double* mrow;

@@ -1,8 +1,11 @@
 // Batched path on gfx950: many parameter points (and many datasets of
 // uneven binning) at once.  The per-point weights turn the fold into a dense
 // GEMM  mu[p][j] = f_bkg b_j + sum_l W[p][l] R[l][j]  (Eq. (matrix_reweight)
-// applied to a batch), run on FP32 MFMA (v_mfma_f32_32x32x2_f32) in one
+// applied to a batch), run on the matrix cores in one
 // persistent grouped launch with a fused Poisson epilogue (Eq. (logL)).
+// The products and sums are FP64 (v_mfma_f64_16x16x4_f64): with FP32
+// matrix cores the -2lnL of prior-box corner points drifts by ~1.3e-3 from
+// the FP64 reference, above the 1e-3 budget.
 #include "batched.h"
 
 #include <cmath>
@@ -11,7 +14,6 @@ namespace nr {
 
 namespace {
 
-typedef float v16f __attribute__((ext_vector_type(16)));
 
 __device__ inline double wave_sum64(double v) {
 #pragma unroll
@@ -77,7 +79,7 @@ __device__ inline void basis_dcoef(const double* th, const Phys& ph,
 
 // ------------------------------------------------------------ weights
 // W^T[l][p] = m_l * w_l(theta_p) with w_l = S_theta(T_l) / S_SM(T_l) and
-// S_theta(T_l) = sum_b c_b(theta_p) I_b(T_l) (FP64), stored as FP32 in the
+// S_theta(T_l) = sum_b c_b(theta_p) I_b(T_l) (FP64), stored in the
 // K-major layout the GEMM streams.  One thread per point, a strip of rows
 // per work-group row; the basis row is wave-uniform.
 constexpr int kWgenRows = 32;
@@ -103,29 +105,37 @@ __global__ __launch_bounds__(256) void k_wgen(WgenArgs a) {
             s = fma(c[b], a.basis[(size_t)b * a.n_t + l], s);
         const double ssm = a.ssm[l];
         const double w = ssm > 0.0 ? s / ssm : 1.0;
-        a.wt[(size_t)l * a.ldw + p] = ok ? (float)(a.mrow[l] * w) : 0.f;
+        a.wt[(size_t)l * a.ldw + p] = ok ? a.mrow[l] * w : 0.0;
     }
 }
 
 // --------------------------------------------------------------- GEMM
+// Tiles of 128 x 128 outputs, K-steps of 16; four waves in 2 x 2, each
+// 64 x 64 = 4 x 4 blocks of v_mfma_f64_16x16x4_f64.  R stays FP32 in HBM
+// and is widened to FP64 when staged into LDS.
 constexpr int BM = 128, BN = 128, BK = 16;
-constexpr int kGemmThreads = 256;  // 4 waves, 2 x 2, each 64 x 64
-constexpr int LDA_S = BM + 4;      // LDS row stride (floats)
-constexpr int LDB_S = BN + 4;
+constexpr int kGemmThreads = 256;
+constexpr int LDS_S = BM + 2;      // LDS row stride (doubles)
+constexpr int EPI_S = 65;          // epilogue staging row stride (doubles)
+
+typedef double v4d __attribute__((ext_vector_type(4)));
 
 template <int MODE>
 __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
                                                        const GemmTile* tiles,
                                                        int n_tiles,
                                                        unsigned* ctr) {
-    __shared__ float As[BK][LDA_S];
-    __shared__ float Bs[BK][LDB_S];
-    __shared__ float Cs[BM / 2][BN + 1];
+    // As[BK][LDS_S] then Bs[BK][LDS_S]; reused by the epilogue staging
+    __shared__ double smem[2 * BK * LDS_S];
+    __shared__ double rowred[BM][2];
+    __shared__ double rowred2[BM][2];
     __shared__ int s_tile;
+    double (*As)[LDS_S] = reinterpret_cast<double (*)[LDS_S]>(smem);
+    double (*Bs)[LDS_S] = reinterpret_cast<double (*)[LDS_S]>(smem + BK * LDS_S);
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
-    const int li = lane & 31, lk = lane >> 5;
+    const int li = lane & 15, lk = lane >> 4;
 
     for (;;) {
         if (tid == 0) s_tile = (int)atomicAdd(&ctr[0], 1u);
@@ -138,55 +148,56 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
         const int m0 = tl.mt * BM, n0 = tl.nt * BN;
         const int K = pr.K;
 
-        v16f acc[2][2];
+        v4d acc[4][4];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+            for (int j = 0; j < 4; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-        float4 ra[2], rb[2];
+        double2 ra[4];
+        float4 rb[2];
         auto gload = [&](int k0) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {  // A^T: BK x BM doubles, M contiguous
+                const int q = tid + i * kGemmThreads;  // 0..1023
+                const int kk = q >> 6, c2 = q & 63;
+                const int k = k0 + kk, m = m0 + 2 * c2;
+                ra[i] = (k < K && m < pr.lda)
+                            ? *reinterpret_cast<const double2*>(pr.At + (size_t)k * pr.lda + m)
+                            : make_double2(0.0, 0.0);
+            }
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int q = tid + i * kGemmThreads;  // 0..511
-                {   // A^T tile: BK rows x BM floats, M contiguous
-                    const int kk = q >> 5, c4 = q & 31;
-                    const int k = k0 + kk, m = m0 + 4 * c4;
-                    ra[i] = (k < K && m < pr.lda)
-                                ? *reinterpret_cast<const float4*>(
-                                      pr.At + (size_t)k * pr.lda + m)
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-                if (MODE != kModeAdj) {  // B[k][n], N contiguous
+                if (MODE != kModeAdj) {  // B[k][n] = R[k][n], N contiguous
                     const int kk = q >> 5, c4 = q & 31;
                     const int k = k0 + kk, n = n0 + 4 * c4;
                     rb[i] = (k < K && n < pr.ldb)
-                                ? *reinterpret_cast<const float4*>(
-                                      pr.B + (size_t)k * pr.ldb + n)
+                                ? *reinterpret_cast<const float4*>(pr.B + (size_t)k * pr.ldb + n)
                                 : make_float4(0.f, 0.f, 0.f, 0.f);
                 } else {  // B[k][n] = R[n][k], K contiguous
                     const int nn = q >> 2, k4 = q & 3;
                     const int n = n0 + nn, k = k0 + 4 * k4;
                     rb[i] = (n < pr.N && k < pr.ldb)
-                                ? *reinterpret_cast<const float4*>(
-                                      pr.B + (size_t)n * pr.ldb + k)
+                                ? *reinterpret_cast<const float4*>(pr.B + (size_t)n * pr.ldb + k)
                                 : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
             }
         };
         auto sstore = [&]() {
 #pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int q = tid + i * kGemmThreads;
+                const int kk = q >> 6, c2 = q & 63;
+                *reinterpret_cast<double2*>(&As[kk][2 * c2]) = ra[i];
+            }
+#pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int q = tid + i * kGemmThreads;
-                {
-                    const int kk = q >> 5, c4 = q & 31;
-                    *reinterpret_cast<float4*>(&As[kk][4 * c4]) = ra[i];
-                }
                 if (MODE != kModeAdj) {
                     const int kk = q >> 5, c4 = q & 31;
-                    *reinterpret_cast<float4*>(&Bs[kk][4 * c4]) = rb[i];
+                    double* d = &Bs[kk][4 * c4];
+                    d[0] = rb[i].x; d[1] = rb[i].y; d[2] = rb[i].z; d[3] = rb[i].w;
                 } else {
                     const int nn = q >> 2, k4 = q & 3;
                     Bs[4 * k4 + 0][nn] = rb[i].x;
@@ -204,59 +215,59 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
             __syncthreads();
             if (k0 + BK < K) gload(k0 + BK);
 #pragma unroll
-            for (int kk = 0; kk < BK; kk += 2) {
-                const float a0 = As[kk + lk][wm * 64 + li];
-                const float a1 = As[kk + lk][wm * 64 + 32 + li];
-                const float b0 = Bs[kk + lk][wn * 64 + li];
-                const float b1 = Bs[kk + lk][wn * 64 + 32 + li];
-                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+            for (int kk = 0; kk < BK; kk += 4) {
+                double a[4], b[4];
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    a[x] = As[kk + lk][wm * 64 + x * 16 + li];
+                    b[x] = Bs[kk + lk][wn * 64 + x * 16 + li];
+                }
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+                        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
             }
         }
 
-        // ---- epilogue.  Output element (i, j) of a 32x32 block sits in
-        // lane j + 32 * ((i / 4) % 2), register (i / 8) * 4 + i % 4.
+        // ---- epilogue.  Output (i, j) of a 16x16 block sits in lane
+        // j + 16 * (i % 4), register i / 4.
         if (MODE == kModeAdj) {
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
+            for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
+                for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int i = wm * 64 + bi * 32 + (r >> 2) * 8 + lk * 4 + (r & 3);
-                        const int j = wn * 64 + bj * 32 + li;
-                        const int p = m0 + i, col = n0 + j;
+                    for (int r = 0; r < 4; ++r) {
+                        const int p = m0 + wm * 64 + bi * 16 + lk + 4 * r;
+                        const int col = n0 + wn * 64 + bj * 16 + li;
                         if (p < pr.M && col < pr.N)
                             pr.C[(size_t)p * pr.ldc + col] = acc[bi][bj][r];
                     }
         } else {
-            // Accumulators go through LDS one 64-row half at a time; four
-            // threads share a row and walk 32 columns each.
+            // one 16-row strip of each wave at a time through LDS; four lanes
+            // share a row and take 16 of the wave's 64 columns each
+            double* stage = smem + wave * 16 * EPI_S;
 #pragma unroll
-            for (int bi = 0; bi < 2; ++bi) {
+            for (int bi = 0; bi < 4; ++bi) {
                 __syncthreads();
 #pragma unroll
-                for (int bj = 0; bj < 2; ++bj)
+                for (int bj = 0; bj < 4; ++bj)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
-                        const int il = wm * 32 + (r >> 2) * 8 + lk * 4 + (r & 3);
-                        Cs[il][wn * 64 + bj * 32 + li] = acc[bi][bj][r];
-                    }
+                    for (int r = 0; r < 4; ++r)
+                        stage[(lk + 4 * r) * EPI_S + bj * 16 + li] = acc[bi][bj][r];
                 __syncthreads();
-                const int il = tid >> 2, cq = tid & 3;
-                const int i = (il >> 5) * 64 + bi * 32 + (il & 31);
+                const int r16 = lane >> 2, cs = lane & 3;
+                const int i = wm * 64 + bi * 16 + r16;
                 const int p = m0 + i;
                 double dsum = 0.0, gsum = 0.0;
                 if (p < pr.M) {
                     const double fb = pr.theta[(size_t)p * kNTheta + 6];
-                    for (int q = 0; q < 32; ++q) {
-                        const int j = cq * 32 + q;
-                        const int col = n0 + j;
+                    for (int q = 0; q < 16; ++q) {
+                        const int col = n0 + wn * 64 + cs * 16 + q;
                         if (col >= pr.N) break;
                         const double bj_ = pr.b[col];
-                        const double mu = fb * bj_ + (double)Cs[il][j];
+                        const double mu = fb * bj_ + stage[r16 * EPI_S + cs * 16 + q];
                         const double nj = pr.n[col];
                         double d;
                         if (nj > 0.0)
@@ -267,7 +278,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
                         if (pr.mu) pr.mu[(size_t)p * pr.N + col] = mu;
                         if (pr.aout) {
                             const double aj = 2.0 * (1.0 - nj / mu);
-                            pr.aout[(size_t)col * pr.lda_out + p] = (float)aj;
+                            pr.aout[(size_t)col * pr.lda_out + p] = aj;
                             gsum += aj * bj_;
                         }
                     }
@@ -276,9 +287,18 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
                 dsum += __shfl_xor(dsum, 2, 64);
                 gsum += __shfl_xor(gsum, 1, 64);
                 gsum += __shfl_xor(gsum, 2, 64);
-                if (cq == 0 && p < pr.M) {
-                    pr.part[(size_t)p * pr.n_nt + tl.nt] = dsum;
-                    if (pr.aout) pr.part_gb[(size_t)p * pr.n_nt + tl.nt] = gsum;
+                if (cs == 0) {
+                    rowred[i][wn] = dsum;
+                    rowred2[i][wn] = gsum;
+                }
+            }
+            __syncthreads();
+            if (tid < BM) {
+                const int p = m0 + tid;
+                if (p < pr.M) {
+                    pr.part[(size_t)p * pr.n_nt + tl.nt] = rowred[tid][0] + rowred[tid][1];
+                    if (pr.aout)
+                        pr.part_gb[(size_t)p * pr.n_nt + tl.nt] = rowred2[tid][0] + rowred2[tid][1];
                 }
             }
         }
@@ -323,7 +343,7 @@ __global__ __launch_bounds__(256) void k_adj_contract(ContractArgs a) {
     for (int l = tid; l < a.n_t; l += 256) {
         const double ssm = a.ssm[l];
         if (!(ssm > 0.0)) continue;
-        const double u = (double)a.U[(size_t)p * a.ldu + l] * (a.mrow[l] / ssm);
+        const double u = a.U[(size_t)p * a.ldu + l] * (a.mrow[l] / ssm);
 #pragma unroll
         for (int b = 0; b < kNBasis; ++b) J[b] = fma(u, a.basis[(size_t)b * a.n_t + l], J[b]);
     }

@@ -38,7 +38,7 @@ struct EUnit {
 struct EintArgs {
     const EUnit* units;
     int n_units;
-    const double* nodeE;
+    const double* nodeIE;  // 1 / E_j
     const double* nodeW;
     const double* nodePe;
     const int* srcGroup;

@@ -32,7 +32,7 @@ struct NodeCoef {
 // Eq. (sm_cross_section) with the couplings of Eq. (xs_nsi) plus the
 // magnetic term of Eq. (xs_mm), Eq. (xs_total), written as a Laurent
 // polynomial in T:  a0 + a1 T + a2 T^2 + am / T  (weak prefactor = 1).
-__device__ inline NodeCoef node_coef(double E, double nu, double pe,
+__device__ inline NodeCoef node_coef(double iE, double nu, double pe,
                                      const double* th, const Phys& ph) {
     const double Pe = pe;
     const double Pm = (1.0 - pe) * (1.0 - ph.tau_frac);
@@ -43,7 +43,6 @@ __device__ inline NodeCoef node_coef(double E, double nu, double pe,
     const double A = Pe * gle * gle + Pm * glm * glm + Pt * glt * glt;
     const double B = Pe * gre * gre + Pm * grm * grm + Pt * grt * grt;
     const double C = Pe * gle * gre + Pm * glm * grm + Pt * glt * grt;
-    const double iE = 1.0 / E;
     const double mm = ph.cmm * th[4] * (Pe + Pm + Pt);
     NodeCoef c;
     c.a0 = nu * (A + B - mm * iE);
@@ -73,7 +72,7 @@ __global__ __launch_bounds__(256) void k_eint(EintArgs a) {
     const double f = a.srcGroup[un.src] ? th[5] : 1.0;
     if (lane < un.cnt) {
         const int j = un.j0 + lane;
-        NodeCoef c = node_coef(a.nodeE[j], a.nodeW[j] * f, a.nodePe[j], th,
+        NodeCoef c = node_coef(a.nodeIE[j], a.nodeW[j] * f, a.nodePe[j], th,
                                a.ph);
         cs[wave][lane] = make_double4(c.a0, c.a1, c.a2, c.am);
     }
@@ -125,33 +124,19 @@ constexpr int kFoldCols = 256;             // 64 lanes x float4
 constexpr int kFoldUnroll = 8;
 constexpr int kFoldMaxRows = 2048;
 
-__device__ inline double block_sum_512(double v, double* sh) {
-    v = wave_sum(v);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kFoldWaves; ++w) s += sh[w];
-    return s;  // valid in thread 0
-}
 
-// Weights (Eqs. (fT_norm), (reweight_factor)), fold through the response
-// (Eqs. (Rij), (fNp_reweight), (mu_total)) and the Poisson likelihood
-// (Eq. (logL)).  Work-group (rb, cc) streams rows [rb*rows, +rows) and
-// columns [cc*256, +256) of R with 16-byte loads; the per-row weights sit
-// in LDS.  Partial column sums go to colpart; the last work-group of every
-// column chunk (atomic arrival counter) adds the row-block partials in a
-// fixed order, forms mu_j and the deviance terms, and the last chunk
-// finisher sums the chunks and writes -2lnL.  Deterministic: no float
-// atomics.
+// Weights (Eqs. (fT_norm), (reweight_factor)) and the fold through the
+// response (Eqs. (Rij), (fNp_reweight), (mu_total)).  Work-group (rb, cc)
+// streams rows [rb*rows, +rows) and columns [cc*256, +256) of R with 16-byte
+// streaming loads, eight rows in flight per wave; the per-row
+// weights sit in LDS.  R is FP32 in HBM; products and sums are FP64, which
+// the full-rate FP64 vector units of gfx950 absorb at no cost to this
+// bandwidth-bound loop.  The work-group writes its column partial sums; no
+// cross-work-group synchronisation happens here (the partial sums are read
+// by the next kernel).
 __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
     __shared__ double vs[kFoldMaxRows];
-    __shared__ double4 red[kFoldWaves][64];
-    __shared__ double dred[kFoldWaves];
-    __shared__ double dred2[kFoldWaves];
-    __shared__ int s_last;
+    __shared__ double red[kFoldWaves][kFoldCols + 1];
     const int rb = blockIdx.x, cc = blockIdx.y;
     const int row0 = rb * a.rows_per_wg;
     int nrows = a.n_t - row0;
@@ -159,7 +144,6 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
 
-    // weights for this work-group's rows (FP64, kept in LDS)
     for (int r = tid; r < nrows; r += kFoldThreads) {
         const int l = row0 + r;
         const int blk = l / kRowsPerBlock, ln = l % kRowsPerBlock;
@@ -173,25 +157,22 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
     }
     __syncthreads();
 
-    // Stream the row block.  R is FP32 in HBM; the products and sums are
-    // formed in FP64, which the full-rate FP64 vector units of gfx950 absorb
-    // at no cost to this bandwidth-bound loop.
     const int ld4 = a.ldr >> 2;
     const int c4 = cc * 64 + lane;
     const bool colok = c4 < ld4;
     const float4* __restrict__ Rp =
         reinterpret_cast<const float4*>(a.R) + (size_t)row0 * ld4 + c4;
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    constexpr int U = kFoldUnroll;
     if (colok) {
         int r = wave;
-        for (; r + kFoldWaves * (kFoldUnroll - 1) < nrows;
-             r += kFoldWaves * kFoldUnroll) {
-            float4 x[kFoldUnroll];
+        for (; r + kFoldWaves * (U - 1) < nrows; r += kFoldWaves * U) {
+            float4 x[U];
 #pragma unroll
-            for (int q = 0; q < kFoldUnroll; ++q)
+            for (int q = 0; q < U; ++q)
                 x[q] = ld_stream(Rp + (size_t)(r + q * kFoldWaves) * ld4);
 #pragma unroll
-            for (int q = 0; q < kFoldUnroll; ++q) {
+            for (int q = 0; q < U; ++q) {
                 const double v = vs[r + q * kFoldWaves];
                 acc0 = fma((double)x[q].x, v, acc0);
                 acc1 = fma((double)x[q].y, v, acc1);
@@ -200,80 +181,111 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
             }
         }
         for (; r < nrows; r += kFoldWaves) {
-            const float4 x = ld_stream(Rp + (size_t)r * ld4);
+            const float4 z = ld_stream(Rp + (size_t)r * ld4);
             const double v = vs[r];
-            acc0 = fma((double)x.x, v, acc0);
-            acc1 = fma((double)x.y, v, acc1);
-            acc2 = fma((double)x.z, v, acc2);
-            acc3 = fma((double)x.w, v, acc3);
+            acc0 = fma((double)z.x, v, acc0);
+            acc1 = fma((double)z.y, v, acc1);
+            acc2 = fma((double)z.z, v, acc2);
+            acc3 = fma((double)z.w, v, acc3);
         }
     }
-    red[wave][lane] = make_double4(acc0, acc1, acc2, acc3);
+    red[wave][4 * lane + 0] = acc0;
+    red[wave][4 * lane + 1] = acc1;
+    red[wave][4 * lane + 2] = acc2;
+    red[wave][4 * lane + 3] = acc3;
     __syncthreads();
     if (tid < kFoldCols) {
         const int col = cc * kFoldCols + tid;
         if (col < a.ldr) {
             double s = 0.0;
-            const int k = tid & 3;
-            for (int w = 0; w < kFoldWaves; ++w) {
-                const double4 q = red[w][tid >> 2];
-                s += k == 0 ? q.x : k == 1 ? q.y : k == 2 ? q.z : q.w;
-            }
+            for (int w = 0; w < kFoldWaves; ++w) s += red[w][tid];
             a.colpart[(size_t)rb * a.ldr + col] = s;
         }
     }
-    __threadfence();
+}
+
+// Poisson likelihood (Eq. (logL)) from the fold partials.  Work-group cc
+// owns 256 columns; four threads per column add the row-block partials in a
+// fixed order, then mu_j, the deviance mu - n + n ln(n/mu) and
+// a_j = d(-2lnL)/d mu_j.  The chunk sums meet in the last work-group
+// (arrival counter; only the writing wave fences), which adds the data
+// constant and the pulls.  Deterministic: no float atomics.
+constexpr int kFinThreads = 1024;
+
+__global__ __launch_bounds__(kFinThreads) void k_fold_finish(FoldArgs a) {
+    __shared__ double ps[4][kFoldCols];
+    __shared__ double dred[kFinThreads / 64];
+    __shared__ double gred[kFinThreads / 64];
+    __shared__ int s_last;
+    const int cc = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int ci = tid & (kFoldCols - 1), qd = tid >> 8;
+    const int col = cc * kFoldCols + ci;
+    double s = 0.0;
+    if (col < a.n_reco) {
+        int q = qd;
+        for (; q + 12 < a.n_rb; q += 16) {
+            const double v0 = a.colpart[(size_t)q * a.ldr + col];
+            const double v1 = a.colpart[(size_t)(q + 4) * a.ldr + col];
+            const double v2 = a.colpart[(size_t)(q + 8) * a.ldr + col];
+            const double v3 = a.colpart[(size_t)(q + 12) * a.ldr + col];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; q < a.n_rb; q += 4) s += a.colpart[(size_t)q * a.ldr + col];
+    }
+    ps[qd][ci] = s;
     __syncthreads();
-    if (tid == 0) {
-        const unsigned prev = atomicAdd(&a.ctr[cc], 1u);
-        s_last = prev == (unsigned)(a.n_rb - 1);
+    double dev = 0.0, gb = 0.0;
+    if (qd == 0 && col < a.n_reco) {
+        const double fold = ps[0][ci] + ps[1][ci] + ps[2][ci] + ps[3][ci];
+        const double bj = a.b[col];
+        const double mu = fold + a.theta[6] * bj;
+        const double nj = a.n[col];
+        if (a.out_mu) a.out_mu[col] = mu;
+        if (nj > 0.0)
+            dev = mu > 0.0 ? (mu - nj + nj * log(nj / mu)) : INFINITY;
+        else
+            dev = mu;
+        const double aj = 2.0 * (1.0 - nj / mu);
+        if (a.out_a) a.out_a[col] = aj;
+        gb = aj * bj;
+    } else if (qd == 0 && col < a.ldr && a.out_a) {
+        a.out_a[col] = 0.0;
+    }
+    dev = wave_sum(dev);
+    gb = wave_sum(gb);
+    if (lane == 0) {
+        dred[wave] = dev;
+        gred[wave] = gb;
     }
     __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-
-    // last work-group of column chunk cc: mu_j and deviance terms
-    double dev = 0.0, gb = 0.0;
-    if (tid < kFoldCols) {
-        const int col = cc * kFoldCols + tid;
-        if (col < a.n_reco) {
-            double s = 0.0;
-            for (int q = 0; q < a.n_rb; ++q)
-                s += __builtin_nontemporal_load(&a.colpart[(size_t)q * a.ldr + col]);
-            const double bj = a.b[col];
-            const double mu = s + a.theta[6] * bj;
-            const double nj = a.n[col];
-            if (a.out_mu) a.out_mu[col] = mu;
-            if (nj > 0.0) {
-                dev = mu > 0.0 ? (mu - nj + nj * log(nj / mu)) : INFINITY;
-            } else {
-                dev = mu;
+    if (wave == 0) {
+        double d = 0.0, g = 0.0;
+        if (lane == 0) {
+            for (int w = 0; w < kFinThreads / 64; ++w) {
+                d += dred[w];
+                g += gred[w];
             }
-            const double aj = 2.0 * (1.0 - nj / mu);
-            if (a.out_a) a.out_a[col] = aj;
-            gb = aj * bj;
-        } else if (col < a.ldr && a.out_a) {
-            a.out_a[col] = 0.0;
+            a.chunk_dev[cc] = d;
+            a.chunk_gb[cc] = g;
+        }
+        __threadfence();
+        if (lane == 0) {
+            const unsigned prev = atomicAdd(&a.ctr[0], 1u);
+            s_last = prev == (unsigned)(a.n_cc - 1);
         }
     }
-    const double dsum = block_sum_512(dev, dred);
-    const double gsum = block_sum_512(gb, dred2);
-    if (tid == 0) {
-        a.chunk_dev[cc] = dsum;
-        a.chunk_gb[cc] = gsum;
-        a.ctr[cc] = 0u;
-        __threadfence();
-        const unsigned prev = atomicAdd(&a.ctr[a.n_cc], 1u);
-        s_last = prev == (unsigned)(a.n_cc - 1);
-    }
     __syncthreads();
-    if (!s_last) return;
-    if (tid == 0) {
-        __threadfence();
+    if (!s_last || wave != 0) return;
+    __threadfence();
+    if (lane == 0) {
         double d = 0.0, g = 0.0;
         for (int q = 0; q < a.n_cc; ++q) {
-            d += __builtin_nontemporal_load(&a.chunk_dev[q]);
-            g += __builtin_nontemporal_load(&a.chunk_gb[q]);
+            d += a.chunk_dev[q];
+            g += a.chunk_gb[q];
         }
         double pulls = 0.0;
         for (int i = 0; i < kNTheta; ++i)
@@ -283,7 +295,7 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
             }
         a.out_nll[0] = 2.0 * d + 2.0 * a.cdata + pulls;
         if (a.out_gb) a.out_gb[0] = g;
-        a.ctr[a.n_cc] = 0u;
+        a.ctr[0] = 0u;
     }
 }
 
@@ -337,7 +349,6 @@ __device__ inline void basis_dcoef(const double* th, const Phys& ph,
 __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
     __shared__ double as[kAdjMaxLd];
     __shared__ double jsh[kAdjThreads / 64][kNBasis];
-    __shared__ int s_last;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ld4 = a.ldr >> 2;
     const bool lds = a.ldr <= kAdjMaxLd;
@@ -370,20 +381,28 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
         for (int w = 0; w < kAdjThreads / 64; ++w) s += jsh[w][tid];
         a.jpart[(size_t)blockIdx.x * kNBasis + tid] = s;
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) {
-        const unsigned prev = atomicAdd(a.ctr, 1u);
-        s_last = prev == gridDim.x - 1;
+}
+
+// Sum of the per-work-group basis contractions (fixed order) and the
+// gradient: grad_i = sum_b dc_ib(theta) J_b + [i = f_bkg] sum_j a_j b_j +
+// the pull term.
+constexpr int kAdjGroups = 12;
+
+__global__ __launch_bounds__(256) void k_adjoint_finish(AdjArgs a, int grid) {
+    __shared__ double jsh[kAdjGroups][kNBasis];
+    __shared__ double jt[kNBasis];
+    const int tid = threadIdx.x;
+    if (tid < kAdjGroups * kNBasis) {
+        const int b = tid % kNBasis, g = tid / kNBasis;
+        double s = 0.0;
+        for (int q = g; q < grid; q += kAdjGroups) s += a.jpart[(size_t)q * kNBasis + b];
+        jsh[g][b] = s;
     }
     __syncthreads();
-    if (!s_last) return;
-    __threadfence();
     if (tid < kNBasis) {
         double s = 0.0;
-        for (unsigned g = 0; g < gridDim.x; ++g)
-            s += __builtin_nontemporal_load(&a.jpart[(size_t)g * kNBasis + tid]);
-        jsh[0][tid] = s;
+        for (int g = 0; g < kAdjGroups; ++g) s += jsh[g][tid];
+        jt[tid] = s;
     }
     __syncthreads();
     if (tid == 0) {
@@ -393,14 +412,13 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
         basis_dcoef(th, a.ph, dc);
         for (int i = 0; i < kNTheta; ++i) {
             double g = 0.0;
-            for (int b = 0; b < kNBasis; ++b) g += dc[i][b] * jsh[0][b];
+            for (int b = 0; b < kNBasis; ++b) g += dc[i][b] * jt[b];
             if (i == 6) g += a.gb[0];
             if (a.pull_sigma[i] > 0.0)
                 g += 2.0 * (th[i] - a.pull_mean[i]) /
                      (a.pull_sigma[i] * a.pull_sigma[i]);
             a.out_grad[i] = g;
         }
-        a.ctr[0] = 0u;
     }
 }
 
@@ -424,6 +442,9 @@ hipError_t launch_fold(const FoldArgs& a, hipStream_t s) {
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fold, dim3(a.n_rb, a.n_cc), dim3(kFoldThreads), 0, s,
                        a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_fold_finish, dim3(a.n_cc), dim3(kFinThreads), 0, s, a);
     return hipGetLastError();
 }
 
@@ -436,6 +457,9 @@ int adjoint_grid(int n_t) {
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t s) {
     hipLaunchKernelGGL(k_adjoint, dim3(grid), dim3(kAdjThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adjoint_finish, dim3(1), dim3(256), 0, s, a, grid);
     return hipGetLastError();
 }
 

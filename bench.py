@@ -49,6 +49,50 @@ def build_plain(cfg_id=1):
     return dict(cfg=c, seeds=s, src=src, R=rsp.R, b=b, n=n, ctx=ctx)
 
 
+def build_batched(n_datasets=64):
+    """The uneven-binning scan: 64 analyses, 16 shape classes."""
+    import synth
+    import paper_2607_00488_amd as nr
+    t0 = time.time()
+    ctxs, ths, flops = [], [], 0.0
+    src = synth.source_nodes(256)
+    for sd in synth.batched_schedule(n_datasets):
+        rsp = synth.response_mc(sd["n_t"], sd["n_reco"], sd["n_mc"],
+                                seed=sd["seed_response"], keep_counts=False)
+        b = np.full(sd["n_reco"], 10.0)
+        ctx = nr.Context(0)
+        ctx.set_sources(src, sd["n_t"])
+        ctx.set_response(rsp.R, n_sig=1.0e4)
+        ctx.set_data(b, b)
+        mu_sm = ctx.eval_mu(synth.theta_sm())[0]
+        ctx.set_data(synth.poisson_data(mu_sm, sd["seed_data"]), b)
+        ctxs.append(ctx)
+        ths.append(synth.theta_grid_scan(sd["n_pts"], sd["seed_theta"]))
+        flops += 2.0 * sd["n_pts"] * sd["n_t"] * sd["n_reco"]
+    log(f"[bench] batched inputs ({n_datasets} datasets) in {time.time() - t0:.1f}s")
+    return ctxs, ths, flops
+
+
+def time_batched(ctxs, ths, reps=3, grad=False):
+    import torch
+    import paper_2607_00488_amd as nr
+    dev = torch.device("cuda:0")
+    tt = [torch.tensor(t, dtype=torch.float64, device=dev) for t in ths]
+    nl = [torch.empty(len(t), dtype=torch.float64, device=dev) for t in ths]
+    gr = ([torch.empty(len(t), 7, dtype=torch.float64, device=dev) for t in ths]
+          if grad else None)
+    s = torch.cuda.Stream(device=dev)
+    nr.eval_nll_multi_dev(ctxs, tt, nl, gr, stream=s)  # capture + run
+    s.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        nr.eval_nll_multi_dev(ctxs, tt, nl, gr, stream=s)
+    s.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    return dt, [x.cpu().numpy() for x in nl], (None if gr is None else
+                                                [g.cpu().numpy() for g in gr])
+
+
 def cpu_baseline(p, n_eval, gpu_ctx):
     """The FP64 oracle on the host cores for a bounded sample of points, and
     the GPU's -2lnL on the same inputs for the |Delta| column."""
@@ -83,6 +127,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-evals", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU "
@@ -126,7 +171,8 @@ def main():
 
     # roofline of the dominant kernel (fold + likelihood), HIP events on the
     # context stream around back-to-back launches
-    fold_ms = ctx.time_stage(2, 200)
+    fold_ms = ctx.time_stage(4, 200)
+    fold_lik_ms = ctx.time_stage(2, 200)
     eint_ms = ctx.time_stage(1, 200)
     alg_bytes = 4 * c.n_t * c.n_reco + 4 * c.n_t + 16 * c.n_reco
     achieved = alg_bytes / (fold_ms * 1e-3) / 1e9
@@ -147,7 +193,39 @@ def main():
                roofline=roof,
                detail=dict(sync_latency_ms_mean=round(float(lat.mean()), 4),
                            sync_latency_ms_std=round(float(lat.std()), 4),
-                           eint_kernel_us=round(eint_ms * 1e3, 2)))
+                           eint_weights_us=round(eint_ms * 1e3, 2),
+                           fold_plus_likelihood_us=round(fold_lik_ms * 1e3, 2)))
+    forms = {}
+    # gradient form: 1024 points at the same shapes, -2lnL + 7 derivatives
+    # per point through the FP64-MFMA forward and adjoint products
+    thg = synth.theta_prior(1024, p["seeds"]["theta"] + 5, f_range=(0.8, 1.2))
+    dtg, _, _ = time_batched([ctx], [thg], reps=3, grad=True)
+    forms["grad_batched"] = dict(
+        evals_per_s=round(1024 / dtg, 1), points=1024, ms=round(dtg * 1e3, 3),
+        flop=2 * 2.0 * 1024 * c.n_t * c.n_reco,
+        tflops=round(2 * 2.0 * 1024 * c.n_t * c.n_reco / dtg / 1e12, 2),
+        peak_tflops=78.6, what="nll + gradient, forward and adjoint GEMMs")
+    dtb, _, _ = time_batched([ctx], [thg], reps=3, grad=False)
+    forms["nll_batched_same_shapes"] = dict(
+        evals_per_s=round(1024 / dtb, 1), points=1024, ms=round(dtb * 1e3, 3),
+        tflops=round(2.0 * 1024 * c.n_t * c.n_reco / dtb / 1e12, 2))
+    log(f"[bench] grad batched: {1024 / dtg:.0f} evals/s; nll batched "
+        f"{1024 / dtb:.0f} evals/s")
+    if not args.no_batched:
+        ctxs, ths, flops = build_batched()
+        dt2, _, _ = time_batched(ctxs, ths, reps=2)
+        npts = sum(len(t) for t in ths)
+        forms["batched_scan_64_datasets"] = dict(
+            evals_per_s=round(npts / dt2, 1), points=npts,
+            ms=round(dt2 * 1e3, 3), flop=flops,
+            tflops=round(flops / dt2 / 1e12, 2), peak_tflops=78.6,
+            what="64 datasets, N_T 2048-16384, N_reco 512-4096, one grouped "
+                 "persistent FP64-MFMA launch per scan (graph replay)")
+        log(f"[bench] batched scan: {npts / dt2:.0f} evals/s, "
+            f"{flops / dt2 / 1e12:.1f} TFLOP/s")
+        for cx in ctxs:
+            cx.close()
+    res["forms"] = forms
     if not args.no_cpu_baseline:
         cb, dmax = cpu_baseline(p, args.cpu_evals, ctx)
         res["cpu_baseline"] = cb

@@ -172,15 +172,64 @@ int nr_get_reference(nr_ctx *ctx, double *s_sm, double *m);
  * work against it. */
 void *nr_stream(nr_ctx *ctx);
 
-/* Average device time in milliseconds of one kernel of the single-point
+/* Average device time in milliseconds of one stage of the single-point
  * path, launched `iters` times back to back on the context stream between
- * HIP events (stage 1: E-integral, 2: fold + likelihood, 3: adjoint).  The
- * last evaluated point's inputs are reused.  For roofline measurements. */
+ * HIP events (stage 1: E-integral + weights, 2: fold + likelihood,
+ * 3: adjoint, 4: the R-streaming fold kernel alone).  The last evaluated
+ * point's inputs are reused.  For roofline measurements. */
 int nr_time_stage(nr_ctx *ctx, int stage, int iters, double *avg_ms);
 
 /* Tuning knobs of the fold kernel (0 keeps the current value): rows per
  * work-group and column chunks; for sweeps. */
 int nr_set_fold_tiling(nr_ctx *ctx, int rows_per_wg, int use_graph);
+
+/* ---- Learned surrogate (not in the paper): an MLP theta -> log mu_j,
+ * 7 -> hidden -> hidden -> hidden -> n_out with SiLU activations, BF16
+ * weights and activations on the matrix cores, FP32 accumulation, FP32
+ * master weights and Adam moments.  The parameters are one flat FP32 vector:
+ * for each layer l, W_l^T as [n_out_l][k_l] rows with the bias in column
+ * n_in_l (the layer input carries a constant one there); k_0 = 32 (7 inputs,
+ * bias at 7), k_l = hidden + 8 (bias at hidden) for l > 0.  Inputs are
+ * mapped from the box [lo, hi] to [-1, 1]; outputs are standardised log mu
+ * (log mu_j = mean_j + std_j * y_j). */
+typedef struct nr_mlp nr_mlp;
+
+int nr_mlp_create(int device, int hidden, int n_out, nr_mlp **out);
+void nr_mlp_destroy(nr_mlp *mlp);
+long nr_mlp_num_params(nr_mlp *mlp);
+int nr_mlp_set_params(nr_mlp *mlp, const float *params, long n);
+int nr_mlp_get_params(nr_mlp *mlp, float *params, long n);
+/* Gradient of the last training step (same layout as the parameters). */
+int nr_mlp_get_grads(nr_mlp *mlp, float *grads, long n);
+int nr_mlp_set_box(nr_mlp *mlp, const double *lo, const double *hi);
+int nr_mlp_set_output_norm(nr_mlp *mlp, const float *mean, const float *std);
+
+/* Standardised log mu targets from expected spectra d_mu [P][n_out]
+ * (device, FP64) into d_t [P][n_out] (device, FP32). */
+int nr_mlp_targets_dev(nr_mlp *mlp, const double *d_mu, int P, float *d_t,
+                       void *stream);
+
+/* One Adam step on the mean squared error of the standardised log mu for a
+ * batch (B a multiple of 8): d_theta [B][7] FP64, d_t [B][n_out] FP32.
+ * *loss (host, may be NULL) receives the batch loss (synchronises). */
+int nr_mlp_train_step_dev(nr_mlp *mlp, const double *d_theta, const float *d_t,
+                          int B, float lr, double *loss, void *stream);
+
+/* Predicted log mu [B][n_out] (device FP32). */
+int nr_mlp_logmu_dev(nr_mlp *mlp, const double *d_theta, int B,
+                     float *d_logmu, void *stream);
+
+/* Surrogate -2lnL against ctx's data (Eq. (logL) with mu = exp of the
+ * prediction; the output layer, exp and the Poisson deviance are fused):
+ * d_nll [B] device FP64; d_outside [B] (device int, may be NULL) flags
+ * points outside the training box. */
+int nr_mlp_nll_dev(nr_mlp *mlp, nr_ctx *ctx, const double *d_theta, int B,
+                   double *d_nll, int *d_outside, void *stream);
+
+/* Expected spectra of the batched form on device pointers: d_theta
+ * [n_pts][7], d_mu [n_pts][n_reco] FP64 (training data for the surrogate). */
+int nr_eval_mu_batched_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
+                           double *d_mu, void *stream);
 
 /* Message for the last non-zero status on this thread. */
 const char *nr_last_error(void);

@@ -27,6 +27,10 @@ EXPORTS = (
     "nr_time_stage", "nr_set_fold_tiling", "nr_last_error",
     "nr_eval_nll_batched", "nr_eval_nll_grad_batched", "nr_eval_mu_batched",
     "nr_eval_nll_multi", "nr_eval_nll_multi_dev",
+    "nr_mlp_create", "nr_mlp_destroy", "nr_mlp_num_params", "nr_mlp_set_params",
+    "nr_mlp_get_params", "nr_mlp_get_grads", "nr_mlp_set_box",
+    "nr_mlp_set_output_norm", "nr_mlp_targets_dev", "nr_mlp_train_step_dev",
+    "nr_mlp_logmu_dev", "nr_mlp_nll_dev", "nr_eval_mu_batched_dev",
 )
 
 
@@ -99,9 +103,26 @@ def load():
     L.nr_eval_nll_multi_dev.argtypes = [C.POINTER(P), I, C.POINTER(P),
                                         C.POINTER(I), C.POINTER(P),
                                         C.POINTER(P), P]
+    pF = C.POINTER(C.c_float)
+    L.nr_mlp_create.argtypes = [I, I, I, C.POINTER(P)]
+    L.nr_mlp_destroy.argtypes = [P]
+    L.nr_mlp_destroy.restype = None
+    L.nr_mlp_num_params.argtypes = [P]
+    L.nr_mlp_num_params.restype = C.c_long
+    L.nr_mlp_set_params.argtypes = [P, pF, C.c_long]
+    L.nr_mlp_get_params.argtypes = [P, pF, C.c_long]
+    L.nr_mlp_get_grads.argtypes = [P, pF, C.c_long]
+    L.nr_mlp_set_box.argtypes = [P, pD, pD]
+    L.nr_mlp_set_output_norm.argtypes = [P, pF, pF]
+    L.nr_mlp_targets_dev.argtypes = [P, P, I, P, P]
+    L.nr_mlp_train_step_dev.argtypes = [P, P, P, I, C.c_float, pD, P]
+    L.nr_mlp_logmu_dev.argtypes = [P, P, I, P, P]
+    L.nr_mlp_nll_dev.argtypes = [P, P, P, I, P, P, P]
+    L.nr_eval_mu_batched_dev.argtypes = [P, P, I, P, P]
     for name in EXPORTS:
         fn = getattr(L, name)
-        if name not in ("nr_destroy", "nr_stream", "nr_last_error"):
+        if name not in ("nr_destroy", "nr_stream", "nr_last_error",
+                        "nr_mlp_destroy", "nr_mlp_num_params"):
             fn.restype = C.c_int
     _lib = L
     return L
@@ -274,6 +295,86 @@ def nr_eval_nll_multi_dev(handles, theta_ptrs, n_pts, nll_ptrs,
     GR = None if grad_ptrs is None else (C.c_void_p * n)(*grad_ptrs)
     _check(load().nr_eval_nll_multi_dev(H, n, TH, NP, OUT, GR,
                                         C.c_void_p(stream_ptr or 0)))
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def nr_mlp_create(device, hidden, n_out):
+    h = C.c_void_p()
+    _check(load().nr_mlp_create(int(device), int(hidden), int(n_out),
+                                C.byref(h)))
+    return h
+
+
+def nr_mlp_destroy(h):
+    load().nr_mlp_destroy(h)
+
+
+def nr_mlp_num_params(h):
+    return int(load().nr_mlp_num_params(h))
+
+
+def nr_mlp_set_params(h, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(load().nr_mlp_set_params(h, _fp(p), p.size))
+
+
+def nr_mlp_get_params(h):
+    p = np.empty(nr_mlp_num_params(h), dtype=np.float32)
+    _check(load().nr_mlp_get_params(h, _fp(p), p.size))
+    return p
+
+
+def nr_mlp_get_grads(h):
+    p = np.empty(nr_mlp_num_params(h), dtype=np.float32)
+    _check(load().nr_mlp_get_grads(h, _fp(p), p.size))
+    return p
+
+
+def nr_mlp_set_box(h, lo, hi):
+    lo, hi = _f64(lo), _f64(hi)
+    _check(load().nr_mlp_set_box(h, _dp(lo), _dp(hi)))
+
+
+def nr_mlp_set_output_norm(h, mean, std):
+    m = np.ascontiguousarray(mean, dtype=np.float32)
+    s_ = np.ascontiguousarray(std, dtype=np.float32)
+    _check(load().nr_mlp_set_output_norm(h, _fp(m), _fp(s_)))
+
+
+def nr_mlp_targets_dev(h, d_mu, P, d_t, stream=None):
+    _check(load().nr_mlp_targets_dev(h, C.c_void_p(d_mu), int(P),
+                                     C.c_void_p(d_t), C.c_void_p(stream or 0)))
+
+
+def nr_mlp_train_step_dev(h, d_theta, d_t, B, lr, want_loss=False,
+                          stream=None):
+    loss = C.c_double(float("nan"))
+    _check(load().nr_mlp_train_step_dev(
+        h, C.c_void_p(d_theta), C.c_void_p(d_t), int(B), float(lr),
+        C.byref(loss) if want_loss else None, C.c_void_p(stream or 0)))
+    return loss.value
+
+
+def nr_mlp_logmu_dev(h, d_theta, B, d_logmu, stream=None):
+    _check(load().nr_mlp_logmu_dev(h, C.c_void_p(d_theta), int(B),
+                                   C.c_void_p(d_logmu),
+                                   C.c_void_p(stream or 0)))
+
+
+def nr_mlp_nll_dev(h, ctx_h, d_theta, B, d_nll, d_outside=None, stream=None):
+    _check(load().nr_mlp_nll_dev(h, ctx_h, C.c_void_p(d_theta), int(B),
+                                 C.c_void_p(d_nll),
+                                 C.c_void_p(d_outside or 0),
+                                 C.c_void_p(stream or 0)))
+
+
+def nr_eval_mu_batched_dev(ctx_h, d_theta, n_pts, d_mu, stream=None):
+    _check(load().nr_eval_mu_batched_dev(ctx_h, C.c_void_p(d_theta),
+                                         int(n_pts), C.c_void_p(d_mu),
+                                         C.c_void_p(stream or 0)))
 
 
 def nr_last_error():

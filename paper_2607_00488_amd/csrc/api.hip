@@ -2,6 +2,7 @@
 // paragraph and Sec. III.B: the SM reference and the response are built once
 // and kept resident), stream-ordered launches, HIP-graph replay, errors.
 #include "batched.h"
+#include "mlp.h"
 #include "../../include/nureweight.h"
 
 #include <algorithm>
@@ -84,6 +85,16 @@ struct BatchPlan {
 struct nr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
+    // second stream: the E-integral and weights of the next point run there
+    // while the fold of the current point streams R
+    hipStream_t stream2 = nullptr;
+    // third stream: the likelihood reduction of point p overlaps the fold of
+    // point p + 1 (fold partial sums double-buffered by parity)
+    hipStream_t stream3 = nullptr;
+    hipEvent_t ev_w[2] = {nullptr, nullptr}, ev_f[2] = {nullptr, nullptr};
+    hipEvent_t ev_fin[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    double* d_v[2] = {nullptr, nullptr};  // [n_t] fold vectors, by parity
     nr::Phys ph{};
     // sources and grid
     bool have_src = false, have_rsp = false, have_data = false;
@@ -112,7 +123,8 @@ struct nr_ctx {
     double pull_mean[NR_NTHETA] = {0}, pull_sigma[NR_NTHETA] = {0};
     // fold / adjoint scratch
     int rows_per_wg = 0, n_rb = 0, n_cc = 0, adj_grid = 0;
-    double *d_colpart = nullptr, *d_chunk_dev = nullptr, *d_chunk_gb = nullptr;
+    double *d_colpart = nullptr;  // [2][n_rb][ldr]
+    double *d_chunk_dev = nullptr, *d_chunk_gb = nullptr;
     unsigned* d_ctr = nullptr;  // [n_cc + 1] fold, [1] adjoint after that
     double* d_a = nullptr;
     double *d_gb = nullptr, *d_jpart = nullptr;
@@ -126,6 +138,7 @@ struct nr_ctx {
     std::map<GraphKey, hipGraphExec_t> graphs;
     // last launch arguments (for nr_time_stage)
     nr::EintArgs last_e{};
+    nr::WeightArgs last_w{};
     nr::FoldArgs last_f{};
     nr::AdjArgs last_a{};
     bool have_last = false, have_last_adj = false;
@@ -214,15 +227,20 @@ int choose_tiling(nr_ctx* c, int rows_req) {
     if (rows_req > 0) {
         rows = rows_req;
     } else {
-        int target_rb = std::max(1, 1024 / c->n_cc);
-        rows = (c->n_t + target_rb - 1) / target_rb;
-        rows = ((rows + 63) / 64) * 64;
+        // measured on MI355X at 16384 x 4096: 1024-row tiles (16 x 16
+        // work-groups) stream fastest and leave 16 partial rows per column
+        rows = 1024;
+        if (c->n_t < 16 * 1024) {
+            int target_rb = std::max(1, 256 / c->n_cc);
+            rows = (c->n_t + target_rb - 1) / target_rb;
+            rows = std::min(1024, ((rows + 63) / 64) * 64);
+        }
     }
     rows = std::max(8, std::min(rows, 2048));
     c->rows_per_wg = rows;
     c->n_rb = (c->n_t + rows - 1) / rows;
     int rc;
-    if ((rc = dalloc(&c->d_colpart, (size_t)c->n_rb * c->ldr))) return rc;
+    if ((rc = dalloc(&c->d_colpart, (size_t)2 * c->n_rb * c->ldr))) return rc;
     if ((rc = dalloc(&c->d_chunk_dev, (size_t)c->n_cc))) return rc;
     if ((rc = dalloc(&c->d_chunk_gb, (size_t)c->n_cc))) return rc;
     if ((rc = dalloc(&c->d_ctr, (size_t)c->n_cc + 2))) return rc;
@@ -272,81 +290,105 @@ nr::EintArgs eint_args(nr_ctx* c, const double* d_theta) {
     return a;
 }
 
-// One single-point evaluation: a1 (E-integral), a2-a5 (weights, fold,
-// likelihood) and, with a gradient, the adjoint pass.
-int enqueue_point(nr_ctx* c, const double* th, double* nll, double* grad,
-                  double* mu, double* w, hipStream_t s) {
-    nr::EintArgs ea = eint_args(c, th);
-    HIPCHK(nr::launch_eint(ea, s));
-    nr::FoldArgs fa{};
-    fa.R = c->d_R;
-    fa.ldr = c->ldr;
-    fa.n_t = c->n_t;
-    fa.n_reco = c->n_reco;
-    fa.part = c->d_part;
-    fa.ustart = c->d_ustart;
-    fa.ssm = c->d_ssm;
-    fa.mrow = c->d_mrow;
-    fa.n = c->d_n;
-    fa.b = c->d_b;
-    fa.theta = th;
-    fa.colpart = c->d_colpart;
-    fa.ctr = c->d_ctr;
-    fa.chunk_dev = c->d_chunk_dev;
-    fa.chunk_gb = c->d_chunk_gb;
-    fa.out_nll = nll;
-    fa.out_mu = mu;
-    fa.out_a = grad ? c->d_a : nullptr;
-    fa.out_gb = grad ? c->d_gb : nullptr;
-    fa.out_w = w;
-    fa.cdata = c->cdata;
-    for (int i = 0; i < NR_NTHETA; ++i) {
-        fa.pull_mean[i] = c->pull_mean[i];
-        fa.pull_sigma[i] = c->pull_sigma[i];
-    }
-    fa.rows_per_wg = c->rows_per_wg;
-    fa.n_rb = c->n_rb;
-    fa.n_cc = c->n_cc;
-    HIPCHK(nr::launch_fold(fa, s));
-    c->last_e = ea;
-    c->last_f = fa;
-    c->have_last = true;
-    if (grad) {
-        nr::AdjArgs aa{};
-        aa.R = c->d_R;
-        aa.ldr = c->ldr;
-        aa.n_t = c->n_t;
-        aa.n_reco = c->n_reco;
-        aa.a = c->d_a;
-        aa.ssm = c->d_ssm;
-        aa.mrow = c->d_mrow;
-        aa.basis = c->d_basis;
-        aa.theta = th;
-        aa.gb = c->d_gb;
-        aa.jpart = c->d_jpart;
-        aa.ctr = c->d_ctr + c->n_cc + 1;
-        aa.out_grad = grad;
-        for (int i = 0; i < NR_NTHETA; ++i) {
-            aa.pull_mean[i] = c->pull_mean[i];
-            aa.pull_sigma[i] = c->pull_sigma[i];
-        }
-        aa.ph = c->ph;
-        HIPCHK(nr::launch_adjoint(aa, c->adj_grid, s));
-        c->last_a = aa;
-        c->have_last_adj = true;
-    }
-    return 0;
-}
-
+// Single-point evaluations of a list of points, software-pipelined over
+// three streams: a1 (E-integral) and a2 (weights) of point p run on the
+// second stream, the R-streaming fold (a3) of point p on the main stream,
+// and the likelihood reduction (a4, a5) of point p on the third stream
+// while the fold of point p + 1 streams.  Weight vectors and fold partial
+// sums are double-buffered by parity; with a gradient, the adjoint pass of
+// point p follows its likelihood on the main stream.
 int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
                    double* grad, double* mu, double* w, hipStream_t s) {
+    hipStream_t s2 = c->stream2, s3 = c->stream3;
+    HIPCHK(hipEventRecord(c->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(s2, c->ev_fork, 0));
+    HIPCHK(hipStreamWaitEvent(s3, c->ev_fork, 0));
+    const size_t cp_stride = (size_t)c->n_rb * c->ldr;
     for (int p = 0; p < n_pts; ++p) {
-        int rc = enqueue_point(c, th + (size_t)p * NR_NTHETA, nll ? nll + p : nullptr,
-                               grad ? grad + (size_t)p * NR_NTHETA : nullptr,
-                               mu ? mu + (size_t)p * c->n_reco : nullptr,
-                               w ? w + (size_t)p * c->n_t : nullptr, s);
-        if (rc) return rc;
+        const double* thp = th + (size_t)p * NR_NTHETA;
+        const int par = p & 1;
+        // a1, a2 on the second stream
+        nr::EintArgs ea = eint_args(c, thp);
+        HIPCHK(nr::launch_eint(ea, s2));
+        if (p >= 2) HIPCHK(hipStreamWaitEvent(s2, c->ev_f[par], 0));
+        nr::WeightArgs wa{};
+        wa.part = c->d_part;
+        wa.ustart = c->d_ustart;
+        wa.ssm = c->d_ssm;
+        wa.mrow = c->d_mrow;
+        wa.n_t = c->n_t;
+        wa.v = c->d_v[par];
+        wa.out_w = w ? w + (size_t)p * c->n_t : nullptr;
+        HIPCHK(nr::launch_weights(wa, s2));
+        HIPCHK(hipEventRecord(c->ev_w[par], s2));
+        // a3 on the main stream
+        HIPCHK(hipStreamWaitEvent(s, c->ev_w[par], 0));
+        if (p >= 2) HIPCHK(hipStreamWaitEvent(s, c->ev_fin[par], 0));
+        nr::FoldArgs fa{};
+        fa.R = c->d_R;
+        fa.ldr = c->ldr;
+        fa.n_t = c->n_t;
+        fa.n_reco = c->n_reco;
+        fa.v = c->d_v[par];
+        fa.n = c->d_n;
+        fa.b = c->d_b;
+        fa.theta = thp;
+        fa.colpart = c->d_colpart + par * cp_stride;
+        fa.ctr = c->d_ctr;
+        fa.chunk_dev = c->d_chunk_dev;
+        fa.chunk_gb = c->d_chunk_gb;
+        fa.out_nll = nll + p;
+        fa.out_mu = mu ? mu + (size_t)p * c->n_reco : nullptr;
+        fa.out_a = grad ? c->d_a : nullptr;
+        fa.out_gb = grad ? c->d_gb : nullptr;
+        fa.cdata = c->cdata;
+        for (int i = 0; i < NR_NTHETA; ++i) {
+            fa.pull_mean[i] = c->pull_mean[i];
+            fa.pull_sigma[i] = c->pull_sigma[i];
+        }
+        fa.rows_per_wg = c->rows_per_wg;
+        fa.n_rb = c->n_rb;
+        fa.n_cc = c->n_cc;
+        HIPCHK(nr::launch_fold_stream(fa, s));
+        HIPCHK(hipEventRecord(c->ev_f[par], s));
+        // a4, a5 on the third stream
+        HIPCHK(hipStreamWaitEvent(s3, c->ev_f[par], 0));
+        HIPCHK(nr::launch_fold_finish(fa, s3));
+        HIPCHK(hipEventRecord(c->ev_fin[par], s3));
+        c->last_e = ea;
+        c->last_w = wa;
+        c->last_f = fa;
+        c->have_last = true;
+        if (grad) {
+            HIPCHK(hipStreamWaitEvent(s, c->ev_fin[par], 0));
+            nr::AdjArgs aa{};
+            aa.R = c->d_R;
+            aa.ldr = c->ldr;
+            aa.n_t = c->n_t;
+            aa.n_reco = c->n_reco;
+            aa.a = c->d_a;
+            aa.ssm = c->d_ssm;
+            aa.mrow = c->d_mrow;
+            aa.basis = c->d_basis;
+            aa.theta = thp;
+            aa.gb = c->d_gb;
+            aa.jpart = c->d_jpart;
+            aa.ctr = c->d_ctr + c->n_cc + 1;
+            aa.out_grad = grad + (size_t)p * NR_NTHETA;
+            for (int i = 0; i < NR_NTHETA; ++i) {
+                aa.pull_mean[i] = c->pull_mean[i];
+                aa.pull_sigma[i] = c->pull_sigma[i];
+            }
+            aa.ph = c->ph;
+            HIPCHK(nr::launch_adjoint(aa, c->adj_grid, s));
+            c->last_a = aa;
+            c->have_last_adj = true;
+        }
     }
+    HIPCHK(hipEventRecord(c->ev_join, s2));
+    HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
+    HIPCHK(hipEventRecord(c->ev_join, s3));
+    HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
     return 0;
 }
 
@@ -688,6 +730,15 @@ int nr_create(int device, nr_ctx** out) {
     c->device = device;
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream3, hipStreamNonBlocking);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        e = hipEventCreateWithFlags(&c->ev_w[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_f[i], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fin[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     if (e != hipSuccess) {
         delete c;
         return fail(NR_EHIP, "stream creation: %s", hipGetErrorString(e));
@@ -721,6 +772,18 @@ void nr_destroy(nr_ctx* c) {
     dfree(&c->d_wt); dfree(&c->d_bpart); dfree(&c->d_bpgb); dfree(&c->d_bat);
     dfree(&c->d_bu); dfree(&c->d_bth); dfree(&c->d_bnll); dfree(&c->d_bgrad);
     dfree(&c->d_bmu); dfree(&c->d_gctr);
+    dfree(&c->d_v[0]); dfree(&c->d_v[1]);
+    for (int i = 0; i < 2; ++i) {
+        if (c->ev_w[i]) (void)hipEventDestroy(c->ev_w[i]);
+        if (c->ev_f[i]) (void)hipEventDestroy(c->ev_f[i]);
+        if (c->ev_fin[i]) (void)hipEventDestroy(c->ev_fin[i]);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    (void)hipStreamSynchronize(c->stream2);
+    (void)hipStreamSynchronize(c->stream3);
+    (void)hipStreamDestroy(c->stream2);
+    (void)hipStreamDestroy(c->stream3);
     (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -858,7 +921,8 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
         (rc = dalloc(&c->d_ustart, c->n_blocks + 1)) ||
         (rc = dalloc(&c->d_units, nu)) ||
         (rc = dalloc(&c->d_part, nu * nr::kRowsPerBlock)) ||
-        (rc = dalloc(&c->d_basis, (size_t)nr::kNBasis * n_t)))
+        (rc = dalloc(&c->d_basis, (size_t)nr::kNBasis * n_t)) ||
+        (rc = dalloc(&c->d_v[0], n_t)) || (rc = dalloc(&c->d_v[1], n_t)))
         return rc;
     {
         std::vector<double> ie(c->n_nodes);
@@ -1060,7 +1124,7 @@ int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
     if (!c || !avg_ms || iters <= 0) return fail(NR_EINVAL, "bad argument");
     if (!c->have_last || (stage == 3 && !c->have_last_adj))
         return fail(NR_ESTATE, "no previous evaluation to time");
-    if (stage < 1 || stage > 3) return fail(NR_EINVAL, "stage must be 1, 2 or 3");
+    if (stage < 1 || stage > 4) return fail(NR_EINVAL, "stage must be 1, 2, 3 or 4");
     int rc;
     if ((rc = set_device(c))) return rc;
     hipEvent_t e0, e1;
@@ -1068,9 +1132,13 @@ int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, c->stream));
     for (int i = 0; i < iters; ++i) {
-        if (stage == 1) HIPCHK(nr::launch_eint(c->last_e, c->stream));
+        if (stage == 1) {
+            HIPCHK(nr::launch_eint(c->last_e, c->stream));
+            HIPCHK(nr::launch_weights(c->last_w, c->stream));
+        }
         if (stage == 2) HIPCHK(nr::launch_fold(c->last_f, c->stream));
         if (stage == 3) HIPCHK(nr::launch_adjoint(c->last_a, c->adj_grid, c->stream));
+        if (stage == 4) HIPCHK(nr::launch_fold_stream(c->last_f, c->stream));
     }
     HIPCHK(hipEventRecord(e1, c->stream));
     HIPCHK(hipEventSynchronize(e1));
@@ -1148,6 +1216,371 @@ int nr_eval_nll_multi(nr_ctx* const* ctx, int n_ctx, const double* const* theta,
                               hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return 0;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- surrogate
+struct nr_mlp {
+    int device = 0;
+    int H = 256, n_out = 0, cap = 0, n_layers = 4;
+    int kp[4] = {32, 0, 0, 0};  // padded input width of each layer
+    int nn[4] = {0, 0, 0, 0};   // outputs of each layer
+    long off[5] = {0, 0, 0, 0, 0};
+    long n_params = 0;
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    nr::bf16* w16 = nullptr;
+    nr::bf16 *x = nullptr, *h[3] = {nullptr, nullptr, nullptr};
+    float* z[3] = {nullptr, nullptr, nullptr};
+    nr::bf16 *dy = nullptr, *dz[2] = {nullptr, nullptr};
+    double* tile_loss = nullptr;
+    double* part = nullptr;
+    int* outside = nullptr;
+    float *mean = nullptr, *stdv = nullptr;
+    double lo[NR_NTHETA] = {-0.5, -0.5, -0.5, -0.5, 0.0, 0.8, 0.8};
+    double hi[NR_NTHETA] = {0.5, 0.5, 0.5, 0.5, 25.0, 1.2, 1.2};
+    long step = 0;
+    int train_cap = 0;
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+int mlp_alloc_batch(nr_mlp* q, int B, bool train) {
+    int rc;
+    if (B > q->cap) {
+        const int cap = (B + 127) / 128 * 128;
+        if ((rc = dalloc(&q->x, (size_t)cap * 32))) return rc;
+        for (int l = 0; l < 3; ++l) {
+            if ((rc = dalloc(&q->h[l], (size_t)cap * (q->H + 8)))) return rc;
+            if ((rc = dalloc(&q->z[l], (size_t)cap * q->H))) return rc;
+            HIPCHK(nr::launch_fill_ones_col(q->h[l], cap, q->H + 8, q->H, q->stream));
+        }
+        const int nnt = (q->n_out + 127) / 128;
+        if ((rc = dalloc(&q->part, (size_t)cap * nnt))) return rc;
+        if ((rc = dalloc(&q->outside, (size_t)cap))) return rc;
+        q->cap = cap;
+        q->train_cap = 0;
+    }
+    if (train && B > q->train_cap) {
+        const int cap = q->cap;
+        if ((rc = dalloc(&q->dy, (size_t)cap * q->n_out))) return rc;
+        if ((rc = dalloc(&q->dz[0], (size_t)cap * q->H))) return rc;
+        if ((rc = dalloc(&q->dz[1], (size_t)cap * q->H))) return rc;
+        const int tiles = (cap / 128) * ((q->n_out + 127) / 128);
+        if ((rc = dalloc(&q->tile_loss, (size_t)tiles))) return rc;
+        q->train_cap = cap;
+    }
+    return 0;
+}
+
+nr::MlpGemm mg(const nr::bf16* A, long sam, long sak, const nr::bf16* B,
+               long sbk, long sbn, int M, int N, int K) {
+    nr::MlpGemm g{};
+    g.A = A; g.sam = sam; g.sak = sak;
+    g.B = B; g.sbk = sbk; g.sbn = sbn;
+    g.M = M; g.N = N; g.K = K;
+    return g;
+}
+
+// Forward through the three hidden layers: Z_l = H_{l-1} W_l (bias in the
+// ones column), H_l = SiLU(Z_l).
+int mlp_hidden_forward(nr_mlp* q, int B, hipStream_t s) {
+    const int H = q->H, ldh = H + 8;
+    for (int l = 0; l < 3; ++l) {
+        const nr::bf16* in = l == 0 ? q->x : q->h[l - 1];
+        const int kin = l == 0 ? 32 : ldh;
+        nr::MlpGemm g = mg(in, kin, 1, q->w16 + q->off[l], 1, q->kp[l], B, H, q->kp[l]);
+        g.C32 = q->z[l];
+        g.ldc = H;
+        g.C16 = q->h[l];
+        g.ldc16 = ldh;
+        HIPCHK(nr::launch_mlp_gemm(nr::kMlpSilu, g, s));
+    }
+    return 0;
+}
+
+int mlp_input(nr_mlp* q, const double* th, int B, hipStream_t s) {
+    nr::MlpInput in{};
+    in.theta = th;
+    in.B = B;
+    for (int i = 0; i < NR_NTHETA; ++i) {
+        in.lo[i] = q->lo[i];
+        in.hi[i] = q->hi[i];
+    }
+    in.x = q->x;
+    in.outside = q->outside;
+    HIPCHK(nr::launch_mlp_input(in, s));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int nr_mlp_create(int device, int hidden, int n_out, nr_mlp** out) {
+    if (!out || hidden <= 0 || hidden % 8 || n_out <= 0 || n_out % 8)
+        return fail(NR_EINVAL, "hidden and n_out must be positive multiples of 8");
+    *out = nullptr;
+    nr_mlp* q = new (std::nothrow) nr_mlp();
+    if (!q) return fail(NR_ENOMEM, "mlp allocation");
+    q->device = device;
+    q->H = hidden;
+    q->n_out = n_out;
+    q->kp[0] = 32;
+    q->kp[1] = q->kp[2] = q->kp[3] = hidden + 8;
+    q->nn[0] = q->nn[1] = q->nn[2] = hidden;
+    q->nn[3] = n_out;
+    q->off[0] = 0;
+    for (int l = 0; l < 4; ++l) q->off[l + 1] = q->off[l] + (long)q->nn[l] * q->kp[l];
+    q->n_params = q->off[4];
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete q;
+        return fail(NR_EHIP, "mlp stream: %s", hipGetErrorString(e));
+    }
+    int rc;
+    if ((rc = dalloc(&q->w, q->n_params)) || (rc = dalloc(&q->g, q->n_params)) ||
+        (rc = dalloc(&q->m, q->n_params)) || (rc = dalloc(&q->v, q->n_params)) ||
+        (rc = dalloc(&q->w16, q->n_params)) || (rc = dalloc(&q->mean, n_out)) ||
+        (rc = dalloc(&q->stdv, n_out))) {
+        delete q;
+        return rc;
+    }
+    (void)hipMemset(q->w, 0, sizeof(float) * q->n_params);
+    (void)hipMemset(q->w16, 0, sizeof(nr::bf16) * q->n_params);
+    (void)hipMemset(q->m, 0, sizeof(float) * q->n_params);
+    (void)hipMemset(q->v, 0, sizeof(float) * q->n_params);
+    *out = q;
+    return 0;
+}
+
+void nr_mlp_destroy(nr_mlp* q) {
+    if (!q) return;
+    (void)hipSetDevice(q->device);
+    (void)hipStreamSynchronize(q->stream);
+    dfree(&q->w); dfree(&q->g); dfree(&q->m); dfree(&q->v); dfree(&q->w16);
+    dfree(&q->x); dfree(&q->dy); dfree(&q->dz[0]); dfree(&q->dz[1]);
+    for (int l = 0; l < 3; ++l) { dfree(&q->h[l]); dfree(&q->z[l]); }
+    dfree(&q->tile_loss); dfree(&q->part); dfree(&q->outside);
+    dfree(&q->mean); dfree(&q->stdv);
+    (void)hipStreamDestroy(q->stream);
+    delete q;
+}
+
+long nr_mlp_num_params(nr_mlp* q) { return q ? q->n_params : -1; }
+
+int nr_mlp_set_params(nr_mlp* q, const float* params, long n) {
+    if (!q || !params || n != q->n_params) return fail(NR_EINVAL, "expected %ld parameters", q ? q->n_params : -1L);
+    int rc;
+    if ((rc = dalloc(&q->g, q->n_params))) return rc;
+    HIPCHK(hipSetDevice(q->device));
+    std::vector<nr::bf16> h16(n);
+    for (long i = 0; i < n; ++i) h16[i] = (nr::bf16)params[i];
+    HIPCHK(hipMemcpy(q->w, params, sizeof(float) * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(q->w16, h16.data(), sizeof(nr::bf16) * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(q->m, 0, sizeof(float) * n));
+    HIPCHK(hipMemset(q->v, 0, sizeof(float) * n));
+    q->step = 0;
+    return 0;
+}
+
+int nr_mlp_get_params(nr_mlp* q, float* params, long n) {
+    if (!q || !params || n != q->n_params) return fail(NR_EINVAL, "expected %ld parameters", q ? q->n_params : -1L);
+    HIPCHK(hipSetDevice(q->device));
+    HIPCHK(hipStreamSynchronize(q->stream));
+    HIPCHK(hipMemcpy(params, q->w, sizeof(float) * n, hipMemcpyDeviceToHost));
+    return 0;
+}
+
+int nr_mlp_get_grads(nr_mlp* q, float* grads, long n) {
+    if (!q || !grads || n != q->n_params) return fail(NR_EINVAL, "expected %ld values", q ? q->n_params : -1L);
+    HIPCHK(hipSetDevice(q->device));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(grads, q->g, sizeof(float) * n, hipMemcpyDeviceToHost));
+    return 0;
+}
+
+int nr_mlp_set_box(nr_mlp* q, const double* lo, const double* hi) {
+    if (!q || !lo || !hi) return fail(NR_EINVAL, "null argument");
+    for (int i = 0; i < NR_NTHETA; ++i)
+        if (!(std::isfinite(lo[i]) && std::isfinite(hi[i]) && hi[i] > lo[i]))
+            return fail(NR_EINVAL, "box component %d must satisfy lo < hi", i);
+    for (int i = 0; i < NR_NTHETA; ++i) {
+        q->lo[i] = lo[i];
+        q->hi[i] = hi[i];
+    }
+    return 0;
+}
+
+int nr_mlp_set_output_norm(nr_mlp* q, const float* mean, const float* stdv) {
+    if (!q || !mean || !stdv) return fail(NR_EINVAL, "null argument");
+    for (int j = 0; j < q->n_out; ++j)
+        if (!(std::isfinite(mean[j]) && stdv[j] > 0)) return fail(NR_EINVAL, "bad output norm at %d", j);
+    HIPCHK(hipSetDevice(q->device));
+    HIPCHK(hipMemcpy(q->mean, mean, sizeof(float) * q->n_out, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(q->stdv, stdv, sizeof(float) * q->n_out, hipMemcpyHostToDevice));
+    return 0;
+}
+
+int nr_mlp_targets_dev(nr_mlp* q, const double* d_mu, int P, float* d_t, void* stream) {
+    if (!q || !d_mu || !d_t || P <= 0) return fail(NR_EINVAL, "bad argument");
+    HIPCHK(hipSetDevice(q->device));
+    nr::TargetArgs a{d_mu, P, q->n_out, q->mean, q->stdv, d_t};
+    HIPCHK(nr::launch_targets(a, stream ? (hipStream_t)stream : q->stream));
+    return 0;
+}
+
+int nr_mlp_train_step_dev(nr_mlp* q, const double* d_theta, const float* d_t,
+                          int B, float lr, double* loss, void* stream) {
+    if (!q || !d_theta || !d_t || B <= 0 || B % 8)
+        return fail(NR_EINVAL, "batch must be a positive multiple of 8");
+    HIPCHK(hipSetDevice(q->device));
+    int rc;
+    if ((rc = mlp_alloc_batch(q, B, true))) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : q->stream;
+    const int H = q->H, ldh = H + 8, N = q->n_out;
+    if ((rc = mlp_input(q, d_theta, B, s))) return rc;
+    if ((rc = mlp_hidden_forward(q, B, s))) return rc;
+    // output layer with the MSE gradient in the epilogue
+    nr::MlpGemm go = mg(q->h[2], ldh, 1, q->w16 + q->off[3], 1, ldh, B, N, ldh);
+    go.aux = d_t;
+    go.ldaux = N;
+    go.C16 = q->dy;
+    go.ldc16 = N;
+    go.scale = 1.0f / ((float)B * (float)N);
+    go.tile_loss = q->tile_loss;
+    HIPCHK(nr::launch_mlp_gemm(nr::kMlpMse, go, s));
+    // output layer weight gradient: G3^T = dY^T H2
+    {
+        nr::MlpGemm g = mg(q->dy, 1, N, q->h[2], ldh, 1, N, ldh, B);
+        g.C32 = q->g + q->off[3];
+        g.ldc = ldh;
+        HIPCHK(nr::launch_mlp_gemm(nr::kMlpStore32, g, s));
+    }
+    // back through the hidden layers
+    const nr::bf16* up = q->dy;   // gradient w.r.t. the next layer's output
+    int upw = N;                  // its width
+    for (int l = 2; l >= 0; --l) {
+        nr::bf16* dzl = q->dz[l & 1];
+        // dZ_l = (up W_{l+1}) * SiLU'(Z_l), with W_{l+1} = (W^T_{l+1})^T
+        nr::MlpGemm gd = mg(up, upw, 1, q->w16 + q->off[l + 1], ldh, 1, B, H, upw);
+        gd.aux = q->z[l];
+        gd.ldaux = H;
+        gd.C16 = dzl;
+        gd.ldc16 = H;
+        HIPCHK(nr::launch_mlp_gemm(nr::kMlpDSilu, gd, s));
+        // G_l^T = dZ_l^T H_{l-1}  (H_{-1} = x)
+        const nr::bf16* in = l == 0 ? q->x : q->h[l - 1];
+        const int kin = l == 0 ? 32 : ldh;
+        nr::MlpGemm gw = mg(dzl, 1, H, in, kin, 1, H, q->kp[l], B);
+        gw.C32 = q->g + q->off[l];
+        gw.ldc = q->kp[l];
+        HIPCHK(nr::launch_mlp_gemm(nr::kMlpStore32, gw, s));
+        up = dzl;
+        upw = H;
+    }
+    q->step += 1;
+    nr::AdamArgs ad{};
+    ad.w = q->w;
+    ad.w16 = q->w16;
+    ad.g = q->g;
+    ad.m = q->m;
+    ad.v = q->v;
+    ad.n = q->n_params;
+    ad.lr = lr;
+    ad.b1 = 0.9f;
+    ad.b2 = 0.999f;
+    ad.eps = 1e-8f;
+    ad.bc1 = 1.0f - powf(0.9f, (float)q->step);
+    ad.bc2 = 1.0f - powf(0.999f, (float)q->step);
+    HIPCHK(nr::launch_adam(ad, s));
+    if (loss) {
+        const int tiles = ((B + 127) / 128) * ((N + 127) / 128);
+        std::vector<double> tl(tiles);
+        HIPCHK(hipMemcpyAsync(tl.data(), q->tile_loss, sizeof(double) * tiles,
+                              hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        double t = 0;
+        for (double x : tl) t += x;
+        *loss = t / ((double)B * N);
+    }
+    return 0;
+}
+
+int nr_mlp_logmu_dev(nr_mlp* q, const double* d_theta, int B, float* d_logmu,
+                     void* stream) {
+    if (!q || !d_theta || !d_logmu || B <= 0 || B % 8)
+        return fail(NR_EINVAL, "batch must be a positive multiple of 8");
+    HIPCHK(hipSetDevice(q->device));
+    int rc;
+    if ((rc = mlp_alloc_batch(q, B, false))) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : q->stream;
+    const int ldh = q->H + 8;
+    if ((rc = mlp_input(q, d_theta, B, s))) return rc;
+    if ((rc = mlp_hidden_forward(q, B, s))) return rc;
+    nr::MlpGemm go = mg(q->h[2], ldh, 1, q->w16 + q->off[3], 1, ldh, B, q->n_out, ldh);
+    go.mean = q->mean;
+    go.stdv = q->stdv;
+    go.C32 = d_logmu;
+    go.ldc = q->n_out;
+    HIPCHK(nr::launch_mlp_gemm(nr::kMlpLogMu, go, s));
+    return 0;
+}
+
+int nr_mlp_nll_dev(nr_mlp* q, nr_ctx* c, const double* d_theta, int B,
+                   double* d_nll, int* d_outside, void* stream) {
+    int rc;
+    if (!q || !d_theta || !d_nll || B <= 0 || B % 8)
+        return fail(NR_EINVAL, "batch must be a positive multiple of 8");
+    if ((rc = check_ready(c))) return rc;
+    if (c->n_reco != q->n_out) return fail(NR_EINVAL, "surrogate outputs %d bins, data has %d", q->n_out, c->n_reco);
+    HIPCHK(hipSetDevice(q->device));
+    if ((rc = mlp_alloc_batch(q, B, false))) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : q->stream;
+    const int ldh = q->H + 8;
+    const int nnt = (q->n_out + 127) / 128;
+    if ((rc = mlp_input(q, d_theta, B, s))) return rc;
+    if ((rc = mlp_hidden_forward(q, B, s))) return rc;
+    nr::MlpGemm go = mg(q->h[2], ldh, 1, q->w16 + q->off[3], 1, ldh, B, q->n_out, ldh);
+    go.mean = q->mean;
+    go.stdv = q->stdv;
+    go.nobs = c->d_n;
+    go.part = q->part;
+    go.n_nt = nnt;
+    HIPCHK(nr::launch_mlp_gemm(nr::kMlpNll, go, s));
+    nr::FinalArgs f{};
+    f.part = q->part;
+    f.theta = d_theta;
+    f.n_pts = B;
+    f.n_nt = nnt;
+    f.cdata = c->cdata;
+    for (int i = 0; i < NR_NTHETA; ++i) {
+        f.pull_mean[i] = c->pull_mean[i];
+        f.pull_sigma[i] = c->pull_sigma[i];
+    }
+    f.nll = d_nll;
+    HIPCHK(nr::launch_finalize(f, s));
+    if (d_outside)
+        HIPCHK(hipMemcpyAsync(d_outside, q->outside, sizeof(int) * B, hipMemcpyDeviceToDevice, s));
+    return 0;
+}
+
+int nr_eval_mu_batched_dev(nr_ctx* c, const double* d_theta, int n_pts,
+                           double* d_mu, void* stream) {
+    int rc;
+    if ((rc = check_ready(c))) return rc;
+    if (!d_theta || !d_mu || n_pts <= 0) return fail(NR_EINVAL, "bad argument");
+    if ((rc = set_device(c))) return rc;
+    if ((rc = ensure_batch(c, n_pts, false, 0))) return rc;
+    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    nr_ctx* cs[1] = {c};
+    const double* ths[1] = {d_theta};
+    double* nls[1] = {c->d_bnll};
+    double* mus[1] = {d_mu};
+    MultiCall mc{cs, 1, ths, &n_pts, nls, nullptr, mus};
+    return run_multi(mc, s);
 }
 
 }  // extern "C"

@@ -50,14 +50,21 @@ struct EintArgs {
     double* part;         // [n_units][64]
 };
 
-struct FoldArgs {
-    const float* R;       // [n_t][ldr]
-    int ldr;              // leading dimension (floats), multiple of 4
-    int n_t, n_reco;
+struct WeightArgs {
     const double* part;   // E-integral partials
     const int* ustart;    // [n_blocks+1] first unit of each row block
     const double* ssm;    // [n_t] S_SM (device E-integral at theta_SM)
     const double* mrow;   // [n_t] row factors m_l
+    int n_t;
+    double* v;            // [n_t] m_l w_l
+    double* out_w;        // [n_t] or null: weights w_l
+};
+
+struct FoldArgs {
+    const float* R;       // [n_t][ldr]
+    int ldr;              // leading dimension (floats), multiple of 4
+    int n_t, n_reco;
+    const double* v;      // [n_t] m_l w_l
     const double* n;      // [n_reco]
     const double* b;      // [n_reco]
     const double* theta;  // device, 7 doubles
@@ -69,7 +76,6 @@ struct FoldArgs {
     double* out_mu;       // [n_reco] or null
     double* out_a;        // [ldr] or null: d(-2lnL)/d mu_j
     double* out_gb;       // [1] or null: sum_j a_j b_j
-    double* out_w;        // [n_t] or null: weights w_l
     double cdata;
     double pull_mean[kNTheta];
     double pull_sigma[kNTheta];
@@ -97,7 +103,10 @@ struct AdjArgs {
 hipError_t launch_eint(const EintArgs& a, hipStream_t s);
 hipError_t launch_spectrum_reduce(const double* part, const int* ustart,
                                   int n_t, double* out, hipStream_t s);
+hipError_t launch_weights(const WeightArgs& a, hipStream_t s);
 hipError_t launch_fold(const FoldArgs& a, hipStream_t s);
+hipError_t launch_fold_stream(const FoldArgs& a, hipStream_t s);
+hipError_t launch_fold_finish(const FoldArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t s);
 int adjoint_grid(int n_t);
 

@@ -1,0 +1,256 @@
+// Learned surrogate on gfx950: an MLP theta -> log mu_j whose forward,
+// backward and optimiser steps run on BF16 matrix cores
+// (v_mfma_f32_32x32x16_bf16) with FP32 accumulation.  Biases ride along as
+// an extra input column fixed to one, so every layer is one GEMM.
+#include "mlp.h"
+
+#include <cmath>
+
+namespace nr {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int TM = 128, TN = 128, TK = 32;
+constexpr int kMlpThreads = 256;
+constexpr int LDK = TK + 8;  // LDS row stride (bf16): rows stay 16-byte aligned
+
+__device__ inline float silu(float z) { return z / (1.f + __expf(-z)); }
+
+// Loads one 128 x 32 operand tile (rows = m or n, k contiguous in LDS).
+// kc: the operand is k-contiguous in memory (16-byte chunks along k);
+// otherwise it is row-contiguous and each 16-byte chunk scatters along k.
+__device__ inline void load_tile(const bf16* __restrict__ P, long s_row,
+                                 long s_k, int rows, int K, int r0, int k0,
+                                 uint4 reg[2]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int c = tid + i * kMlpThreads;  // 0..511 chunks of 8
+        int r, k;
+        if (s_k == 1) {
+            r = c >> 2;
+            k = (c & 3) * 8;
+        } else {
+            k = c >> 4;
+            r = (c & 15) * 8;
+        }
+        const int gr = r0 + r, gk = k0 + k;
+        const bool ok = gr < rows && gk < K;
+        reg[i] = ok ? *reinterpret_cast<const uint4*>(P + (long)gr * s_row + (long)gk * s_k)
+                    : make_uint4(0u, 0u, 0u, 0u);
+    }
+}
+
+__device__ inline void store_tile(bf16 (*S)[LDK], long s_k, const uint4 reg[2]) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int c = tid + i * kMlpThreads;
+        if (s_k == 1) {
+            const int r = c >> 2, k = (c & 3) * 8;
+            *reinterpret_cast<uint4*>(&S[r][k]) = reg[i];
+        } else {
+            const int k = c >> 4, r = (c & 15) * 8;
+            const bf16* v = reinterpret_cast<const bf16*>(&reg[i]);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) S[r + e][k] = v[e];
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kMlpThreads) void k_mlp_gemm(MlpGemm g) {
+    __shared__ bf16 As[TM][LDK];
+    __shared__ bf16 Bs[TN][LDK];
+    __shared__ double red[TM][2];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int li = lane & 31, lh = lane >> 5;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    // A tile rows are m (stride sam along m, sak along k); B tile rows are n
+    const long a_row = g.sam, a_k = g.sak;
+    const long b_row = g.sbn, b_k = g.sbk;
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+    uint4 ra[2], rb[2];
+    load_tile(g.A, a_row, a_k, g.M, g.K, m0, 0, ra);
+    load_tile(g.B, b_row, b_k, g.N, g.K, n0, 0, rb);
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+        __syncthreads();
+        store_tile(As, a_k, ra);
+        store_tile(Bs, b_k, rb);
+        __syncthreads();
+        if (k0 + TK < g.K) {
+            load_tile(g.A, a_row, a_k, g.M, g.K, m0, k0 + TK, ra);
+            load_tile(g.B, b_row, b_k, g.N, g.K, n0, k0 + TK, rb);
+        }
+#pragma unroll
+        for (int ks = 0; ks < TK; ks += 16) {
+            bf16x8 a[2], b[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                a[x] = *reinterpret_cast<const bf16x8*>(&As[wm * 64 + x * 32 + li][ks + 8 * lh]);
+                b[x] = *reinterpret_cast<const bf16x8*>(&Bs[wn * 64 + x * 32 + li][ks + 8 * lh]);
+            }
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[x], b[y], acc[x][y], 0, 0, 0);
+        }
+    }
+
+    // Output (i, j) of a 32x32 block: lane j + 32 * ((i / 4) % 2),
+    // register (i / 8) * 4 + i % 4.
+    double lsum = 0.0;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = wm * 64 + bi * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
+            const int m = m0 + i;
+            double rowpart = 0.0;
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                const int n = n0 + wn * 64 + bj * 32 + li;
+                if (m >= g.M || n >= g.N) continue;
+                const float v = acc[bi][bj][r];
+                if (MODE == kMlpStore32) {
+                    g.C32[(long)m * g.ldc + n] = v;
+                } else if (MODE == kMlpSilu) {
+                    g.C32[(long)m * g.ldc + n] = v;
+                    g.C16[(long)m * g.ldc16 + n] = (bf16)silu(v);
+                } else if (MODE == kMlpMse) {
+                    const float rr = v - g.aux[(long)m * g.ldaux + n];
+                    g.C16[(long)m * g.ldc16 + n] = (bf16)(g.scale * 2.f * rr);
+                    lsum += (double)rr * rr;
+                } else if (MODE == kMlpDSilu) {
+                    const float z = g.aux[(long)m * g.ldaux + n];
+                    const float sg = 1.f / (1.f + __expf(-z));
+                    g.C16[(long)m * g.ldc16 + n] = (bf16)(v * sg * (1.f + z * (1.f - sg)));
+                } else if (MODE == kMlpLogMu) {
+                    g.C32[(long)m * g.ldc + n] = g.mean[n] + g.stdv[n] * v;
+                } else if (MODE == kMlpNll) {
+                    const double mu = exp((double)g.mean[n] + (double)g.stdv[n] * (double)v);
+                    const double nj = g.nobs[n];
+                    rowpart += nj > 0.0 ? (mu - nj + nj * log(nj / mu)) : mu;
+                }
+            }
+            if (MODE == kMlpNll) {
+#pragma unroll
+                for (int o = 16; o > 0; o >>= 1) rowpart += __shfl_xor(rowpart, o, 64);
+                if (li == 0) red[i][wn] = rowpart;
+            }
+        }
+    }
+    if (MODE == kMlpNll) {
+        __syncthreads();
+        if (tid < TM && m0 + tid < g.M)
+            g.part[(long)(m0 + tid) * g.n_nt + blockIdx.x] = red[tid][0] + red[tid][1];
+    }
+    if (MODE == kMlpMse) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
+        if (lane == 0) red[wave][0] = lsum;
+        __syncthreads();
+        if (tid == 0)
+            g.tile_loss[blockIdx.y * gridDim.x + blockIdx.x] =
+                red[0][0] + red[1][0] + red[2][0] + red[3][0];
+    }
+}
+
+__global__ void k_mlp_input(MlpInput a) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.B) return;
+    bool out = false;
+    bf16* x = a.x + (long)p * 32;
+    for (int i = 0; i < kNTheta; ++i) {
+        const double t = a.theta[(long)p * kNTheta + i];
+        out = out || !(t >= a.lo[i] && t <= a.hi[i]);
+        x[i] = (bf16)(float)(2.0 * (t - a.lo[i]) / (a.hi[i] - a.lo[i]) - 1.0);
+    }
+    x[kNTheta] = (bf16)1.f;
+    for (int i = kNTheta + 1; i < 32; ++i) x[i] = (bf16)0.f;
+    if (a.outside) a.outside[p] = out ? 1 : 0;
+}
+
+__global__ void k_adam(AdamArgs a) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const float g = a.g[i];
+    const float m = a.b1 * a.m[i] + (1.f - a.b1) * g;
+    const float v = a.b2 * a.v[i] + (1.f - a.b2) * g * g;
+    a.m[i] = m;
+    a.v[i] = v;
+    const float w = a.w[i] - a.lr * (m / a.bc1) / (sqrtf(v / a.bc2) + a.eps);
+    a.w[i] = w;
+    a.w16[i] = (bf16)w;
+}
+
+__global__ void k_targets(TargetArgs a) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long)a.P * a.N) return;
+    const int n = (int)(i % a.N);
+    const double mu = a.mu[i];
+    const float lm = (float)log(mu > 1e-300 ? mu : 1e-300);
+    a.t[i] = (lm - a.mean[n]) / a.stdv[n];
+}
+
+__global__ void k_ones_col(bf16* h, int B, int ld, int col) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= B) return;
+    h[(long)p * ld + col] = (bf16)1.f;
+    for (int c = col + 1; c < ld; ++c) h[(long)p * ld + c] = (bf16)0.f;
+}
+
+}  // namespace
+
+hipError_t launch_mlp_gemm(int mode, const MlpGemm& g, hipStream_t s) {
+    if (g.M % 8 || g.N % 8 || g.K % 8 || (g.sak != 1 && g.sam != 1) ||
+        (g.sbk != 1 && g.sbn != 1))
+        return hipErrorInvalidValue;
+    dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
+    switch (mode) {
+        case kMlpStore32: hipLaunchKernelGGL(k_mlp_gemm<kMlpStore32>, grid, dim3(kMlpThreads), 0, s, g); break;
+        case kMlpSilu: hipLaunchKernelGGL(k_mlp_gemm<kMlpSilu>, grid, dim3(kMlpThreads), 0, s, g); break;
+        case kMlpMse: hipLaunchKernelGGL(k_mlp_gemm<kMlpMse>, grid, dim3(kMlpThreads), 0, s, g); break;
+        case kMlpDSilu: hipLaunchKernelGGL(k_mlp_gemm<kMlpDSilu>, grid, dim3(kMlpThreads), 0, s, g); break;
+        case kMlpNll: hipLaunchKernelGGL(k_mlp_gemm<kMlpNll>, grid, dim3(kMlpThreads), 0, s, g); break;
+        case kMlpLogMu: hipLaunchKernelGGL(k_mlp_gemm<kMlpLogMu>, grid, dim3(kMlpThreads), 0, s, g); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_input(const MlpInput& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_mlp_input, dim3((a.B + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_targets(const TargetArgs& a, hipStream_t s) {
+    const long n = (long)a.P * a.N;
+    hipLaunchKernelGGL(k_targets, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_ones_col(bf16* h, int B, int ld, int col, hipStream_t s) {
+    hipLaunchKernelGGL(k_ones_col, dim3((B + 255) / 256), dim3(256), 0, s, h, B, ld, col);
+    return hipGetLastError();
+}
+
+}  // namespace nr

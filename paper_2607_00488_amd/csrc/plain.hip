@@ -104,20 +104,68 @@ __global__ __launch_bounds__(256) void k_eint(EintArgs a) {
     a.part[(size_t)u * kRowsPerBlock + lane] = rowok ? acc : 0.0;
 }
 
-// Sum of the unit partials of each recoil row: S_theta(T_l).
-__global__ void k_spectrum_reduce(const double* __restrict__ part,
-                                  const int* __restrict__ ustart, int n_t,
-                                  double* __restrict__ out) {
-    const int l = blockIdx.x * blockDim.x + threadIdx.x;
-    if (l >= n_t) return;
-    const int blk = l / kRowsPerBlock, lane = l % kRowsPerBlock;
+// Sum of the unit partials of every recoil row of a 64-row block,
+// S_theta(T_l) = sum_u part[u][l].  Sixteen waves take every sixteenth unit
+// (four loads in flight each) and the per-wave sums are added in a fixed
+// order, so the result is bitwise reproducible and identical in both uses
+// below.
+constexpr int kRowSumThreads = 1024;
+constexpr int kRowSumWaves = kRowSumThreads / 64;
+
+__device__ inline double block_row_sum(const double* __restrict__ part,
+                                       const int* __restrict__ ustart,
+                                       int blk, double* sh) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int u0 = ustart[blk], u1 = ustart[blk + 1];
     double s = 0.0;
-    for (int u = ustart[blk]; u < ustart[blk + 1]; ++u)
-        s += part[(size_t)u * kRowsPerBlock + lane];
-    out[l] = s;
+    int u = u0 + wave;
+    for (; u + 3 * kRowSumWaves < u1; u += 4 * kRowSumWaves) {
+        const double p0 = part[(size_t)u * kRowsPerBlock + lane];
+        const double p1 = part[(size_t)(u + kRowSumWaves) * kRowsPerBlock + lane];
+        const double p2 = part[(size_t)(u + 2 * kRowSumWaves) * kRowsPerBlock + lane];
+        const double p3 = part[(size_t)(u + 3 * kRowSumWaves) * kRowsPerBlock + lane];
+        s += p0;
+        s += p1;
+        s += p2;
+        s += p3;
+    }
+    for (; u < u1; u += kRowSumWaves) s += part[(size_t)u * kRowsPerBlock + lane];
+    sh[wave * kRowsPerBlock + lane] = s;
+    __syncthreads();
+    double t = 0.0;
+    if (wave == 0)
+        for (int w = 0; w < kRowSumWaves; ++w) t += sh[w * kRowsPerBlock + lane];
+    return t;  // valid in wave 0
 }
 
-// ------------------------------------------------------------- a2 - a5
+__global__ __launch_bounds__(kRowSumThreads) void k_spectrum_reduce(
+    const double* __restrict__ part, const int* __restrict__ ustart, int n_t,
+    double* __restrict__ out) {
+    __shared__ double sh[kRowSumWaves * kRowsPerBlock];
+    const int blk = blockIdx.x;
+    const double s = block_row_sum(part, ustart, blk, sh);
+    const int l = blk * kRowsPerBlock + (threadIdx.x & 63);
+    if (threadIdx.x < 64 && l < n_t) out[l] = s;
+}
+
+// a2: weights w_l = S_theta(T_l) / S_SM(T_l) (Eqs. (fT_norm),
+// (reweight_factor)), w_l := 1 where S_SM = 0, and the fold vector
+// v_l = m_l w_l.  S_theta is summed exactly as the SM reference was, so
+// w = 1 exactly at theta_SM.
+__global__ __launch_bounds__(kRowSumThreads) void k_weights(WeightArgs a) {
+    __shared__ double sh[kRowSumWaves * kRowsPerBlock];
+    const int blk = blockIdx.x;
+    const double s = block_row_sum(a.part, a.ustart, blk, sh);
+    const int l = blk * kRowsPerBlock + (threadIdx.x & 63);
+    if (threadIdx.x < 64 && l < a.n_t) {
+        const double ssm = a.ssm[l];
+        const double w = ssm > 0.0 ? s / ssm : 1.0;
+        if (a.out_w) a.out_w[l] = w;
+        a.v[l] = a.mrow[l] * w;
+    }
+}
+
+// ------------------------------------------------------------- a3 - a5
 constexpr int kFoldThreads = 512;          // 8 waves
 constexpr int kFoldWaves = kFoldThreads / 64;
 constexpr int kFoldCols = 256;             // 64 lanes x float4
@@ -125,15 +173,15 @@ constexpr int kFoldUnroll = 8;
 constexpr int kFoldMaxRows = 2048;
 
 
-// Weights (Eqs. (fT_norm), (reweight_factor)) and the fold through the
-// response (Eqs. (Rij), (fNp_reweight), (mu_total)).  Work-group (rb, cc)
-// streams rows [rb*rows, +rows) and columns [cc*256, +256) of R with 16-byte
-// streaming loads, eight rows in flight per wave; the per-row
-// weights sit in LDS.  R is FP32 in HBM; products and sums are FP64, which
-// the full-rate FP64 vector units of gfx950 absorb at no cost to this
-// bandwidth-bound loop.  The work-group writes its column partial sums; no
-// cross-work-group synchronisation happens here (the partial sums are read
-// by the next kernel).
+// Fold through the response (Eqs. (Rij), (fNp_reweight), (mu_total)).
+// Work-group (rb, cc) streams rows [rb*rows, +rows) and columns
+// [cc*256, +256) of R with 16-byte streaming loads, eight rows in flight per
+// wave (the first eight are issued before the weights are staged); the
+// per-row weights v_l = m_l w_l sit in LDS.  R is FP32 in HBM; products and
+// sums are FP64, which the full-rate FP64 vector units of gfx950 absorb at
+// no cost to this bandwidth-bound loop.  The work-group writes its column
+// partial sums; no cross-work-group synchronisation happens here (the
+// partial sums are read by the next kernel).
 __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
     __shared__ double vs[kFoldMaxRows];
     __shared__ double red[kFoldWaves][kFoldCols + 1];
@@ -144,42 +192,41 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
 
-    for (int r = tid; r < nrows; r += kFoldThreads) {
-        const int l = row0 + r;
-        const int blk = l / kRowsPerBlock, ln = l % kRowsPerBlock;
-        double s = 0.0;
-        for (int u = a.ustart[blk]; u < a.ustart[blk + 1]; ++u)
-            s += a.part[(size_t)u * kRowsPerBlock + ln];
-        const double ssm = a.ssm[l];
-        const double w = ssm > 0.0 ? s / ssm : 1.0;
-        if (a.out_w && cc == 0) a.out_w[l] = w;
-        vs[r] = a.mrow[l] * w;
-    }
-    __syncthreads();
-
     const int ld4 = a.ldr >> 2;
     const int c4 = cc * 64 + lane;
     const bool colok = c4 < ld4;
     const float4* __restrict__ Rp =
         reinterpret_cast<const float4*>(a.R) + (size_t)row0 * ld4 + c4;
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     constexpr int U = kFoldUnroll;
-    if (colok) {
-        int r = wave;
-        for (; r + kFoldWaves * (U - 1) < nrows; r += kFoldWaves * U) {
-            float4 x[U];
+    float4 x[U];
+    int r = wave;
+    bool full = colok && r + kFoldWaves * (U - 1) < nrows;
+    if (full) {
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+            x[q] = ld_stream(Rp + (size_t)(r + q * kFoldWaves) * ld4);
+    }
+    for (int q = tid; q < nrows; q += kFoldThreads) vs[q] = a.v[row0 + q];
+    __syncthreads();
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    while (full) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const double v = vs[r + q * kFoldWaves];
+            acc0 = fma((double)x[q].x, v, acc0);
+            acc1 = fma((double)x[q].y, v, acc1);
+            acc2 = fma((double)x[q].z, v, acc2);
+            acc3 = fma((double)x[q].w, v, acc3);
+        }
+        r += kFoldWaves * U;
+        full = r + kFoldWaves * (U - 1) < nrows;
+        if (full) {
 #pragma unroll
             for (int q = 0; q < U; ++q)
                 x[q] = ld_stream(Rp + (size_t)(r + q * kFoldWaves) * ld4);
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const double v = vs[r + q * kFoldWaves];
-                acc0 = fma((double)x[q].x, v, acc0);
-                acc1 = fma((double)x[q].y, v, acc1);
-                acc2 = fma((double)x[q].z, v, acc2);
-                acc3 = fma((double)x[q].w, v, acc3);
-            }
         }
+    }
+    if (colok) {
         for (; r < nrows; r += kFoldWaves) {
             const float4 z = ld_stream(Rp + (size_t)r * ld4);
             const double v = vs[r];
@@ -432,8 +479,27 @@ hipError_t launch_eint(const EintArgs& a, hipStream_t s) {
 
 hipError_t launch_spectrum_reduce(const double* part, const int* ustart,
                                   int n_t, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_spectrum_reduce, dim3((n_t + 255) / 256), dim3(256),
-                       0, s, part, ustart, n_t, out);
+    hipLaunchKernelGGL(k_spectrum_reduce, dim3((n_t + kRowsPerBlock - 1) / kRowsPerBlock),
+                       dim3(kRowSumThreads), 0, s, part, ustart, n_t, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights(const WeightArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_weights, dim3((a.n_t + kRowsPerBlock - 1) / kRowsPerBlock),
+                       dim3(kRowSumThreads), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_stream(const FoldArgs& a, hipStream_t s) {
+    if (a.rows_per_wg > kFoldMaxRows || a.rows_per_wg <= 0)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fold, dim3(a.n_rb, a.n_cc), dim3(kFoldThreads), 0, s,
+                       a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_finish(const FoldArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_fold_finish, dim3(a.n_cc), dim3(kFinThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,148 @@
+"""The learned surrogate: its BF16 matrix-core forward and backward kernels
+against a plain numpy reference with the same weights, training on spectra
+from the batched method, and the fallback to the exact method."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp as ref
+from problems import config_inputs, gpu_context
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    return torch, torch.device("cuda:0")
+
+
+def test_backward_kernels_match_reference(torch_dev):
+    torch, dev = torch_dev
+    from paper_2607_00488_amd.surrogate import Surrogate, init_params
+    lo, hi = synth.theta_box()
+    H, N, B = 256, 256, 128
+    s = Surrogate(N, lo, hi, hidden=H, seed=11)
+    params = init_params(H, N, 12, out_scale=1.0)
+    s.set_params(params)
+    from paper_2607_00488_amd import nr_mlp_set_output_norm, nr_mlp_train_step_dev
+    nr_mlp_set_output_norm(s.h, np.zeros(N, np.float32), np.ones(N, np.float32))
+    g = synth.rng(13)
+    th = g.uniform(lo, hi, (B, 7))
+    tg = g.standard_normal((B, N)).astype(np.float32)
+    tt = torch.tensor(th, dtype=torch.float64, device=dev)
+    tgt = torch.tensor(tg, device=dev)
+    loss = nr_mlp_train_step_dev(s.h, tt.data_ptr(), tgt.data_ptr(), B, 0.0, True)
+    got = s.grads().astype(np.float64)
+    rl, rg = ref.mse_grad(params.astype(np.float64), th, tg.astype(np.float64),
+                          lo, hi, H, N, bf16=True)
+    assert loss == pytest.approx(rl, rel=2e-3)
+    err = np.linalg.norm(got - rg) / np.linalg.norm(rg)
+    log(f"[gpu] mlp gradient rel L2 error vs reference {err:.2e}")
+    assert err < 5e-3
+    # layer by layer
+    o = 0
+    for rows, kp, _ in [(H, 32, 7), (H, H + 8, H), (H, H + 8, H), (N, H + 8, H)]:
+        a, b = got[o:o + rows * kp], rg[o:o + rows * kp]
+        assert np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)) > 0.9999
+        o += rows * kp
+    # forward (log mu with mean 0, std 1 is the raw output)
+    y = s.logmu(tt).cpu().numpy()
+    ry, _, _ = ref.forward(params.astype(np.float64), th, lo, hi, H, N, bf16=True)
+    assert np.max(np.abs(y - ry)) <= 2e-3 * np.max(np.abs(ry)) + 1e-4
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def trained(torch_dev):
+    torch, dev = torch_dev
+    from paper_2607_00488_amd.surrogate import Surrogate
+    p = config_inputs(0)
+    ctx = gpu_context(p)
+    lo, hi = synth.theta_box()
+    s = Surrogate(p["n_reco"], lo, hi, hidden=256, seed=4001)
+    th_train = s.sample_box(1 << 14, 4001)
+    t0 = time.time()
+    targets = s.make_targets(ctx, th_train)
+    info = s.train(th_train, targets, epochs=60, batch=1024, log_every=200)
+    log(f"[gpu] surrogate trained: {info['steps']} steps in {info['seconds']:.1f}s "
+        f"(data+train {time.time() - t0:.1f}s); losses {info['losses'][-3:]}")
+    return p, ctx, s
+
+
+def test_surrogate_accuracy_and_fallback(trained, torch_dev):
+    torch, dev = torch_dev
+    import paper_2607_00488_amd as nr
+    p, ctx, s = trained
+    o = p["oracle"]
+    th_val = s.sample_box(1 << 11, 4002)
+    nll_s, outside = s.nll(ctx, th_val)
+    exact = torch.empty_like(nll_s)
+    nr.eval_nll_multi_dev([ctx], [th_val], [exact])
+    torch.cuda.synchronize()
+    d = (nll_s - exact).abs().cpu().numpy()
+    assert not outside.any()
+    log(f"[gpu] surrogate |d(-2lnL)| on validation: median {np.median(d):.3g}, "
+        f"90% {np.quantile(d, 0.9):.3g}, max {d.max():.3g}; "
+        f"within 0.1: {np.mean(d <= 0.1):.3f}")
+    # the exact reference itself against the oracle on a few points
+    ev = exact.cpu().numpy()
+    tv = th_val.cpu().numpy()
+    for i in range(0, len(tv), 512):
+        assert abs(ev[i] - o.nll(tv[i])) <= 1e-3
+    # fallback 1: a failing spot check sends the whole batch to the exact path
+    out, info = s.evaluate(ctx, th_val, force_fail=True)
+    assert info["fallback"] == "batch"
+    assert torch.equal(out, exact)
+    # fallback 2: points outside the training box always take the exact path
+    th_mix = th_val[:256].clone()
+    th_mix[::4, 4] = 40.0          # mu_nu beyond the box
+    th_mix[1::4, 0] = -0.9         # eps_eL beyond the box
+    exact_mix = torch.empty(256, dtype=torch.float64, device=dev)
+    nr.eval_nll_multi_dev([ctx], [th_mix.contiguous()], [exact_mix])
+    out, info = s.evaluate(ctx, th_mix, tol=1e30)  # spot checks always pass
+    ob = torch.zeros(256, dtype=torch.bool, device=dev)
+    ob[::4] = True
+    ob[1::4] = True
+    assert info["fallback"] == "outside"
+    assert torch.equal(out[ob], exact_mix[ob])
+    assert info["fallback_fraction"] == pytest.approx(0.5)
+
+
+def test_surrogate_gain(trained, torch_dev):
+    """What the trained network gains over the exact batched method, with
+    spot checks and fallback counted: reported, not assumed."""
+    torch, dev = torch_dev
+    import paper_2607_00488_amd as nr
+    p, ctx, s = trained
+    th = s.sample_box(1 << 14, 4005)
+    exact = torch.empty(len(th), dtype=torch.float64, device=dev)
+    nr.eval_nll_multi_dev([ctx], [th], [exact])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        nr.eval_nll_multi_dev([ctx], [th], [exact])
+    torch.cuda.synchronize()
+    t_exact = (time.perf_counter() - t0) / 3
+    out, info = s.evaluate(ctx, th)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(3):
+        out, info = s.evaluate(ctx, th, seed=k)
+    torch.cuda.synchronize()
+    t_sur = (time.perf_counter() - t0) / 3
+    d = (out - exact).abs()
+    log(f"[gpu] surrogate gain {t_exact / t_sur:.2f}x over exact batched "
+        f"({len(th) / t_sur:.0f} vs {len(th) / t_exact:.0f} evals/s), "
+        f"fallback {info['fallback']} ({info['fallback_fraction']:.2f}), "
+        f"spot worst {info['spot_worst']:.3g}, max |d| returned {d.max().item():.3g}")
+    if info["fallback"] == "batch":
+        assert torch.equal(out, exact)

@@ -128,6 +128,10 @@ def main():
     ap.add_argument("--cpu-evals", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="short run for hardware-counter collection: 20 "
+                         "single-point evaluations, then 20 plain 256 MiB "
+                         "device copies as the byte-count reference")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU "
@@ -139,6 +143,21 @@ def main():
     dev = torch.device("cuda:0")
     p = build_plain(1)
     ctx, c = p["ctx"], p["cfg"]
+    if args.counter_pass:
+        th = torch.tensor(synth.theta_prior(20, 99), dtype=torch.float64,
+                          device=dev)
+        out = torch.empty(20, dtype=torch.float64, device=dev)
+        ctx.set_fold_tiling(0, 0)           # eager launches, one per kernel
+        ctx.eval_nll_dev(th, out)
+        torch.cuda.synchronize()
+        a = torch.empty(1 << 26, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] counter pass done")
+        return
     K, W = args.steps, args.warmup
     th = synth.theta_prior(K, p["seeds"]["theta"])
     tt = torch.tensor(th, dtype=torch.float64, device=dev)
@@ -184,7 +203,7 @@ def main():
     res = dict(metric=METRIC, value=round(evals_s, 1), unit="evals/s",
                n_gpus=1, steps=K, warmup=W, ms_per_step=round(ms_step, 5),
                higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="f32", data="synthetic",
+               dtype="f64", data="synthetic",
                config=dict(workload="plain single-point eval: N_T=16384 "
                            "recoil bins, N_reco=4096, N_E=2048 per continuum "
                            "(5 solar sources), dense FP32 response 256 MiB "

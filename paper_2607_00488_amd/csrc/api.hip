@@ -14,6 +14,7 @@
 #include <string>
 #include <tuple>
 #include <vector>
+#include <sys/stat.h>
 
 namespace {
 
@@ -76,6 +77,7 @@ struct BatchPlan {
     nr::GemmProb* d_probs_a = nullptr;
     nr::GemmTile* d_tiles_a = nullptr;
     int n_tiles_f = 0, n_tiles_a = 0, grid_f = 1, grid_a = 1;
+    int cfg = 0;  // GEMM tile configuration (see batched.h)
     hipGraphExec_t graph = nullptr;
     unsigned long epoch = 0;
 };
@@ -442,7 +444,7 @@ namespace {
 // ------------------------------------------------------------ batched path
 int ensure_batch(nr_ctx* c, int n_pts, bool grad, size_t mu_elems) {
     const int ldw = (n_pts + 3) / 4 * 4;
-    const int nnt = (c->n_reco + nr::kGemmBN - 1) / nr::kGemmBN;
+    const int nnt = (c->n_reco + 63) / 64;  // column tiles of the narrowest config
     int rc;
     bool moved = false;
     if (n_pts > c->b_cap || ldw > c->b_ldw || nnt != c->b_nnt) {
@@ -501,7 +503,8 @@ nr::WgenArgs wgen_args(nr_ctx* c, const double* th, int P) {
     return w;
 }
 
-int build_plan(const MultiCall& mc, bool grad, BatchPlan* pl) {
+int build_plan(const MultiCall& mc, bool grad, int cfg, BatchPlan* pl) {
+    const int TMt = nr::gemm_tile_m(cfg), TNt = nr::gemm_tile_n(cfg);
     std::vector<nr::GemmProb> pf(mc.n), pa(mc.n);
     std::vector<nr::GemmTile> tf, ta;
     for (int d = 0; d < mc.n; ++d) {
@@ -520,14 +523,14 @@ int build_plan(const MultiCall& mc, bool grad, BatchPlan* pl) {
         f.theta = mc.theta[d];
         f.part = c->d_bpart;
         f.part_gb = c->d_bpgb;
-        f.n_nt = c->b_nnt;
+        f.n_nt = (c->n_reco + TNt - 1) / TNt;
         f.aout = grad ? c->d_bat : nullptr;
         f.lda_out = c->b_ldw;
         f.mu = mc.mu ? mc.mu[d] : nullptr;
         pf[d] = f;
-        const int mt = (P + nr::kGemmBM - 1) / nr::kGemmBM;
+        const int mt = (P + TMt - 1) / TMt;
         for (int i = 0; i < mt; ++i)
-            for (int j = 0; j < c->b_nnt; ++j) tf.push_back({d, i, j, c->n_t});
+            for (int j = 0; j < f.n_nt; ++j) tf.push_back({d, i, j, c->n_t});
         if (grad) {
             nr::GemmProb a{};
             a.At = c->d_bat;
@@ -540,7 +543,7 @@ int build_plan(const MultiCall& mc, bool grad, BatchPlan* pl) {
             a.C = c->d_bu;
             a.ldc = c->n_t;
             pa[d] = a;
-            const int nt = (c->n_t + nr::kGemmBN - 1) / nr::kGemmBN;
+            const int nt = (c->n_t + TNt - 1) / TNt;
             for (int i = 0; i < mt; ++i)
                 for (int j = 0; j < nt; ++j) ta.push_back({d, i, j, c->n_reco});
         }
@@ -555,14 +558,15 @@ int build_plan(const MultiCall& mc, bool grad, BatchPlan* pl) {
     HIPCHK(hipMemcpy(pl->d_probs_f, pf.data(), sizeof(nr::GemmProb) * pf.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(pl->d_tiles_f, tf.data(), sizeof(nr::GemmTile) * tf.size(), hipMemcpyHostToDevice));
     pl->n_tiles_f = (int)tf.size();
-    pl->grid_f = nr::gemm_grid(nr::kModeNll, pl->n_tiles_f);
+    pl->cfg = cfg;
+    pl->grid_f = nr::gemm_grid(nr::kModeNll, cfg, pl->n_tiles_f);
     if (grad) {
         if ((rc = dalloc(&pl->d_probs_a, pa.size())) || (rc = dalloc(&pl->d_tiles_a, ta.size())))
             return rc;
         HIPCHK(hipMemcpy(pl->d_probs_a, pa.data(), sizeof(nr::GemmProb) * pa.size(), hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(pl->d_tiles_a, ta.data(), sizeof(nr::GemmTile) * ta.size(), hipMemcpyHostToDevice));
         pl->n_tiles_a = (int)ta.size();
-        pl->grid_a = nr::gemm_grid(nr::kModeAdj, pl->n_tiles_a);
+        pl->grid_a = nr::gemm_grid(nr::kModeAdj, cfg, pl->n_tiles_a);
     }
     pl->epoch = g_epoch;
     return 0;
@@ -572,15 +576,15 @@ int enqueue_plan(const MultiCall& mc, bool grad, BatchPlan* pl, unsigned* ctr,
                  hipStream_t s) {
     for (int d = 0; d < mc.n; ++d)
         HIPCHK(nr::launch_wgen(wgen_args(mc.ctx[d], mc.theta[d], mc.n_pts[d]), s));
-    HIPCHK(nr::launch_gemm(nr::kModeNll, pl->d_probs_f, pl->d_tiles_f, pl->n_tiles_f,
-                           ctr, pl->grid_f, s));
+    HIPCHK(nr::launch_gemm(nr::kModeNll, pl->cfg, pl->d_probs_f, pl->d_tiles_f,
+                           pl->n_tiles_f, ctr, pl->grid_f, s));
     for (int d = 0; d < mc.n; ++d) {
         nr_ctx* c = mc.ctx[d];
         nr::FinalArgs f{};
         f.part = c->d_bpart;
         f.theta = mc.theta[d];
         f.n_pts = mc.n_pts[d];
-        f.n_nt = c->b_nnt;
+        f.n_nt = (c->n_reco + nr::gemm_tile_n(pl->cfg) - 1) / nr::gemm_tile_n(pl->cfg);
         f.cdata = c->cdata;
         for (int i = 0; i < NR_NTHETA; ++i) {
             f.pull_mean[i] = c->pull_mean[i];
@@ -590,8 +594,8 @@ int enqueue_plan(const MultiCall& mc, bool grad, BatchPlan* pl, unsigned* ctr,
         HIPCHK(nr::launch_finalize(f, s));
     }
     if (grad) {
-        HIPCHK(nr::launch_gemm(nr::kModeAdj, pl->d_probs_a, pl->d_tiles_a, pl->n_tiles_a,
-                               ctr + 2, pl->grid_a, s));
+        HIPCHK(nr::launch_gemm(nr::kModeAdj, pl->cfg, pl->d_probs_a, pl->d_tiles_a,
+                               pl->n_tiles_a, ctr + 2, pl->grid_a, s));
         for (int d = 0; d < mc.n; ++d) {
             nr_ctx* c = mc.ctx[d];
             nr::ContractArgs a{};
@@ -599,7 +603,7 @@ int enqueue_plan(const MultiCall& mc, bool grad, BatchPlan* pl, unsigned* ctr,
             a.ldu = c->n_t;
             a.n_t = c->n_t;
             a.n_pts = mc.n_pts[d];
-            a.n_nt = c->b_nnt;
+            a.n_nt = (c->n_reco + nr::gemm_tile_n(pl->cfg) - 1) / nr::gemm_tile_n(pl->cfg);
             a.ssm = c->d_ssm;
             a.mrow = c->d_mrow;
             a.basis = c->d_basis;
@@ -614,6 +618,140 @@ int enqueue_plan(const MultiCall& mc, bool grad, BatchPlan* pl, unsigned* ctr,
             HIPCHK(nr::launch_adj_contract(a, s));
         }
     }
+    return 0;
+}
+
+// ---- project autotuner for the grouped GEMM.  A shape class is the sorted
+// list of (points rounded up to 64, N_reco, N_T) of the call plus the mode;
+// the first call of a class times every tile configuration on the real
+// problem (one warm-up and two timed runs each) and keeps the fastest, in
+// memory and in a small JSON file (NR_AUTOTUNE_CACHE, default
+// $HOME/.cache/nureweight/autotune.json).  NR_AUTOTUNE=0 skips tuning; a
+// missing, unreadable or corrupt cache file only means tuning again.
+struct TuneCache {
+    bool loaded = false;
+    std::map<std::string, int> best;
+    std::string path;
+};
+TuneCache g_tune;
+
+std::string tune_path() {
+    const char* p = getenv("NR_AUTOTUNE_CACHE");
+    if (p && *p) return p;
+    const char* h = getenv("HOME");
+    return std::string(h && *h ? h : "/tmp") + "/.cache/nureweight/autotune.json";
+}
+
+void tune_load() {
+    const std::string path = tune_path();
+    if (g_tune.loaded && path == g_tune.path) return;
+    g_tune.loaded = true;
+    g_tune.best.clear();
+    g_tune.path = path;
+    FILE* f = fopen(g_tune.path.c_str(), "r");
+    if (!f) return;
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, n);
+    fclose(f);
+    // entries are "key": value with keys free of quotes
+    size_t i = 0;
+    while ((i = txt.find('"', i)) != std::string::npos) {
+        const size_t j = txt.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = txt.substr(i + 1, j - i - 1);
+        const size_t c = txt.find(':', j);
+        if (c == std::string::npos) break;
+        char* end = nullptr;
+        const long v = strtol(txt.c_str() + c + 1, &end, 10);
+        if (end != txt.c_str() + c + 1 && v >= 0 && v < nr::kGemmConfigs)
+            g_tune.best[key] = (int)v;
+        i = (end && end > txt.c_str() + c) ? (size_t)(end - txt.c_str()) : j + 1;
+    }
+}
+
+void tune_save() {
+    std::string dir = g_tune.path.substr(0, g_tune.path.rfind('/'));
+    std::string cmd;
+    for (size_t k = 1; k <= dir.size(); ++k)  // mkdir -p without a shell
+        if (k == dir.size() || dir[k] == '/') (void)mkdir(dir.substr(0, k).c_str(), 0755);
+    FILE* f = fopen((g_tune.path + ".tmp").c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    size_t k = 0;
+    for (auto& kv : g_tune.best)
+        fprintf(f, "  \"%s\": %d%s\n", kv.first.c_str(), kv.second,
+                ++k < g_tune.best.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+    (void)rename((g_tune.path + ".tmp").c_str(), g_tune.path.c_str());
+}
+
+std::string shape_class(const MultiCall& mc, bool grad) {
+    std::vector<std::string> parts;
+    for (int d = 0; d < mc.n; ++d) {
+        char b[96];
+        snprintf(b, sizeof(b), "%dx%dx%d", (mc.n_pts[d] + 63) / 64 * 64,
+                 mc.ctx[d]->n_reco, mc.ctx[d]->n_t);
+        parts.push_back(b);
+    }
+    std::sort(parts.begin(), parts.end());
+    std::string key = grad ? "grad" : "nll";
+    for (auto& p : parts) key += "|" + p;
+    if (key.size() > 200) {  // long groups: a stable hash keeps the file small
+        unsigned long h = 1469598103934665603ul;
+        for (char ch : key) h = (h ^ (unsigned char)ch) * 1099511628211ul;
+        char b[64];
+        snprintf(b, sizeof(b), "%s|n%d|h%016lx", grad ? "grad" : "nll", mc.n, h);
+        key = b;
+    }
+    return key;
+}
+
+int tuned_config(const MultiCall& mc, bool grad, hipStream_t s, int* cfg_out) {
+    const char* force = getenv("NR_GEMM_CONFIG");  // pins a configuration
+    if (force && force[0] >= '0' && force[0] < '0' + nr::kGemmConfigs && !force[1]) {
+        *cfg_out = force[0] - '0';
+        return 0;
+    }
+    const char* e = getenv("NR_AUTOTUNE");
+    if (e && e[0] == '0') { *cfg_out = 0; return 0; }
+    tune_load();
+    const std::string key = shape_class(mc, grad);
+    auto it = g_tune.best.find(key);
+    if (it != g_tune.best.end()) { *cfg_out = it->second; return 0; }
+    nr_ctx* owner = mc.ctx[0];
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best = 0;
+    for (int cfg = 0; cfg < nr::kGemmConfigs; ++cfg) {
+        BatchPlan pl;
+        int rc = build_plan(mc, grad, cfg, &pl);
+        if (rc) return rc;
+        rc = enqueue_plan(mc, grad, &pl, owner->d_gctr, s);  // warm-up
+        if (!rc) {
+            HIPCHK(hipEventRecord(e0, s));
+            for (int r = 0; r < 2 && !rc; ++r) rc = enqueue_plan(mc, grad, &pl, owner->d_gctr, s);
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (pl.d_probs_f) (void)hipFree(pl.d_probs_f);
+        if (pl.d_tiles_f) (void)hipFree(pl.d_tiles_f);
+        if (pl.d_probs_a) (void)hipFree(pl.d_probs_a);
+        if (pl.d_tiles_a) (void)hipFree(pl.d_tiles_a);
+        if (rc) return rc;
+        if (ms < best_ms) { best_ms = ms; best = cfg; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    g_tune.best[key] = best;
+    tune_save();
+    *cfg_out = best;
     return 0;
 }
 
@@ -643,9 +781,12 @@ int run_multi(const MultiCall& mc, hipStream_t s) {
                 if (kv.second && kv.first != key) free_plan(kv.second);
             owner->plans.clear();
         }
+        int cfg = 0;
+        int rc = tuned_config(mc, grad, s, &cfg);
+        if (rc) return rc;
         BatchPlan*& np = owner->plans[key];
         np = new BatchPlan();
-        int rc = build_plan(mc, grad, np);
+        rc = build_plan(mc, grad, cfg, np);
         if (rc) { free_plan(np); owner->plans.erase(key); return rc; }
         if (owner->use_graph) {
             hipGraph_t g;

@@ -70,13 +70,17 @@ struct ContractArgs {
     double* grad;    // [n_pts][7]
 };
 
-constexpr int kGemmBM = 128, kGemmBN = 128;
 
 hipError_t launch_wgen(const WgenArgs& a, hipStream_t s);
-hipError_t launch_gemm(int mode, const GemmProb* probs, const GemmTile* tiles,
+// Tile configurations of the GEMM: 0: 128x128, 1: 64x128, 2: 128x64,
+// 3: 64x64 (M x N per work-group).
+constexpr int kGemmConfigs = 4;
+hipError_t launch_gemm(int mode, int cfg, const GemmProb* probs, const GemmTile* tiles,
                        int n_tiles, unsigned* ctr, int grid, hipStream_t s);
+int gemm_tile_m(int cfg);
+int gemm_tile_n(int cfg);
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s);
 hipError_t launch_adj_contract(const ContractArgs& a, hipStream_t s);
-int gemm_grid(int mode, int n_tiles);
+int gemm_grid(int mode, int cfg, int n_tiles);
 
 }  // namespace nr

@@ -110,28 +110,33 @@ __global__ __launch_bounds__(256) void k_wgen(WgenArgs a) {
 }
 
 // --------------------------------------------------------------- GEMM
-// Tiles of 128 x 128 outputs, K-steps of 16; four waves in 2 x 2, each
-// 64 x 64 = 4 x 4 blocks of v_mfma_f64_16x16x4_f64.  R stays FP32 in HBM
-// and is widened to FP64 when staged into LDS.
-constexpr int BM = 128, BN = 128, BK = 16;
+// Tiles of BM x BN outputs, K-steps of 16; four waves in 2 x 2, each
+// (BM/2) x (BN/2) = blocks of v_mfma_f64_16x16x4_f64.  R stays FP32 in HBM
+// and is widened to FP64 when staged into LDS.  The tile shape is a
+// template parameter; the host picks one per shape class by timing.
+constexpr int BK = 16;
 constexpr int kGemmThreads = 256;
-constexpr int LDS_S = BM + 2;      // LDS row stride (doubles)
-constexpr int EPI_S = 65;          // epilogue staging row stride (doubles)
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <int MODE>
+template <int MODE, int BM, int BN>
 __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
                                                        const GemmTile* tiles,
                                                        int n_tiles,
                                                        unsigned* ctr) {
-    // As[BK][LDS_S] then Bs[BK][LDS_S]; reused by the epilogue staging
-    __shared__ double smem[2 * BK * LDS_S];
+    constexpr int WTM = BM / 2, WTN = BN / 2;   // wave tile
+    constexpr int BI = WTM / 16, BJ = WTN / 16;  // 16x16 blocks per wave
+    constexpr int LDA = BM + 2, LDB = BN + 2;   // LDS row strides (doubles)
+    constexpr int EPI = WTN + 1;                 // epilogue staging stride
+    constexpr int NA = BM / 32;                  // double2 chunks per thread
+    constexpr int NB = BN / 64;                  // float4 chunks per thread
+    constexpr int MAIN = BK * (LDA + LDB), STAGE = 4 * 16 * EPI;
+    __shared__ double smem[MAIN > STAGE ? MAIN : STAGE];
     __shared__ double rowred[BM][2];
     __shared__ double rowred2[BM][2];
     __shared__ int s_tile;
-    double (*As)[LDS_S] = reinterpret_cast<double (*)[LDS_S]>(smem);
-    double (*Bs)[LDS_S] = reinterpret_cast<double (*)[LDS_S]>(smem + BK * LDS_S);
+    double (*As)[LDA] = reinterpret_cast<double (*)[LDA]>(smem);
+    double (*Bs)[LDB] = reinterpret_cast<double (*)[LDB]>(smem + BK * LDA);
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
@@ -148,29 +153,29 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
         const int m0 = tl.mt * BM, n0 = tl.nt * BN;
         const int K = pr.K;
 
-        v4d acc[4][4];
+        v4d acc[BI][BJ];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < BI; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
+            for (int j = 0; j < BJ; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-        double2 ra[4];
-        float4 rb[2];
+        double2 ra[NA];
+        float4 rb[NB];
         auto gload = [&](int k0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {  // A^T: BK x BM doubles, M contiguous
-                const int q = tid + i * kGemmThreads;  // 0..1023
-                const int kk = q >> 6, c2 = q & 63;
+            for (int i = 0; i < NA; ++i) {  // A^T: BK x BM doubles, M contiguous
+                const int q = tid + i * kGemmThreads;
+                const int kk = q / (BM / 2), c2 = q % (BM / 2);
                 const int k = k0 + kk, m = m0 + 2 * c2;
                 ra[i] = (k < K && m < pr.lda)
                             ? *reinterpret_cast<const double2*>(pr.At + (size_t)k * pr.lda + m)
                             : make_double2(0.0, 0.0);
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int q = tid + i * kGemmThreads;  // 0..511
+            for (int i = 0; i < NB; ++i) {
+                const int q = tid + i * kGemmThreads;
                 if (MODE != kModeAdj) {  // B[k][n] = R[k][n], N contiguous
-                    const int kk = q >> 5, c4 = q & 31;
+                    const int kk = q / (BN / 4), c4 = q % (BN / 4);
                     const int k = k0 + kk, n = n0 + 4 * c4;
                     rb[i] = (k < K && n < pr.ldb)
                                 ? *reinterpret_cast<const float4*>(pr.B + (size_t)k * pr.ldb + n)
@@ -186,16 +191,16 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
         };
         auto sstore = [&]() {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < NA; ++i) {
                 const int q = tid + i * kGemmThreads;
-                const int kk = q >> 6, c2 = q & 63;
+                const int kk = q / (BM / 2), c2 = q % (BM / 2);
                 *reinterpret_cast<double2*>(&As[kk][2 * c2]) = ra[i];
             }
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < NB; ++i) {
                 const int q = tid + i * kGemmThreads;
                 if (MODE != kModeAdj) {
-                    const int kk = q >> 5, c4 = q & 31;
+                    const int kk = q / (BN / 4), c4 = q % (BN / 4);
                     double* d = &Bs[kk][4 * c4];
                     d[0] = rb[i].x; d[1] = rb[i].y; d[2] = rb[i].z; d[3] = rb[i].w;
                 } else {
@@ -216,16 +221,15 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
             if (k0 + BK < K) gload(k0 + BK);
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
-                double a[4], b[4];
+                double a[BI], b[BJ];
 #pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    a[x] = As[kk + lk][wm * 64 + x * 16 + li];
-                    b[x] = Bs[kk + lk][wn * 64 + x * 16 + li];
-                }
+                for (int x = 0; x < BI; ++x) a[x] = As[kk + lk][wm * WTM + x * 16 + li];
 #pragma unroll
-                for (int x = 0; x < 4; ++x)
+                for (int y = 0; y < BJ; ++y) b[y] = Bs[kk + lk][wn * WTN + y * 16 + li];
 #pragma unroll
-                    for (int y = 0; y < 4; ++y)
+                for (int x = 0; x < BI; ++x)
+#pragma unroll
+                    for (int y = 0; y < BJ; ++y)
                         acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
             }
         }
@@ -234,40 +238,41 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
         // j + 16 * (i % 4), register i / 4.
         if (MODE == kModeAdj) {
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi)
+            for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
+                for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int p = m0 + wm * 64 + bi * 16 + lk + 4 * r;
-                        const int col = n0 + wn * 64 + bj * 16 + li;
+                        const int p = m0 + wm * WTM + bi * 16 + lk + 4 * r;
+                        const int col = n0 + wn * WTN + bj * 16 + li;
                         if (p < pr.M && col < pr.N)
                             pr.C[(size_t)p * pr.ldc + col] = acc[bi][bj][r];
                     }
         } else {
             // one 16-row strip of each wave at a time through LDS; four lanes
-            // share a row and take 16 of the wave's 64 columns each
-            double* stage = smem + wave * 16 * EPI_S;
+            // share a row and take a quarter of the wave's columns each
+            double* stage = smem + wave * 16 * EPI;
+            constexpr int CQ = WTN / 4;
 #pragma unroll
-            for (int bi = 0; bi < 4; ++bi) {
+            for (int bi = 0; bi < BI; ++bi) {
                 __syncthreads();
 #pragma unroll
-                for (int bj = 0; bj < 4; ++bj)
+                for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        stage[(lk + 4 * r) * EPI_S + bj * 16 + li] = acc[bi][bj][r];
+                        stage[(lk + 4 * r) * EPI + bj * 16 + li] = acc[bi][bj][r];
                 __syncthreads();
                 const int r16 = lane >> 2, cs = lane & 3;
-                const int i = wm * 64 + bi * 16 + r16;
+                const int i = wm * WTM + bi * 16 + r16;
                 const int p = m0 + i;
                 double dsum = 0.0, gsum = 0.0;
                 if (p < pr.M) {
                     const double fb = pr.theta[(size_t)p * kNTheta + 6];
-                    for (int q = 0; q < 16; ++q) {
-                        const int col = n0 + wn * 64 + cs * 16 + q;
+                    for (int q = 0; q < CQ; ++q) {
+                        const int col = n0 + wn * WTN + cs * CQ + q;
                         if (col >= pr.N) break;
                         const double bj_ = pr.b[col];
-                        const double mu = fb * bj_ + stage[r16 * EPI_S + cs * 16 + q];
+                        const double mu = fb * bj_ + stage[r16 * EPI + cs * CQ + q];
                         const double nj = pr.n[col];
                         double d;
                         if (nj > 0.0)
@@ -381,15 +386,30 @@ hipError_t launch_wgen(const WgenArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_gemm(int mode, const GemmProb* probs, const GemmTile* tiles,
-                       int n_tiles, unsigned* ctr, int grid, hipStream_t s) {
-    if (mode == kModeAdj)
-        hipLaunchKernelGGL(k_gemm<kModeAdj>, dim3(grid), dim3(kGemmThreads), 0, s,
-                           probs, tiles, n_tiles, ctr);
-    else
-        hipLaunchKernelGGL(k_gemm<kModeNll>, dim3(grid), dim3(kGemmThreads), 0, s,
-                           probs, tiles, n_tiles, ctr);
+template <int MODE, int BM, int BN>
+static hipError_t launch_one(const GemmProb* probs, const GemmTile* tiles,
+                             int n_tiles, unsigned* ctr, int grid, hipStream_t s) {
+    hipLaunchKernelGGL((k_gemm<MODE, BM, BN>), dim3(grid), dim3(kGemmThreads), 0, s,
+                       probs, tiles, n_tiles, ctr);
     return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_mode(int cfg, const GemmProb* probs, const GemmTile* tiles,
+                              int n_tiles, unsigned* ctr, int grid, hipStream_t s) {
+    switch (cfg) {
+        case 0: return launch_one<MODE, 128, 128>(probs, tiles, n_tiles, ctr, grid, s);
+        case 1: return launch_one<MODE, 64, 128>(probs, tiles, n_tiles, ctr, grid, s);
+        case 2: return launch_one<MODE, 128, 64>(probs, tiles, n_tiles, ctr, grid, s);
+        case 3: return launch_one<MODE, 64, 64>(probs, tiles, n_tiles, ctr, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gemm(int mode, int cfg, const GemmProb* probs, const GemmTile* tiles,
+                       int n_tiles, unsigned* ctr, int grid, hipStream_t s) {
+    if (mode == kModeAdj) return launch_mode<kModeAdj>(cfg, probs, tiles, n_tiles, ctr, grid, s);
+    return launch_mode<kModeNll>(cfg, probs, tiles, n_tiles, ctr, grid, s);
 }
 
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
@@ -407,21 +427,33 @@ hipError_t launch_adj_contract(const ContractArgs& a, hipStream_t s) {
 namespace nr {
 
 // Persistent grid: as many work-groups as can be resident at once.
-int gemm_grid(int mode, int n_tiles) {
-    int dev = 0, cus = 0, per_cu = 0;
+template <int MODE, int BM, int BN>
+static int per_cu() {
+    int n = 0;
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gemm<MODE, BM, BN>,
+                                                       kGemmThreads, 0);
+    return n;
+}
+
+int gemm_grid(int mode, int cfg, int n_tiles) {
+    int dev = 0, cus = 0, pc = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (mode == kModeAdj)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm<kModeAdj>,
-                                                           kGemmThreads, 0);
-    else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_gemm<kModeNll>,
-                                                           kGemmThreads, 0);
+    const bool adj = mode == kModeAdj;
+    switch (cfg) {
+        case 0: pc = adj ? per_cu<kModeAdj, 128, 128>() : per_cu<kModeNll, 128, 128>(); break;
+        case 1: pc = adj ? per_cu<kModeAdj, 64, 128>() : per_cu<kModeNll, 64, 128>(); break;
+        case 2: pc = adj ? per_cu<kModeAdj, 128, 64>() : per_cu<kModeNll, 128, 64>(); break;
+        default: pc = adj ? per_cu<kModeAdj, 64, 64>() : per_cu<kModeNll, 64, 64>(); break;
+    }
     if (cus <= 0) cus = 256;
-    if (per_cu <= 0) per_cu = 1;
-    int g = cus * per_cu;
+    if (pc <= 0) pc = 1;
+    int g = cus * pc;
     if (g > n_tiles) g = n_tiles;
     return g < 1 ? 1 : g;
 }
+
+int gemm_tile_m(int cfg) { return (cfg == 1 || cfg == 3) ? 64 : 128; }
+int gemm_tile_n(int cfg) { return (cfg == 2 || cfg == 3) ? 64 : 128; }
 
 }  // namespace nr

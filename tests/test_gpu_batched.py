@@ -126,3 +126,44 @@ def test_grouped_graph_replay_and_grad(multi):
             assert abs(ref[d][i] - v) <= 1e-3
             scale = np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())
             assert np.all(np.abs(g[i] - rg) <= 1e-4 * scale + 1e-6), (d, i)
+
+
+@pytest.mark.parametrize("cfg", ["0", "1", "2", "3"])
+def test_every_tile_configuration(cfg, monkeypatch):
+    """Each GEMM tile shape the autotuner may pick gives the same results
+    (tile edges in M, N and K included)."""
+    import paper_2607_00488_amd as nr
+    monkeypatch.setenv("NR_GEMM_CONFIG", cfg)
+    probs, ctxs, ths = [], [], []
+    for d, (n_t, n_reco, n_e, P) in enumerate(SHAPES[:4]):
+        p = inputs(n_t, n_reco, n_e, 100_000, 500 + d, 600 + d)
+        probs.append(p)
+        ctxs.append(gpu_context(p))
+        ths.append(synth.theta_prior(P, 700 + d))
+    outs = nr.eval_nll_multi(ctxs, ths)
+    for d, (p, th, out) in enumerate(zip(probs, ths, outs)):
+        for i in range(0, len(th), max(1, len(th) // 8)):
+            assert abs(out[i] - p["oracle"].nll(th[i])) <= 1e-3, (cfg, d, i)
+    for c in ctxs:
+        c.close()
+
+
+def test_autotuner_cache(tmp_path, monkeypatch):
+    """The autotuner writes its choice to the cache file; a corrupt file is
+    ignored (the shape class is tuned again)."""
+    import json
+    import paper_2607_00488_amd as nr
+    cache = tmp_path / "tune.json"
+    cache.write_text("{ this is not json")
+    monkeypatch.setenv("NR_AUTOTUNE_CACHE", str(cache))
+    monkeypatch.delenv("NR_GEMM_CONFIG", raising=False)
+    p = inputs(*SHAPES[0][:3], 100_000, 500, 600)
+    ctx = gpu_context(p)
+    th = synth.theta_prior(SHAPES[0][3], 700)
+    out = ctx.eval_nll_batched(th)
+    assert abs(out[0] - p["oracle"].nll(th[0])) <= 1e-3
+    saved = json.loads(cache.read_text())
+    assert len(saved) == 1
+    (key, cfg), = saved.items()
+    assert key.startswith("nll|") and cfg in (0, 1, 2, 3)
+    ctx.close()

@@ -11,6 +11,20 @@ import torch
 from . import Context, eval_nll_multi_dev
 
 
+def _buffers(context: Context, P: int, dev, batched: bool):
+    """Fixed input/output buffers per (context, P, form): the library then
+    replays one cached graph for every call of a fit."""
+    cache = context.__dict__.setdefault("_autograd_bufs", {})
+    key = (P, str(dev), batched)
+    b = cache.get(key)
+    if b is None:
+        b = (torch.empty(P, 7, dtype=torch.float64, device=dev),
+             torch.empty(P, dtype=torch.float64, device=dev),
+             torch.empty(P, 7, dtype=torch.float64, device=dev))
+        cache[key] = b
+    return b
+
+
 class NllFunction(torch.autograd.Function):
     """nll[p] = -2lnL(theta[p]) for theta [P, 7] float64 on the context's
     device.  ``batched`` selects the GEMM form (many points at once) instead
@@ -19,17 +33,17 @@ class NllFunction(torch.autograd.Function):
     @staticmethod
     def forward(fctx, theta: torch.Tensor, context: Context,
                 batched: bool = True):
-        th = theta.detach().to(torch.float64).contiguous()
-        P = th.shape[0]
-        nll = torch.empty(P, dtype=torch.float64, device=th.device)
-        grad = torch.empty(P, 7, dtype=torch.float64, device=th.device)
+        P = theta.shape[0]
+        th, nll, grad = _buffers(context, P, theta.device, batched)
+        th.copy_(theta.detach())
         stream = torch.cuda.current_stream(th.device)
         if batched:
             eval_nll_multi_dev([context], [th], [nll], [grad], stream=stream)
         else:
             context.eval_nll_dev(th, nll, grad, stream=stream)
-        fctx.save_for_backward(grad)
-        return nll
+        out, g = nll.clone(), grad.clone()
+        fctx.save_for_backward(g)
+        return out
 
     @staticmethod
     def backward(fctx, g):

@@ -40,7 +40,11 @@ int fail(int code, const char* fmt, ...) {
 
 template <class T>
 int dalloc(T** p, size_t n) {
-    if (*p) { (void)hipFree(*p); *p = nullptr; }
+    if (*p) {  // the old buffer may still be read by in-flight work
+        (void)hipDeviceSynchronize();
+        (void)hipFree(*p);
+        *p = nullptr;
+    }
     if (n == 0) n = 1;
     hipError_t e = hipMalloc((void**)p, n * sizeof(T));
     if (e != hipSuccess) {
@@ -160,8 +164,12 @@ struct nr_ctx {
 
 namespace {
 
+// Graph executables and the tile tables their kernels read may still be in
+// flight (the _dev entry points return without waiting): wait for the device
+// before destroying or freeing them.
 void free_plan(BatchPlan* p) {
     if (!p) return;
+    (void)hipDeviceSynchronize();
     if (p->graph) (void)hipGraphExecDestroy(p->graph);
     if (p->d_probs_f) (void)hipFree(p->d_probs_f);
     if (p->d_tiles_f) (void)hipFree(p->d_tiles_f);
@@ -171,6 +179,7 @@ void free_plan(BatchPlan* p) {
 }
 
 void clear_graphs(nr_ctx* c) {
+    if (!c->graphs.empty() || !c->plans.empty()) (void)hipDeviceSynchronize();
     for (auto& kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
     c->graphs.clear();
     for (auto& kv : c->plans) free_plan(kv.second);
@@ -899,7 +908,7 @@ int nr_create(int device, nr_ctx** out) {
 void nr_destroy(nr_ctx* c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    (void)hipStreamSynchronize(c->stream);
+    (void)hipDeviceSynchronize();
     clear_graphs(c);
     dfree(&c->d_E); dfree(&c->d_W); dfree(&c->d_Pe); dfree(&c->d_tc);
     dfree(&c->d_ssm); dfree(&c->d_basis); dfree(&c->d_part);

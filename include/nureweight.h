@@ -36,8 +36,10 @@
  *
  * Ownership: every set_* call copies what it is given before returning; the
  * caller keeps its arrays.  Outputs are caller-allocated.  The _dev entry
- * points borrow device pointers, enqueue on the given stream (NULL = the
- * context's stream) and do not synchronise.  A context is not thread-safe.
+ * points borrow device pointers, enqueue on the given stream and do not
+ * synchronise; a NULL stream means the HIP default stream (the work is
+ * ordered after what is already on it, and later work on it waits for the
+ * results).  A context is not thread-safe.
  */
 #ifndef NUREWEIGHT_H
 #define NUREWEIGHT_H
@@ -119,7 +121,7 @@ int nr_eval_mu(nr_ctx *ctx, const double *theta, int n_pts, double *mu);
 
 /* Device-pointer variant of nr_eval_nll / nr_eval_nll_grad: d_theta
  * [n_pts][7] double, d_nll [n_pts] double, d_grad [n_pts][7] double or
- * NULL.  Enqueued on `stream` (hipStream_t, NULL = the context stream);
+ * NULL.  Enqueued on `stream` (hipStream_t, NULL = the default stream);
  * returns without waiting.  Replays a cached HIP graph for repeated
  * (pointer, n_pts) combinations. */
 int nr_eval_nll_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
@@ -153,8 +155,8 @@ int nr_eval_nll_multi(nr_ctx *const *ctx, int n_ctx,
 
 /* Device-pointer variant of nr_eval_nll_multi (and of the batched gradient
  * when d_grad is not NULL: d_grad[d] is [n_pts[d]][7]).  Enqueued on
- * `stream` (NULL = ctx[0]'s stream); a cached HIP graph of the whole grouped
- * evaluation is replayed for repeated pointer sets. */
+ * `stream` (NULL = the default stream); a cached HIP graph of the whole
+ * grouped evaluation is replayed for repeated pointer sets. */
 int nr_eval_nll_multi_dev(nr_ctx *const *ctx, int n_ctx,
                           const double *const *d_theta, const int *n_pts,
                           double *const *d_nll, double *const *d_grad,

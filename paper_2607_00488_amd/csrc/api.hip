@@ -61,6 +61,38 @@ void dfree(T** p) {
     *p = nullptr;
 }
 
+// A NULL stream argument of the _dev entry points means the HIP default
+// stream.  Work cannot be captured on it, so it runs on an internal stream
+// ordered after everything already on the default stream, and the default
+// stream waits for its end.
+struct Bridge {
+    hipStream_t work = nullptr;
+    hipEvent_t out = nullptr;
+    bool on = false;
+};
+
+int bridge_begin(Bridge& b, void* user, hipStream_t internal, hipEvent_t in,
+                 hipEvent_t out) {
+    if (user) {
+        b.work = (hipStream_t)user;
+        b.on = false;
+        return 0;
+    }
+    b.work = internal;
+    b.out = out;
+    b.on = true;
+    HIPCHK(hipEventRecord(in, nullptr));
+    HIPCHK(hipStreamWaitEvent(internal, in, 0));
+    return 0;
+}
+
+int bridge_end(Bridge& b) {
+    if (!b.on) return 0;
+    HIPCHK(hipEventRecord(b.out, b.work));
+    HIPCHK(hipStreamWaitEvent(nullptr, b.out, 0));
+    return 0;
+}
+
 bool finite_all(const double* p, size_t n) {
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(p[i])) return false;
@@ -100,6 +132,7 @@ struct nr_ctx {
     hipEvent_t ev_w[2] = {nullptr, nullptr}, ev_f[2] = {nullptr, nullptr};
     hipEvent_t ev_fin[2] = {nullptr, nullptr};
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;  // default-stream bridge
     double* d_v[2] = {nullptr, nullptr};  // [n_t] fold vectors, by parity
     nr::Phys ph{};
     // sources and grid
@@ -889,6 +922,8 @@ int nr_create(int device, nr_ctx** out) {
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
     if (e != hipSuccess) {
         delete c;
         return fail(NR_EHIP, "stream creation: %s", hipGetErrorString(e));
@@ -930,6 +965,8 @@ void nr_destroy(nr_ctx* c) {
     }
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     (void)hipStreamSynchronize(c->stream2);
     (void)hipStreamSynchronize(c->stream3);
     (void)hipStreamDestroy(c->stream2);
@@ -1186,8 +1223,11 @@ int nr_eval_nll_dev(nr_ctx* c, const double* d_theta, int n_pts, double* d_nll,
     if (!d_theta || !d_nll || n_pts <= 0)
         return fail(NR_EINVAL, "null device pointer or n_pts <= 0");
     if ((rc = set_device(c))) return rc;
-    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
-    return run_points(c, d_theta, n_pts, d_nll, d_grad, nullptr, nullptr, s);
+    Bridge br;
+    if ((rc = bridge_begin(br, stream, c->stream, c->ev_in, c->ev_out))) return rc;
+    if ((rc = run_points(c, d_theta, n_pts, d_nll, d_grad, nullptr, nullptr, br.work)))
+        return rc;
+    return bridge_end(br);
 }
 
 static int eval_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
@@ -1330,9 +1370,12 @@ int nr_eval_nll_multi_dev(nr_ctx* const* ctx, int n_ctx,
     if ((rc = set_device(ctx[0]))) return rc;
     for (int d = 0; d < n_ctx; ++d)
         if ((rc = ensure_batch(ctx[d], n_pts[d], d_grad != nullptr, 0))) return rc;
-    hipStream_t s = stream ? (hipStream_t)stream : ctx[0]->stream;
+    Bridge br;
+    if ((rc = bridge_begin(br, stream, ctx[0]->stream, ctx[0]->ev_in, ctx[0]->ev_out)))
+        return rc;
     MultiCall mc{ctx, n_ctx, d_theta, n_pts, d_nll, d_grad, nullptr};
-    return run_multi(mc, s);
+    if ((rc = run_multi(mc, br.work))) return rc;
+    return bridge_end(br);
 }
 
 int nr_eval_nll_multi(nr_ctx* const* ctx, int n_ctx, const double* const* theta,
@@ -1392,6 +1435,7 @@ struct nr_mlp {
     long step = 0;
     int train_cap = 0;
     hipStream_t stream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 namespace {
@@ -1486,6 +1530,8 @@ int nr_mlp_create(int device, int hidden, int n_out, nr_mlp** out) {
     q->n_params = q->off[4];
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_in, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&q->ev_out, hipEventDisableTiming);
     if (e != hipSuccess) {
         delete q;
         return fail(NR_EHIP, "mlp stream: %s", hipGetErrorString(e));
@@ -1515,6 +1561,8 @@ void nr_mlp_destroy(nr_mlp* q) {
     for (int l = 0; l < 3; ++l) { dfree(&q->h[l]); dfree(&q->z[l]); }
     dfree(&q->tile_loss); dfree(&q->part); dfree(&q->outside);
     dfree(&q->mean); dfree(&q->stdv);
+    if (q->ev_in) (void)hipEventDestroy(q->ev_in);
+    if (q->ev_out) (void)hipEventDestroy(q->ev_out);
     (void)hipStreamDestroy(q->stream);
     delete q;
 }
@@ -1578,8 +1626,11 @@ int nr_mlp_targets_dev(nr_mlp* q, const double* d_mu, int P, float* d_t, void* s
     if (!q || !d_mu || !d_t || P <= 0) return fail(NR_EINVAL, "bad argument");
     HIPCHK(hipSetDevice(q->device));
     nr::TargetArgs a{d_mu, P, q->n_out, q->mean, q->stdv, d_t};
-    HIPCHK(nr::launch_targets(a, stream ? (hipStream_t)stream : q->stream));
-    return 0;
+    Bridge br;
+    int rc;
+    if ((rc = bridge_begin(br, stream, q->stream, q->ev_in, q->ev_out))) return rc;
+    HIPCHK(nr::launch_targets(a, br.work));
+    return bridge_end(br);
 }
 
 int nr_mlp_train_step_dev(nr_mlp* q, const double* d_theta, const float* d_t,
@@ -1589,7 +1640,9 @@ int nr_mlp_train_step_dev(nr_mlp* q, const double* d_theta, const float* d_t,
     HIPCHK(hipSetDevice(q->device));
     int rc;
     if ((rc = mlp_alloc_batch(q, B, true))) return rc;
-    hipStream_t s = stream ? (hipStream_t)stream : q->stream;
+    Bridge br;
+    if ((rc = bridge_begin(br, stream, q->stream, q->ev_in, q->ev_out))) return rc;
+    hipStream_t s = br.work;
     const int H = q->H, ldh = H + 8, N = q->n_out;
     if ((rc = mlp_input(q, d_theta, B, s))) return rc;
     if ((rc = mlp_hidden_forward(q, B, s))) return rc;
@@ -1646,6 +1699,7 @@ int nr_mlp_train_step_dev(nr_mlp* q, const double* d_theta, const float* d_t,
     ad.bc1 = 1.0f - powf(0.9f, (float)q->step);
     ad.bc2 = 1.0f - powf(0.999f, (float)q->step);
     HIPCHK(nr::launch_adam(ad, s));
+    if ((rc = bridge_end(br))) return rc;
     if (loss) {
         const int tiles = ((B + 127) / 128) * ((N + 127) / 128);
         std::vector<double> tl(tiles);
@@ -1666,7 +1720,9 @@ int nr_mlp_logmu_dev(nr_mlp* q, const double* d_theta, int B, float* d_logmu,
     HIPCHK(hipSetDevice(q->device));
     int rc;
     if ((rc = mlp_alloc_batch(q, B, false))) return rc;
-    hipStream_t s = stream ? (hipStream_t)stream : q->stream;
+    Bridge br;
+    if ((rc = bridge_begin(br, stream, q->stream, q->ev_in, q->ev_out))) return rc;
+    hipStream_t s = br.work;
     const int ldh = q->H + 8;
     if ((rc = mlp_input(q, d_theta, B, s))) return rc;
     if ((rc = mlp_hidden_forward(q, B, s))) return rc;
@@ -1676,7 +1732,7 @@ int nr_mlp_logmu_dev(nr_mlp* q, const double* d_theta, int B, float* d_logmu,
     go.C32 = d_logmu;
     go.ldc = q->n_out;
     HIPCHK(nr::launch_mlp_gemm(nr::kMlpLogMu, go, s));
-    return 0;
+    return bridge_end(br);
 }
 
 int nr_mlp_nll_dev(nr_mlp* q, nr_ctx* c, const double* d_theta, int B,
@@ -1688,7 +1744,9 @@ int nr_mlp_nll_dev(nr_mlp* q, nr_ctx* c, const double* d_theta, int B,
     if (c->n_reco != q->n_out) return fail(NR_EINVAL, "surrogate outputs %d bins, data has %d", q->n_out, c->n_reco);
     HIPCHK(hipSetDevice(q->device));
     if ((rc = mlp_alloc_batch(q, B, false))) return rc;
-    hipStream_t s = stream ? (hipStream_t)stream : q->stream;
+    Bridge br;
+    if ((rc = bridge_begin(br, stream, q->stream, q->ev_in, q->ev_out))) return rc;
+    hipStream_t s = br.work;
     const int ldh = q->H + 8;
     const int nnt = (q->n_out + 127) / 128;
     if ((rc = mlp_input(q, d_theta, B, s))) return rc;
@@ -1714,7 +1772,7 @@ int nr_mlp_nll_dev(nr_mlp* q, nr_ctx* c, const double* d_theta, int B,
     HIPCHK(nr::launch_finalize(f, s));
     if (d_outside)
         HIPCHK(hipMemcpyAsync(d_outside, q->outside, sizeof(int) * B, hipMemcpyDeviceToDevice, s));
-    return 0;
+    return bridge_end(br);
 }
 
 int nr_eval_mu_batched_dev(nr_ctx* c, const double* d_theta, int n_pts,
@@ -1724,13 +1782,15 @@ int nr_eval_mu_batched_dev(nr_ctx* c, const double* d_theta, int n_pts,
     if (!d_theta || !d_mu || n_pts <= 0) return fail(NR_EINVAL, "bad argument");
     if ((rc = set_device(c))) return rc;
     if ((rc = ensure_batch(c, n_pts, false, 0))) return rc;
-    hipStream_t s = stream ? (hipStream_t)stream : c->stream;
+    Bridge br;
+    if ((rc = bridge_begin(br, stream, c->stream, c->ev_in, c->ev_out))) return rc;
     nr_ctx* cs[1] = {c};
     const double* ths[1] = {d_theta};
     double* nls[1] = {c->d_bnll};
     double* mus[1] = {d_mu};
     MultiCall mc{cs, 1, ths, &n_pts, nls, nullptr, mus};
-    return run_multi(mc, s);
+    if ((rc = run_multi(mc, br.work))) return rc;
+    return bridge_end(br);
 }
 
 }  // extern "C"

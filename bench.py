@@ -5,7 +5,8 @@ E-integral, weights, HBM-streaming fold of the 16384 x 4096 FP32 response,
 Poisson -2lnL) at a fresh parameter point, with every input resident in HBM.
 The K timed steps are one HIP-graph replay of K evaluations.
 
-Prints one JSON line (see the design doc for the field definitions).
+Prints one JSON line: the plain rate as `value`, the roofline of the step
+kernel, the batched and gradient forms and the CPU oracle timed beside it.
 """
 import argparse
 import json
@@ -21,6 +22,13 @@ import numpy as np  # noqa: E402
 METRIC = ("likelihood evals/s at |Δ(−2lnL)|≤1e-3 vs FP64: "
           "plain vs batched/grad/surrogate")
 HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(n_t, n_reco):
+    """Bytes one evaluation must move at least once: the FP32 response, the
+    two FP64 per-row inputs of the weights (S_SM and m) and the FP64 data
+    and background per observed bin."""
+    return 4 * n_t * n_reco + 16 * n_t + 16 * n_reco
 
 
 def log(msg):
@@ -134,9 +142,9 @@ def main():
                          "device copies as the byte-count reference")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU "
-              "path (a parameter scan shards by points with no collective; "
-              "see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no "
+              "multi-GPU path (a parameter scan would shard by points and "
+              "needs no collective)", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth
@@ -188,17 +196,20 @@ def main():
         lat.append(time.perf_counter() - t1)
     lat = np.array(lat[1:]) * 1e3
 
-    # roofline of the dominant kernel (fold + likelihood), HIP events on the
-    # context stream around back-to-back launches
+    # roofline of the dominant kernel: the step kernel as the pipeline runs
+    # it (fold of one point, weights of the next, reduction of the previous
+    # in one launch), HIP events on the context stream around back-to-back
+    # launches; the fold role alone and the other stages for the breakdown
+    step_ms = ctx.time_stage(5, 200)
     fold_ms = ctx.time_stage(4, 200)
     fold_lik_ms = ctx.time_stage(2, 200)
     eint_ms = ctx.time_stage(1, 200)
-    alg_bytes = 4 * c.n_t * c.n_reco + 4 * c.n_t + 16 * c.n_reco
-    achieved = alg_bytes / (fold_ms * 1e-3) / 1e9
+    alg_bytes = algorithmic_bytes(c.n_t, c.n_reco)
+    achieved = alg_bytes / (step_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=None, kernel="k_fold",
-                avg_kernel_us=round(fold_ms * 1e3, 2),
+                traffic=None, kernel="k_step",
+                avg_kernel_us=round(step_ms * 1e3, 2),
                 algorithmic_bytes=alg_bytes)
     res = dict(metric=METRIC, value=round(evals_s, 1), unit="evals/s",
                n_gpus=1, steps=K, warmup=W, ms_per_step=round(ms_step, 5),
@@ -213,6 +224,7 @@ def main():
                detail=dict(sync_latency_ms_mean=round(float(lat.mean()), 4),
                            sync_latency_ms_std=round(float(lat.std()), 4),
                            eint_weights_us=round(eint_ms * 1e3, 2),
+                           fold_alone_us=round(fold_ms * 1e3, 2),
                            fold_plus_likelihood_us=round(fold_lik_ms * 1e3, 2)))
     forms = {}
     # gradient form: 1024 points at the same shapes, -2lnL + 7 derivatives

@@ -123,15 +123,6 @@ struct BatchPlan {
 struct nr_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
-    // second stream: the E-integral and weights of the next point run there
-    // while the fold of the current point streams R
-    hipStream_t stream2 = nullptr;
-    // third stream: the likelihood reduction of point p overlaps the fold of
-    // point p + 1 (fold partial sums double-buffered by parity)
-    hipStream_t stream3 = nullptr;
-    hipEvent_t ev_w[2] = {nullptr, nullptr}, ev_f[2] = {nullptr, nullptr};
-    hipEvent_t ev_fin[2] = {nullptr, nullptr};
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;  // default-stream bridge
     double* d_v[2] = {nullptr, nullptr};  // [n_t] fold vectors, by parity
     nr::Phys ph{};
@@ -142,13 +133,11 @@ struct nr_ctx {
     std::vector<int> src_off, src_n, src_group;
     std::vector<double> hE, hW, hPe, tc;
     std::vector<int> jmin;
-    std::vector<nr::EUnit> units;
-    std::vector<int> ustart;
     std::vector<double> ssm, basis;
     double *d_E = nullptr /* 1/E per node */, *d_W = nullptr, *d_Pe = nullptr, *d_tc = nullptr;
-    double *d_ssm = nullptr, *d_basis = nullptr, *d_part = nullptr;
-    int *d_group = nullptr, *d_jmin = nullptr, *d_ustart = nullptr;
-    nr::EUnit* d_units = nullptr;
+    double *d_ssm = nullptr, *d_basis = nullptr;
+    int *d_group = nullptr, *d_jmin = nullptr, *d_srcoff = nullptr;
+    double* d_table[2] = {nullptr, nullptr};  // [n_nodes + n_src] double4, by parity
     // response
     int n_reco = 0, ldr = 0;
     float* d_R = nullptr;
@@ -172,12 +161,13 @@ struct nr_ctx {
     double *d_mu = nullptr, *d_w = nullptr;
     size_t cap_pts = 0, cap_mu = 0, cap_w = 0;
     double* d_thsm = nullptr;
+    double* d_tnll = nullptr;  // [1] output of timing-only launches
     // graphs
     bool use_graph = true;
     std::map<GraphKey, hipGraphExec_t> graphs;
     // last launch arguments (for nr_time_stage)
-    nr::EintArgs last_e{};
-    nr::WeightArgs last_w{};
+    nr::ScanArgs last_s{};
+    nr::RowArgs last_r{};
     nr::FoldArgs last_f{};
     nr::AdjArgs last_a{};
     bool have_last = false, have_last_adj = false;
@@ -317,122 +307,166 @@ int ensure_stage(nr_ctx* c, size_t pts, size_t mu_elems, size_t w_elems) {
     return 0;
 }
 
-nr::EintArgs eint_args(nr_ctx* c, const double* d_theta) {
-    nr::EintArgs a{};
-    a.units = c->d_units;
-    a.n_units = (int)c->units.size();
+nr::ScanArgs scan_args(nr_ctx* c, const double* d_theta, int par) {
+    nr::ScanArgs a{};
     a.nodeIE = c->d_E;
     a.nodeW = c->d_W;
     a.nodePe = c->d_Pe;
+    a.srcOff = c->d_srcoff;
     a.srcGroup = c->d_group;
-    a.jmin = c->d_jmin;
-    a.tc = c->d_tc;
-    a.n_t = c->n_t;
     a.theta = d_theta;
     a.ph = c->ph;
-    a.part = c->d_part;
+    a.table = reinterpret_cast<double4*>(c->d_table[par]);
     return a;
 }
 
-// Single-point evaluations of a list of points, software-pipelined over
-// three streams: a1 (E-integral) and a2 (weights) of point p run on the
-// second stream, the R-streaming fold (a3) of point p on the main stream,
-// and the likelihood reduction (a4, a5) of point p on the third stream
-// while the fold of point p + 1 streams.  Weight vectors and fold partial
-// sums are double-buffered by parity; with a gradient, the adjoint pass of
-// point p follows its likelihood on the main stream.
+nr::RowArgs row_args(nr_ctx* c, int par, double* v, double* out_w,
+                     double* out_s) {
+    nr::RowArgs a{};
+    a.table = reinterpret_cast<const double4*>(c->d_table[par]);
+    a.jmin = c->d_jmin;
+    a.tc = c->d_tc;
+    a.n_t = c->n_t;
+    a.n_src = c->n_src;
+    a.ssm = c->d_ssm;
+    a.mrow = c->d_mrow;
+    a.v = v;
+    a.out_w = out_w;
+    a.out_s = out_s;
+    return a;
+}
+
+nr::FoldArgs fold_args(nr_ctx* c, const double* thp, const double* v,
+                       double* colpart, double* nll, double* mu, bool grad) {
+    nr::FoldArgs fa{};
+    fa.R = c->d_R;
+    fa.ldr = c->ldr;
+    fa.n_t = c->n_t;
+    fa.n_reco = c->n_reco;
+    fa.v = v;
+    fa.n = c->d_n;
+    fa.b = c->d_b;
+    fa.theta = thp;
+    fa.colpart = colpart;
+    fa.ctr = c->d_ctr;
+    fa.chunk_dev = c->d_chunk_dev;
+    fa.chunk_gb = c->d_chunk_gb;
+    fa.out_nll = nll;
+    fa.out_mu = mu;
+    fa.out_a = grad ? c->d_a : nullptr;
+    fa.out_gb = grad ? c->d_gb : nullptr;
+    fa.cdata = c->cdata;
+    for (int i = 0; i < NR_NTHETA; ++i) {
+        fa.pull_mean[i] = c->pull_mean[i];
+        fa.pull_sigma[i] = c->pull_sigma[i];
+    }
+    fa.rows_per_wg = c->rows_per_wg;
+    fa.n_rb = c->n_rb;
+    fa.n_cc = c->n_cc;
+    return fa;
+}
+
+int step(nr_ctx* c, const nr::FoldArgs* fold, const nr::RowArgs* rows,
+         const nr::ScanArgs* scan, const nr::FoldArgs* fin, hipStream_t s) {
+    nr::StepArgs a{};
+    if (fold) {
+        a.fold = *fold;
+        a.nb_fold = c->n_rb * c->n_cc;
+    }
+    if (rows) {
+        a.rows = *rows;
+        a.nb_rows = c->n_blocks;
+    }
+    if (scan) {
+        a.scan = *scan;
+        a.nb_scan = c->n_src;
+    }
+    if (fin) {
+        a.fin = *fin;
+        a.nb_fin = c->n_cc;
+    }
+    HIPCHK(nr::launch_step(a, s));
+    return 0;
+}
+
+// Single-point evaluations of a list of points on one stream.  Launch k of
+// the step kernel builds the node table of point k (a1), forms the weights
+// of point k - 1 (a2), folds point k - 2 (a3) and reduces the likelihood of
+// point k - 3 (a4, a5), so all but the fold run beside the R stream
+// instead of after it.  Node tables, weight vectors and fold partial sums
+// alternate between two buffers by point parity, and stream order is the
+// only synchronisation.  With a gradient each point runs its stages in
+// turn, the adjoint pass (which needs the finished a_j) last.
 int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
                    double* grad, double* mu, double* w, hipStream_t s) {
-    hipStream_t s2 = c->stream2, s3 = c->stream3;
-    HIPCHK(hipEventRecord(c->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(s2, c->ev_fork, 0));
-    HIPCHK(hipStreamWaitEvent(s3, c->ev_fork, 0));
-    const size_t cp_stride = (size_t)c->n_rb * c->ldr;
-    for (int p = 0; p < n_pts; ++p) {
-        const double* thp = th + (size_t)p * NR_NTHETA;
-        const int par = p & 1;
-        // a1, a2 on the second stream
-        nr::EintArgs ea = eint_args(c, thp);
-        HIPCHK(nr::launch_eint(ea, s2));
-        if (p >= 2) HIPCHK(hipStreamWaitEvent(s2, c->ev_f[par], 0));
-        nr::WeightArgs wa{};
-        wa.part = c->d_part;
-        wa.ustart = c->d_ustart;
-        wa.ssm = c->d_ssm;
-        wa.mrow = c->d_mrow;
-        wa.n_t = c->n_t;
-        wa.v = c->d_v[par];
-        wa.out_w = w ? w + (size_t)p * c->n_t : nullptr;
-        HIPCHK(nr::launch_weights(wa, s2));
-        HIPCHK(hipEventRecord(c->ev_w[par], s2));
-        // a3 on the main stream
-        HIPCHK(hipStreamWaitEvent(s, c->ev_w[par], 0));
-        if (p >= 2) HIPCHK(hipStreamWaitEvent(s, c->ev_fin[par], 0));
-        nr::FoldArgs fa{};
-        fa.R = c->d_R;
-        fa.ldr = c->ldr;
-        fa.n_t = c->n_t;
-        fa.n_reco = c->n_reco;
-        fa.v = c->d_v[par];
-        fa.n = c->d_n;
-        fa.b = c->d_b;
-        fa.theta = thp;
-        fa.colpart = c->d_colpart + par * cp_stride;
-        fa.ctr = c->d_ctr;
-        fa.chunk_dev = c->d_chunk_dev;
-        fa.chunk_gb = c->d_chunk_gb;
-        fa.out_nll = nll + p;
-        fa.out_mu = mu ? mu + (size_t)p * c->n_reco : nullptr;
-        fa.out_a = grad ? c->d_a : nullptr;
-        fa.out_gb = grad ? c->d_gb : nullptr;
-        fa.cdata = c->cdata;
-        for (int i = 0; i < NR_NTHETA; ++i) {
-            fa.pull_mean[i] = c->pull_mean[i];
-            fa.pull_sigma[i] = c->pull_sigma[i];
+    const size_t cp = (size_t)c->n_rb * c->ldr;
+    auto thp = [&](int p) { return th + (size_t)p * NR_NTHETA; };
+    auto sa = [&](int p) { return scan_args(c, thp(p), p & 1); };
+    auto ra = [&](int p) {
+        return row_args(c, p & 1, c->d_v[p & 1],
+                        w ? w + (size_t)p * c->n_t : nullptr, nullptr);
+    };
+    auto fa = [&](int p) {
+        return fold_args(c, thp(p), c->d_v[p & 1], c->d_colpart + (p & 1) * cp,
+                         nll + p, mu ? mu + (size_t)p * c->n_reco : nullptr,
+                         grad != nullptr);
+    };
+    auto in = [&](int p) { return p >= 0 && p < n_pts; };
+    int rc;
+    if (!grad) {
+        for (int k = 0; k <= n_pts + 2; ++k) {
+            nr::ScanArgs a1;
+            nr::RowArgs a2;
+            nr::FoldArgs a3, a4;
+            if (in(k)) a1 = sa(k);
+            if (in(k - 1)) a2 = ra(k - 1);
+            if (in(k - 2)) a3 = fa(k - 2);
+            if (in(k - 3)) a4 = fa(k - 3);
+            if ((rc = step(c, in(k - 2) ? &a3 : nullptr, in(k - 1) ? &a2 : nullptr,
+                           in(k) ? &a1 : nullptr, in(k - 3) ? &a4 : nullptr, s)))
+                return rc;
         }
-        fa.rows_per_wg = c->rows_per_wg;
-        fa.n_rb = c->n_rb;
-        fa.n_cc = c->n_cc;
-        HIPCHK(nr::launch_fold_stream(fa, s));
-        HIPCHK(hipEventRecord(c->ev_f[par], s));
-        // a4, a5 on the third stream
-        HIPCHK(hipStreamWaitEvent(s3, c->ev_f[par], 0));
-        HIPCHK(nr::launch_fold_finish(fa, s3));
-        HIPCHK(hipEventRecord(c->ev_fin[par], s3));
-        c->last_e = ea;
-        c->last_w = wa;
-        c->last_f = fa;
+        c->last_s = sa(n_pts - 1);
+        c->last_r = ra(n_pts - 1);
+        c->last_f = fa(n_pts - 1);
         c->have_last = true;
-        if (grad) {
-            HIPCHK(hipStreamWaitEvent(s, c->ev_fin[par], 0));
-            nr::AdjArgs aa{};
-            aa.R = c->d_R;
-            aa.ldr = c->ldr;
-            aa.n_t = c->n_t;
-            aa.n_reco = c->n_reco;
-            aa.a = c->d_a;
-            aa.ssm = c->d_ssm;
-            aa.mrow = c->d_mrow;
-            aa.basis = c->d_basis;
-            aa.theta = thp;
-            aa.gb = c->d_gb;
-            aa.jpart = c->d_jpart;
-            aa.ctr = c->d_ctr + c->n_cc + 1;
-            aa.out_grad = grad + (size_t)p * NR_NTHETA;
-            for (int i = 0; i < NR_NTHETA; ++i) {
-                aa.pull_mean[i] = c->pull_mean[i];
-                aa.pull_sigma[i] = c->pull_sigma[i];
-            }
-            aa.ph = c->ph;
-            HIPCHK(nr::launch_adjoint(aa, c->adj_grid, s));
-            c->last_a = aa;
-            c->have_last_adj = true;
-        }
+        return 0;
     }
-    HIPCHK(hipEventRecord(c->ev_join, s2));
-    HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
-    HIPCHK(hipEventRecord(c->ev_join, s3));
-    HIPCHK(hipStreamWaitEvent(s, c->ev_join, 0));
+    for (int p = 0; p < n_pts; ++p) {
+        const nr::ScanArgs a1 = sa(p);
+        const nr::RowArgs a2 = ra(p);
+        const nr::FoldArgs f = fa(p);
+        if ((rc = step(c, nullptr, nullptr, &a1, nullptr, s))) return rc;
+        if ((rc = step(c, nullptr, &a2, nullptr, nullptr, s))) return rc;
+        if ((rc = step(c, &f, nullptr, nullptr, nullptr, s))) return rc;
+        if ((rc = step(c, nullptr, nullptr, nullptr, &f, s))) return rc;
+        nr::AdjArgs aa{};
+        aa.R = c->d_R;
+        aa.ldr = c->ldr;
+        aa.n_t = c->n_t;
+        aa.n_reco = c->n_reco;
+        aa.a = c->d_a;
+        aa.ssm = c->d_ssm;
+        aa.mrow = c->d_mrow;
+        aa.basis = c->d_basis;
+        aa.theta = thp(p);
+        aa.gb = c->d_gb;
+        aa.jpart = c->d_jpart;
+        aa.ctr = c->d_ctr + c->n_cc + 1;
+        aa.out_grad = grad + (size_t)p * NR_NTHETA;
+        for (int i = 0; i < NR_NTHETA; ++i) {
+            aa.pull_mean[i] = c->pull_mean[i];
+            aa.pull_sigma[i] = c->pull_sigma[i];
+        }
+        aa.ph = c->ph;
+        HIPCHK(nr::launch_adjoint(aa, c->adj_grid, s));
+        c->last_s = a1;
+        c->last_r = a2;
+        c->last_f = f;
+        c->last_a = aa;
+        c->have_last = true;
+        c->have_last_adj = true;
+    }
     return 0;
 }
 
@@ -913,15 +947,6 @@ int nr_create(int device, nr_ctx** out) {
     c->device = device;
     hipError_t e = hipSetDevice(device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&c->stream3, hipStreamNonBlocking);
-    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
-        e = hipEventCreateWithFlags(&c->ev_w[i], hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_f[i], hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fin[i], hipEventDisableTiming);
-    }
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -929,7 +954,7 @@ int nr_create(int device, nr_ctx** out) {
         return fail(NR_EHIP, "stream creation: %s", hipGetErrorString(e));
     }
     if (dalloc(&c->d_a, 1) || dalloc(&c->d_gb, 1) || dalloc(&c->d_thsm, NR_NTHETA) ||
-        dalloc(&c->d_gctr, 4)) {
+        dalloc(&c->d_gctr, 4) || dalloc(&c->d_tnll, 1)) {
         delete c;
         return NR_ENOMEM;
     }
@@ -946,9 +971,9 @@ void nr_destroy(nr_ctx* c) {
     (void)hipDeviceSynchronize();
     clear_graphs(c);
     dfree(&c->d_E); dfree(&c->d_W); dfree(&c->d_Pe); dfree(&c->d_tc);
-    dfree(&c->d_ssm); dfree(&c->d_basis); dfree(&c->d_part);
-    dfree(&c->d_group); dfree(&c->d_jmin); dfree(&c->d_ustart);
-    dfree(&c->d_units); dfree(&c->d_R); dfree(&c->d_mrow);
+    dfree(&c->d_ssm); dfree(&c->d_basis); dfree(&c->d_tnll);
+    dfree(&c->d_group); dfree(&c->d_jmin); dfree(&c->d_srcoff);
+    dfree(&c->d_table[0]); dfree(&c->d_table[1]); dfree(&c->d_R); dfree(&c->d_mrow);
     dfree(&c->d_n); dfree(&c->d_b); dfree(&c->d_colpart);
     dfree(&c->d_chunk_dev); dfree(&c->d_chunk_gb); dfree(&c->d_ctr);
     dfree(&c->d_a); dfree(&c->d_gb); dfree(&c->d_jpart);
@@ -958,19 +983,8 @@ void nr_destroy(nr_ctx* c) {
     dfree(&c->d_bu); dfree(&c->d_bth); dfree(&c->d_bnll); dfree(&c->d_bgrad);
     dfree(&c->d_bmu); dfree(&c->d_gctr);
     dfree(&c->d_v[0]); dfree(&c->d_v[1]);
-    for (int i = 0; i < 2; ++i) {
-        if (c->ev_w[i]) (void)hipEventDestroy(c->ev_w[i]);
-        if (c->ev_f[i]) (void)hipEventDestroy(c->ev_f[i]);
-        if (c->ev_fin[i]) (void)hipEventDestroy(c->ev_fin[i]);
-    }
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
-    (void)hipStreamSynchronize(c->stream2);
-    (void)hipStreamSynchronize(c->stream3);
-    (void)hipStreamDestroy(c->stream2);
-    (void)hipStreamDestroy(c->stream3);
     (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -1051,31 +1065,7 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
             c->jmin[(size_t)k * n_t + l] = off + lo;
         }
     }
-    // work units: 64 rows x <= 64 nodes of one source
-    c->n_blocks = (n_t + nr::kRowsPerBlock - 1) / nr::kRowsPerBlock;
-    c->units.clear();
-    c->ustart.assign(c->n_blocks + 1, 0);
-    for (int b = 0; b < c->n_blocks; ++b) {
-        c->ustart[b] = (int)c->units.size();
-        const int l0 = b * nr::kRowsPerBlock;
-        const int l1 = std::min(n_t, l0 + nr::kRowsPerBlock) - 1;
-        for (int k = 0; k < n_src; ++k) {
-            const int lo = c->jmin[(size_t)k * n_t + l0];
-            const int full = c->jmin[(size_t)k * n_t + l1];
-            const int hi = c->src_off[k] + c->src_n[k];
-            for (int j = lo; j < hi; j += nr::kUnitNodes) {
-                nr::EUnit u{};
-                u.block = b;
-                u.src = k;
-                u.j0 = j;
-                u.cnt = std::min(nr::kUnitNodes, hi - j);
-                u.jfull = full;
-                c->units.push_back(u);
-            }
-        }
-    }
-    c->ustart[c->n_blocks] = (int)c->units.size();
-    const size_t nu = std::max<size_t>(1, c->units.size());
+    c->n_blocks = (n_t + nr::kStepRows - 1) / nr::kStepRows;
     // theta-independent basis spectra (FP64), used by the adjoint
     c->basis.assign((size_t)nr::kNBasis * n_t, 0.0);
     for (int l = 0; l < n_t; ++l) {
@@ -1105,9 +1095,9 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
         (rc = dalloc(&c->d_Pe, c->n_nodes)) || (rc = dalloc(&c->d_tc, n_t)) ||
         (rc = dalloc(&c->d_ssm, n_t)) || (rc = dalloc(&c->d_group, n_src)) ||
         (rc = dalloc(&c->d_jmin, (size_t)n_src * n_t)) ||
-        (rc = dalloc(&c->d_ustart, c->n_blocks + 1)) ||
-        (rc = dalloc(&c->d_units, nu)) ||
-        (rc = dalloc(&c->d_part, nu * nr::kRowsPerBlock)) ||
+        (rc = dalloc(&c->d_srcoff, n_src + 1)) ||
+        (rc = dalloc(&c->d_table[0], (size_t)4 * (c->n_nodes + n_src))) ||
+        (rc = dalloc(&c->d_table[1], (size_t)4 * (c->n_nodes + n_src))) ||
         (rc = dalloc(&c->d_basis, (size_t)nr::kNBasis * n_t)) ||
         (rc = dalloc(&c->d_v[0], n_t)) || (rc = dalloc(&c->d_v[1], n_t)))
         return rc;
@@ -1121,17 +1111,15 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
     HIPCHK(hipMemcpy(c->d_tc, c->tc.data(), sizeof(double) * n_t, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_group, c->src_group.data(), sizeof(int) * n_src, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_jmin, c->jmin.data(), sizeof(int) * c->jmin.size(), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->d_ustart, c->ustart.data(), sizeof(int) * (c->n_blocks + 1), hipMemcpyHostToDevice));
-    if (!c->units.empty())
-        HIPCHK(hipMemcpy(c->d_units, c->units.data(), sizeof(nr::EUnit) * c->units.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_srcoff, c->src_off.data(), sizeof(int) * (n_src + 1), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_basis, c->basis.data(), sizeof(double) * c->basis.size(), hipMemcpyHostToDevice));
-    // SM reference on the device with the same E-integral kernel the
+    // SM reference on the device with the same E-integral code the
     // evaluations use, so that w = S_theta / S_SM is exactly 1 at theta_SM.
-    if (!c->units.empty()) {
-        HIPCHK(nr::launch_eint(eint_args(c, c->d_thsm), c->stream));
-        HIPCHK(nr::launch_spectrum_reduce(c->d_part, c->d_ustart, n_t, c->d_ssm, c->stream));
-    } else {
-        HIPCHK(hipMemsetAsync(c->d_ssm, 0, sizeof(double) * n_t, c->stream));
+    {
+        const nr::ScanArgs sa = scan_args(c, c->d_thsm, 0);
+        const nr::RowArgs ra = row_args(c, 0, nullptr, nullptr, c->d_ssm);
+        if ((rc = step(c, nullptr, nullptr, &sa, nullptr, c->stream))) return rc;
+        if ((rc = step(c, nullptr, &ra, nullptr, nullptr, c->stream))) return rc;
     }
     c->ssm.resize(n_t);
     HIPCHK(hipMemcpyAsync(c->ssm.data(), c->d_ssm, sizeof(double) * n_t,
@@ -1314,21 +1302,46 @@ int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
     if (!c || !avg_ms || iters <= 0) return fail(NR_EINVAL, "bad argument");
     if (!c->have_last || (stage == 3 && !c->have_last_adj))
         return fail(NR_ESTATE, "no previous evaluation to time");
-    if (stage < 1 || stage > 4) return fail(NR_EINVAL, "stage must be 1, 2, 3 or 4");
+    if (stage < 1 || stage > 5) return fail(NR_EINVAL, "stage must be 1 to 5");
     int rc;
     if ((rc = set_device(c))) return rc;
+    // Timing launches write only internal buffers: the table and weights go
+    // to the buffers the last fold did not read, the likelihood to a scratch
+    // word.
+    const nr::FoldArgs f = c->last_f;
+    const int par = f.v == c->d_v[1];
+    nr::ScanArgs sa = c->last_s;
+    sa.table = reinterpret_cast<double4*>(c->d_table[par ^ 1]);
+    nr::RowArgs ra = c->last_r;
+    ra.table = reinterpret_cast<const double4*>(c->d_table[par]);
+    ra.v = c->d_v[par ^ 1];
+    ra.out_w = nullptr;
+    ra.out_s = nullptr;
+    nr::FoldArgs g = f;
+    g.colpart = c->d_colpart + (size_t)(par ^ 1) * c->n_rb * c->ldr;
+    g.out_nll = c->d_tnll;
+    g.out_mu = nullptr;
+    g.out_a = nullptr;
+    g.out_gb = nullptr;
+    nr::FoldArgs fo = f;
+    fo.colpart = g.colpart;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, c->stream));
     for (int i = 0; i < iters; ++i) {
         if (stage == 1) {
-            HIPCHK(nr::launch_eint(c->last_e, c->stream));
-            HIPCHK(nr::launch_weights(c->last_w, c->stream));
+            rc = step(c, nullptr, nullptr, &sa, nullptr, c->stream);
+            if (!rc) rc = step(c, nullptr, &ra, nullptr, nullptr, c->stream);
         }
-        if (stage == 2) HIPCHK(nr::launch_fold(c->last_f, c->stream));
+        if (stage == 2) {
+            rc = step(c, &fo, nullptr, nullptr, nullptr, c->stream);
+            if (!rc) rc = step(c, nullptr, nullptr, nullptr, &g, c->stream);
+        }
         if (stage == 3) HIPCHK(nr::launch_adjoint(c->last_a, c->adj_grid, c->stream));
-        if (stage == 4) HIPCHK(nr::launch_fold_stream(c->last_f, c->stream));
+        if (stage == 4) rc = step(c, &fo, nullptr, nullptr, nullptr, c->stream);
+        if (stage == 5) rc = step(c, &f, &ra, &sa, &g, c->stream);
+        if (rc) return rc;
     }
     HIPCHK(hipEventRecord(e1, c->stream));
     HIPCHK(hipEventSynchronize(e1));

@@ -7,8 +7,7 @@
 namespace nr {
 
 constexpr int kNTheta = 7;
-constexpr int kRowsPerBlock = 64;   // recoil rows per E-integral block (lanes)
-constexpr int kUnitNodes = 64;      // energy nodes per E-integral work unit
+constexpr int kStepRows = 512;      // recoil rows per weights work-group
 constexpr int kNBasis = 20;         // theta-independent recoil basis spectra
 
 // Physical constants in the units the device works in: the weak prefactor
@@ -23,41 +22,31 @@ struct Phys {
     double gLe, gLm, gR;  // tree-level chiral couplings (e, mu/tau, R)
 };
 
-// One E-integral work unit: a block of 64 consecutive recoil rows and up to
-// 64 consecutive energy nodes of one source.  Nodes with global index
-// >= jfull are reachable from every row of the block.
-struct EUnit {
-    int block;
-    int src;
-    int j0;
-    int cnt;
-    int jfull;
-    int pad[3];
+// Node table of one point: one work-group per source k builds the suffix
+// sums C_k(j) = sum_{i >= j} c_i of the per-node Laurent coefficients
+// (a0, a1, a2, am) into table[j + k]; table[srcOff[k+1] + k] is zero.
+struct ScanArgs {
+    const double* nodeIE;  // [n_nodes] 1 / E_j, E-sorted within a source
+    const double* nodeW;   // [n_nodes] quadrature weight times flux
+    const double* nodePe;  // [n_nodes] P_ee(E_j)
+    const int* srcOff;     // [n_src+1] first node of each source
+    const int* srcGroup;   // [n_src] 1: scaled by f_8B
+    const double* theta;   // device, 7 doubles
+    Phys ph;
+    double4* table;        // [n_nodes + n_src]
 };
 
-struct EintArgs {
-    const EUnit* units;
-    int n_units;
-    const double* nodeIE;  // 1 / E_j
-    const double* nodeW;
-    const double* nodePe;
-    const int* srcGroup;
+// Weights of one point from its node table, one thread per recoil row.
+struct RowArgs {
+    const double4* table;
     const int* jmin;      // [n_src][n_t] first reachable global node index
     const double* tc;     // [n_t] recoil-bin centres
-    int n_t;
-    const double* theta;  // device, 7 doubles
-    Phys ph;
-    double* part;         // [n_units][64]
-};
-
-struct WeightArgs {
-    const double* part;   // E-integral partials
-    const int* ustart;    // [n_blocks+1] first unit of each row block
-    const double* ssm;    // [n_t] S_SM (device E-integral at theta_SM)
+    int n_t, n_src;
+    const double* ssm;    // [n_t] S_SM (this same computation at theta_SM)
     const double* mrow;   // [n_t] row factors m_l
-    int n_t;
     double* v;            // [n_t] m_l w_l
     double* out_w;        // [n_t] or null: weights w_l
+    double* out_s;        // [n_t] or null: write S_theta itself and stop
 };
 
 struct FoldArgs {
@@ -82,6 +71,19 @@ struct FoldArgs {
     int rows_per_wg, n_rb, n_cc;
 };
 
+// One launch of the single-point step kernel: nb_fold = n_rb * n_cc
+// work-groups fold the point `fold` describes, nb_rows form the weights of
+// the point `rows` describes (512 rows each), nb_scan = n_src build the
+// node table of the point `scan` describes and nb_fin = n_cc finish the
+// point `fin` describes.  Any of the counts may be zero.
+struct StepArgs {
+    FoldArgs fold;
+    FoldArgs fin;
+    RowArgs rows;
+    ScanArgs scan;
+    int nb_fold, nb_rows, nb_scan, nb_fin;
+};
+
 struct AdjArgs {
     const float* R;
     int ldr, n_t, n_reco;
@@ -100,13 +102,7 @@ struct AdjArgs {
 };
 
 // Launchers (plain.hip)
-hipError_t launch_eint(const EintArgs& a, hipStream_t s);
-hipError_t launch_spectrum_reduce(const double* part, const int* ustart,
-                                  int n_t, double* out, hipStream_t s);
-hipError_t launch_weights(const WeightArgs& a, hipStream_t s);
-hipError_t launch_fold(const FoldArgs& a, hipStream_t s);
-hipError_t launch_fold_stream(const FoldArgs& a, hipStream_t s);
-hipError_t launch_fold_finish(const FoldArgs& a, hipStream_t s);
+hipError_t launch_step(const StepArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t s);
 int adjoint_grid(int n_t);
 

@@ -52,140 +52,134 @@ __device__ inline NodeCoef node_coef(double iE, double nu, double pe,
     return c;
 }
 
-// ---------------------------------------------------------------- a1
-// Eq. (fT): every wave takes one work unit (64 recoil rows x <= 64 energy
-// nodes of one source).  Lane i first builds node i's coefficients; the
-// coefficients are then broadcast from LDS while each lane, owning one
-// recoil row, evaluates nu_j dsigma/dT(E_j, T_l) for every node of the unit
-// and accumulates in FP64.  Pairs beyond the kinematic limit are masked
-// with the host-computed first reachable node jmin(k, l).
-__global__ __launch_bounds__(256) void k_eint(EintArgs a) {
-    __shared__ double4 cs[4][kUnitNodes];
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int u = blockIdx.x * 4 + wave;
-    if (u >= a.n_units) return;
-    const EUnit un = a.units[u];
-    double th[kNTheta];
-#pragma unroll
-    for (int i = 0; i < kNTheta; ++i) th[i] = a.theta[i];
-    const double f = a.srcGroup[un.src] ? th[5] : 1.0;
-    if (lane < un.cnt) {
-        const int j = un.j0 + lane;
-        NodeCoef c = node_coef(a.nodeIE[j], a.nodeW[j] * f, a.nodePe[j], th,
-                               a.ph);
-        cs[wave][lane] = make_double4(c.a0, c.a1, c.a2, c.am);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    const int l = un.block * kRowsPerBlock + lane;
-    const bool rowok = l < a.n_t;
-    const double T = rowok ? a.tc[l] : 1.0;
-    const double iT = 1.0 / T;
-    const int jm = rowok ? a.jmin[(size_t)un.src * a.n_t + l] : 0x7fffffff;
-    int nmask = un.jfull - un.j0;
-    nmask = nmask < 0 ? 0 : (nmask > un.cnt ? un.cnt : nmask);
-    double acc = 0.0;
-    int i = 0;
-    for (; i < nmask; ++i) {
-        const double4 c = cs[wave][i];
-        double t = fma(T, fma(T, c.z, c.y), c.x);
-        t = fma(iT, c.w, t);
-        acc += (un.j0 + i >= jm) ? t : 0.0;
-    }
-    if (rowok) {
-        for (; i < un.cnt; ++i) {
-            const double4 c = cs[wave][i];
-            acc = fma(T, fma(T, c.z, c.y), acc + c.x);
-            acc = fma(iT, c.w, acc);
-        }
-    }
-    a.part[(size_t)u * kRowsPerBlock + lane] = rowok ? acc : 0.0;
-}
-
-// Sum of the unit partials of every recoil row of a 64-row block,
-// S_theta(T_l) = sum_u part[u][l].  Sixteen waves take every sixteenth unit
-// (four loads in flight each) and the per-wave sums are added in a fixed
-// order, so the result is bitwise reproducible and identical in both uses
-// below.
-constexpr int kRowSumThreads = 1024;
-constexpr int kRowSumWaves = kRowSumThreads / 64;
-
-__device__ inline double block_row_sum(const double* __restrict__ part,
-                                       const int* __restrict__ ustart,
-                                       int blk, double* sh) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int u0 = ustart[blk], u1 = ustart[blk + 1];
-    double s = 0.0;
-    int u = u0 + wave;
-    for (; u + 3 * kRowSumWaves < u1; u += 4 * kRowSumWaves) {
-        const double p0 = part[(size_t)u * kRowsPerBlock + lane];
-        const double p1 = part[(size_t)(u + kRowSumWaves) * kRowsPerBlock + lane];
-        const double p2 = part[(size_t)(u + 2 * kRowSumWaves) * kRowsPerBlock + lane];
-        const double p3 = part[(size_t)(u + 3 * kRowSumWaves) * kRowsPerBlock + lane];
-        s += p0;
-        s += p1;
-        s += p2;
-        s += p3;
-    }
-    for (; u < u1; u += kRowSumWaves) s += part[(size_t)u * kRowsPerBlock + lane];
-    sh[wave * kRowsPerBlock + lane] = s;
-    __syncthreads();
-    double t = 0.0;
-    if (wave == 0)
-        for (int w = 0; w < kRowSumWaves; ++w) t += sh[w * kRowsPerBlock + lane];
-    return t;  // valid in wave 0
-}
-
-__global__ __launch_bounds__(kRowSumThreads) void k_spectrum_reduce(
-    const double* __restrict__ part, const int* __restrict__ ustart, int n_t,
-    double* __restrict__ out) {
-    __shared__ double sh[kRowSumWaves * kRowsPerBlock];
-    const int blk = blockIdx.x;
-    const double s = block_row_sum(part, ustart, blk, sh);
-    const int l = blk * kRowsPerBlock + (threadIdx.x & 63);
-    if (threadIdx.x < 64 && l < n_t) out[l] = s;
-}
-
-// a2: weights w_l = S_theta(T_l) / S_SM(T_l) (Eqs. (fT_norm),
-// (reweight_factor)), w_l := 1 where S_SM = 0, and the fold vector
-// v_l = m_l w_l.  S_theta is summed exactly as the SM reference was, so
-// w = 1 exactly at theta_SM.
-__global__ __launch_bounds__(kRowSumThreads) void k_weights(WeightArgs a) {
-    __shared__ double sh[kRowSumWaves * kRowsPerBlock];
-    const int blk = blockIdx.x;
-    const double s = block_row_sum(a.part, a.ustart, blk, sh);
-    const int l = blk * kRowsPerBlock + (threadIdx.x & 63);
-    if (threadIdx.x < 64 && l < a.n_t) {
-        const double ssm = a.ssm[l];
-        const double w = ssm > 0.0 ? s / ssm : 1.0;
-        if (a.out_w) a.out_w[l] = w;
-        a.v[l] = a.mrow[l] * w;
-    }
-}
-
-// ------------------------------------------------------------- a3 - a5
-constexpr int kFoldThreads = 512;          // 8 waves
-constexpr int kFoldWaves = kFoldThreads / 64;
+// The roles of the single-point path run in one kernel, k_step, as separate
+// ranges of work-groups of the same launch: the node table of one point,
+// the weights of another, the R-streaming fold of a third and the
+// likelihood reduction of a fourth.  Consecutive launches on one stream
+// form a software pipeline with no cross-stream waits: launch k builds the
+// table of point k, the weights of point k - 1, folds point k - 2 and
+// reduces point k - 3; stream order is the only synchronisation.
+constexpr int kStepThreads = 512;          // 8 waves in every role
+constexpr int kStepWaves = kStepThreads / 64;
 constexpr int kFoldCols = 256;             // 64 lanes x float4
 constexpr int kFoldUnroll = 8;
 constexpr int kFoldMaxRows = 2048;
+constexpr int kSmemFold = kFoldMaxRows + kStepWaves * (kFoldCols + 1);
+constexpr int kSmemScan = 4 * kStepWaves;
+constexpr int kSmemFin = 2 * kFoldCols + 2 * kStepWaves;
+constexpr int kSmemDoubles = kSmemFold > kSmemFin ? kSmemFold : kSmemFin;
+static_assert(kSmemScan <= kSmemDoubles, "scan scratch");
+static_assert(kStepRows == kStepThreads, "one recoil row per thread");
 
+// ---------------------------------------------------------------- a1
+// Eq. (fT) as a sum over the nodes a recoil bin can reach.  For node j the
+// flux-weighted cross section is a Laurent polynomial in T with
+// coefficients c_j = (a0, a1, a2, am) (node_coef), and the nodes of a source
+// that reach T_l are those with index >= jmin(k, l), a suffix of the
+// E-ordered nodes.  So S_theta(T_l) = sum_k C_k(jmin(k, l)) . (1, T, T^2, 1/T)
+// with the suffix sums C_k(j) = sum_{i >= j} c_i: the same quadrature sum,
+// summed in another order.  One work-group per source builds C_k, 512
+// nodes at a time from the high-energy end: each wave scans its 64 nodes
+// with shuffles, the wave totals of a tile meet in LDS, and a carry holds
+// the sum of the tiles already done.  Table entry j + k holds C_k(j); the
+// entry after the source's last node is zero (no reachable node).
+__device__ inline void suffix_scan_wave(double& x, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double y = __shfl_down(x, o, 64);
+        if (lane + o < 64) x += y;
+    }
+}
 
+__device__ void scan_role(const ScanArgs& a, int k, double* smem) {
+    double4* wt = reinterpret_cast<double4*>(smem);          // [8]
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double th[kNTheta];
+#pragma unroll
+    for (int i = 0; i < kNTheta; ++i) th[i] = a.theta[i];
+    const double f = a.srcGroup[k] ? th[5] : 1.0;
+    const int off = a.srcOff[k], end = a.srcOff[k + 1];
+    double4* tab = a.table + k;  // entry j + k for global node j
+    if (threadIdx.x == 0) tab[end] = make_double4(0.0, 0.0, 0.0, 0.0);
+    double4 carry = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int hi = end; hi > off; hi -= kStepThreads) {
+        // node j = hi - 512 + tid; wave 7 holds the highest 64 nodes
+        const int j = hi - kStepThreads + (int)threadIdx.x;
+        double4 c = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (j >= off) {
+            const NodeCoef q = node_coef(a.nodeIE[j], a.nodeW[j] * f,
+                                         a.nodePe[j], th, a.ph);
+            c = make_double4(q.a0, q.a1, q.a2, q.am);
+        }
+        suffix_scan_wave(c.x, lane);
+        suffix_scan_wave(c.y, lane);
+        suffix_scan_wave(c.z, lane);
+        suffix_scan_wave(c.w, lane);
+        if (lane == 0) wt[wave] = c;  // lane 0 holds the wave's total
+        __syncthreads();
+        double4 add = carry;
+        for (int w = kStepWaves - 1; w > wave; --w) {
+            const double4 t = wt[w];
+            add.x += t.x;
+            add.y += t.y;
+            add.z += t.z;
+            add.w += t.w;
+        }
+        if (j >= off)
+            tab[j] = make_double4(c.x + add.x, c.y + add.y, c.z + add.z,
+                                  c.w + add.w);
+        for (int w = kStepWaves - 1; w >= 0; --w) {
+            const double4 t = wt[w];
+            carry.x += t.x;
+            carry.y += t.y;
+            carry.z += t.z;
+            carry.w += t.w;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- a2
+// S_theta(T_l) from the table (sources added in order, then one Laurent
+// evaluation), then Eqs. (fT_norm), (reweight_factor): w_l = S_theta /
+// S_SM, w_l := 1 where S_SM = 0, and the fold vector v_l = m_l w_l.  The SM
+// reference is formed by this same code, so w = 1 exactly at theta_SM.
+__device__ void rows_role(const RowArgs& a, int blk) {
+    const int l = blk * kStepThreads + (int)threadIdx.x;
+    if (l >= a.n_t) return;
+    double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int k = 0; k < a.n_src; ++k) {
+        const double4 t = a.table[a.jmin[(size_t)k * a.n_t + l] + k];
+        s.x += t.x;
+        s.y += t.y;
+        s.z += t.z;
+        s.w += t.w;
+    }
+    const double T = a.tc[l];
+    const double S = fma(T, fma(T, s.z, s.y), s.x) + s.w / T;
+    if (a.out_s) {
+        a.out_s[l] = S;
+        return;
+    }
+    const double ssm = a.ssm[l];
+    const double w = ssm > 0.0 ? S / ssm : 1.0;
+    if (a.out_w) a.out_w[l] = w;
+    a.v[l] = a.mrow[l] * w;
+}
+
+// ------------------------------------------------------------------ a3
 // Fold through the response (Eqs. (Rij), (fNp_reweight), (mu_total)).
-// Work-group (rb, cc) streams rows [rb*rows, +rows) and columns
-// [cc*256, +256) of R with 16-byte streaming loads, eight rows in flight per
-// wave (the first eight are issued before the weights are staged); the
-// per-row weights v_l = m_l w_l sit in LDS.  R is FP32 in HBM; products and
-// sums are FP64, which the full-rate FP64 vector units of gfx950 absorb at
-// no cost to this bandwidth-bound loop.  The work-group writes its column
-// partial sums; no cross-work-group synchronisation happens here (the
-// partial sums are read by the next kernel).
-__global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
-    __shared__ double vs[kFoldMaxRows];
-    __shared__ double red[kFoldWaves][kFoldCols + 1];
-    const int rb = blockIdx.x, cc = blockIdx.y;
+// Tile (rb, cc) streams rows [rb*rows, +rows) and columns [cc*256, +256) of
+// R with 16-byte streaming loads, eight rows in flight per wave (the first
+// eight are issued before the weights are staged); the per-row weights
+// v_l = m_l w_l sit in LDS.  R is FP32 in HBM; products and sums are FP64,
+// which the full-rate FP64 vector units of gfx950 absorb at no cost to this
+// bandwidth-bound loop.  The tile writes its column partial sums; they are
+// reduced by the finish role of the next launch.
+__device__ void fold_role(const FoldArgs& a, int rb, int cc, double* smem) {
+    double* vs = smem;                                         // [2048]
+    double (*red)[kFoldCols + 1] =
+        reinterpret_cast<double (*)[kFoldCols + 1]>(smem + kFoldMaxRows);
     const int row0 = rb * a.rows_per_wg;
     int nrows = a.n_t - row0;
     if (nrows > a.rows_per_wg) nrows = a.rows_per_wg;
@@ -200,34 +194,34 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
     constexpr int U = kFoldUnroll;
     float4 x[U];
     int r = wave;
-    bool full = colok && r + kFoldWaves * (U - 1) < nrows;
+    bool full = colok && r + kStepWaves * (U - 1) < nrows;
     if (full) {
 #pragma unroll
         for (int q = 0; q < U; ++q)
-            x[q] = ld_stream(Rp + (size_t)(r + q * kFoldWaves) * ld4);
+            x[q] = ld_stream(Rp + (size_t)(r + q * kStepWaves) * ld4);
     }
-    for (int q = tid; q < nrows; q += kFoldThreads) vs[q] = a.v[row0 + q];
+    for (int q = tid; q < nrows; q += kStepThreads) vs[q] = a.v[row0 + q];
     __syncthreads();
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     while (full) {
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const double v = vs[r + q * kFoldWaves];
+            const double v = vs[r + q * kStepWaves];
             acc0 = fma((double)x[q].x, v, acc0);
             acc1 = fma((double)x[q].y, v, acc1);
             acc2 = fma((double)x[q].z, v, acc2);
             acc3 = fma((double)x[q].w, v, acc3);
         }
-        r += kFoldWaves * U;
-        full = r + kFoldWaves * (U - 1) < nrows;
+        r += kStepWaves * U;
+        full = r + kStepWaves * (U - 1) < nrows;
         if (full) {
 #pragma unroll
             for (int q = 0; q < U; ++q)
-                x[q] = ld_stream(Rp + (size_t)(r + q * kFoldWaves) * ld4);
+                x[q] = ld_stream(Rp + (size_t)(r + q * kStepWaves) * ld4);
         }
     }
     if (colok) {
-        for (; r < nrows; r += kFoldWaves) {
+        for (; r < nrows; r += kStepWaves) {
             const float4 z = ld_stream(Rp + (size_t)r * ld4);
             const double v = vs[r];
             acc0 = fma((double)z.x, v, acc0);
@@ -245,49 +239,47 @@ __global__ __launch_bounds__(kFoldThreads) void k_fold(FoldArgs a) {
         const int col = cc * kFoldCols + tid;
         if (col < a.ldr) {
             double s = 0.0;
-            for (int w = 0; w < kFoldWaves; ++w) s += red[w][tid];
+            for (int w = 0; w < kStepWaves; ++w) s += red[w][tid];
             a.colpart[(size_t)rb * a.ldr + col] = s;
         }
     }
 }
 
-// Poisson likelihood (Eq. (logL)) from the fold partials.  Work-group cc
-// owns 256 columns; four threads per column add the row-block partials in a
+// ------------------------------------------------------------- a4, a5
+// Poisson likelihood (Eq. (logL)) from the fold partials.  Chunk cc owns
+// 256 columns; two threads per column add the row-block partials in a
 // fixed order, then mu_j, the deviance mu - n + n ln(n/mu) and
-// a_j = d(-2lnL)/d mu_j.  The chunk sums meet in the last work-group
-// (arrival counter; only the writing wave fences), which adds the data
+// a_j = d(-2lnL)/d mu_j.  The chunk sums meet in the last work-group of the
+// role (arrival counter; only the writing wave fences), which adds the data
 // constant and the pulls.  Deterministic: no float atomics.
-constexpr int kFinThreads = 1024;
-
-__global__ __launch_bounds__(kFinThreads) void k_fold_finish(FoldArgs a) {
-    __shared__ double ps[4][kFoldCols];
-    __shared__ double dred[kFinThreads / 64];
-    __shared__ double gred[kFinThreads / 64];
-    __shared__ int s_last;
-    const int cc = blockIdx.x;
+__device__ void finish_role(const FoldArgs& a, int cc, double* smem,
+                            int* s_last) {
+    double (*ps)[kFoldCols] = reinterpret_cast<double (*)[kFoldCols]>(smem);
+    double* dred = smem + 2 * kFoldCols;
+    double* gred = dred + kStepWaves;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int ci = tid & (kFoldCols - 1), qd = tid >> 8;
     const int col = cc * kFoldCols + ci;
     double s = 0.0;
     if (col < a.n_reco) {
         int q = qd;
-        for (; q + 12 < a.n_rb; q += 16) {
+        for (; q + 6 < a.n_rb; q += 8) {
             const double v0 = a.colpart[(size_t)q * a.ldr + col];
-            const double v1 = a.colpart[(size_t)(q + 4) * a.ldr + col];
-            const double v2 = a.colpart[(size_t)(q + 8) * a.ldr + col];
-            const double v3 = a.colpart[(size_t)(q + 12) * a.ldr + col];
+            const double v1 = a.colpart[(size_t)(q + 2) * a.ldr + col];
+            const double v2 = a.colpart[(size_t)(q + 4) * a.ldr + col];
+            const double v3 = a.colpart[(size_t)(q + 6) * a.ldr + col];
             s += v0;
             s += v1;
             s += v2;
             s += v3;
         }
-        for (; q < a.n_rb; q += 4) s += a.colpart[(size_t)q * a.ldr + col];
+        for (; q < a.n_rb; q += 2) s += a.colpart[(size_t)q * a.ldr + col];
     }
     ps[qd][ci] = s;
     __syncthreads();
     double dev = 0.0, gb = 0.0;
     if (qd == 0 && col < a.n_reco) {
-        const double fold = ps[0][ci] + ps[1][ci] + ps[2][ci] + ps[3][ci];
+        const double fold = ps[0][ci] + ps[1][ci];
         const double bj = a.b[col];
         const double mu = fold + a.theta[6] * bj;
         const double nj = a.n[col];
@@ -312,7 +304,7 @@ __global__ __launch_bounds__(kFinThreads) void k_fold_finish(FoldArgs a) {
     if (wave == 0) {
         double d = 0.0, g = 0.0;
         if (lane == 0) {
-            for (int w = 0; w < kFinThreads / 64; ++w) {
+            for (int w = 0; w < kStepWaves; ++w) {
                 d += dred[w];
                 g += gred[w];
             }
@@ -322,11 +314,11 @@ __global__ __launch_bounds__(kFinThreads) void k_fold_finish(FoldArgs a) {
         __threadfence();
         if (lane == 0) {
             const unsigned prev = atomicAdd(&a.ctr[0], 1u);
-            s_last = prev == (unsigned)(a.n_cc - 1);
+            *s_last = prev == (unsigned)(a.n_cc - 1);
         }
     }
     __syncthreads();
-    if (!s_last || wave != 0) return;
+    if (!*s_last || wave != 0) return;
     __threadfence();
     if (lane == 0) {
         double d = 0.0, g = 0.0;
@@ -344,6 +336,33 @@ __global__ __launch_bounds__(kFinThreads) void k_fold_finish(FoldArgs a) {
         if (a.out_gb) a.out_gb[0] = g;
         a.ctr[0] = 0u;
     }
+}
+
+// Work-groups [0, nb_fold) fold one point, the next nb_rows form the
+// weights of another, the next nb_scan (one per source) build the node
+// table of a third and the last nb_fin finish a fourth.  Fold tiles come
+// first so that every compute unit starts streaming R at once; the short
+// work-groups of the other roles fill the remaining slots.  The role branch
+// is uniform over the work-group.
+__global__ __launch_bounds__(kStepThreads) void k_step(StepArgs a) {
+    __shared__ __attribute__((aligned(16))) double smem[kSmemDoubles];
+    __shared__ int s_last;
+    int b = blockIdx.x;
+    if (b < a.nb_fold) {
+        fold_role(a.fold, b % a.fold.n_rb, b / a.fold.n_rb, smem);
+        return;
+    }
+    b -= a.nb_fold;
+    if (b < a.nb_rows) {
+        rows_role(a.rows, b);
+        return;
+    }
+    b -= a.nb_rows;
+    if (b < a.nb_scan) {
+        scan_role(a.scan, b, smem);
+        return;
+    }
+    finish_role(a.fin, b - a.nb_scan, smem, &s_last);
 }
 
 // ------------------------------------------------------------- adjoint
@@ -471,46 +490,16 @@ __global__ __launch_bounds__(256) void k_adjoint_finish(AdjArgs a, int grid) {
 
 }  // namespace
 
-hipError_t launch_eint(const EintArgs& a, hipStream_t s) {
-    const int grid = (a.n_units + 3) / 4;
-    hipLaunchKernelGGL(k_eint, dim3(grid), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_spectrum_reduce(const double* part, const int* ustart,
-                                  int n_t, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_spectrum_reduce, dim3((n_t + kRowsPerBlock - 1) / kRowsPerBlock),
-                       dim3(kRowSumThreads), 0, s, part, ustart, n_t, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_weights(const WeightArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_weights, dim3((a.n_t + kRowsPerBlock - 1) / kRowsPerBlock),
-                       dim3(kRowSumThreads), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_fold_stream(const FoldArgs& a, hipStream_t s) {
-    if (a.rows_per_wg > kFoldMaxRows || a.rows_per_wg <= 0)
+hipError_t launch_step(const StepArgs& a, hipStream_t s) {
+    if (a.nb_fold > 0 && (a.fold.rows_per_wg > kFoldMaxRows || a.fold.rows_per_wg <= 0 ||
+                          a.nb_fold != a.fold.n_rb * a.fold.n_cc))
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fold, dim3(a.n_rb, a.n_cc), dim3(kFoldThreads), 0, s,
-                       a);
-    return hipGetLastError();
-}
-
-hipError_t launch_fold_finish(const FoldArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_fold_finish, dim3(a.n_cc), dim3(kFinThreads), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_fold(const FoldArgs& a, hipStream_t s) {
-    if (a.rows_per_wg > kFoldMaxRows || a.rows_per_wg <= 0)
+    if (a.nb_fin > 0 && a.nb_fin != a.fin.n_cc) return hipErrorInvalidValue;
+    if (a.nb_rows > 0 && a.nb_rows != (a.rows.n_t + kStepThreads - 1) / kStepThreads)
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_fold, dim3(a.n_rb, a.n_cc), dim3(kFoldThreads), 0, s,
-                       a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_fold_finish, dim3(a.n_cc), dim3(kFinThreads), 0, s, a);
+    const int grid = a.nb_fold + a.nb_rows + a.nb_scan + a.nb_fin;
+    if (grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_step, dim3(grid), dim3(kStepThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -31,6 +31,29 @@ def algorithmic_bytes(n_t, n_reco):
     return 4 * n_t * n_reco + 16 * n_t + 16 * n_reco
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles",
+                               "k_step_plain_16384x4096_hbm_traffic.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2607_00488_amd", "csrc", f)
+                  for f in ("plain.hip", "common.h")]
+
+
+def measured_traffic():
+    """HBM bytes per k_step launch from the committed counter summary, or
+    None when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+        src = b"".join(open(f, "rb").read() for f in KERNEL_SOURCES)
+    except OSError:
+        return None
+    vals = dict(ln.split(": ", 1) for ln in txt.splitlines()
+                if ln.startswith(("traffic_bytes_per_launch:",
+                                  "kernel_source_sha256:")))
+    if vals.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    return int(vals["traffic_bytes_per_launch"])
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -208,7 +231,7 @@ def main():
     achieved = alg_bytes / (step_ms * 1e-3) / 1e9
     roof = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=None, kernel="k_step",
+                traffic=measured_traffic(), kernel="k_step",
                 avg_kernel_us=round(step_ms * 1e3, 2),
                 algorithmic_bytes=alg_bytes)
     res = dict(metric=METRIC, value=round(evals_s, 1), unit="evals/s",

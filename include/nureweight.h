@@ -107,8 +107,12 @@ int nr_set_data(nr_ctx *ctx, const double *n, const double *b, int n_reco,
                 const double *pull_mean, const double *pull_sigma);
 
 /* -2lnL for n_pts points (theta: [n_pts][7], host), one plain single-point
- * evaluation per point: device E-integral, weights, HBM-streaming fold and
- * likelihood reduction.  nll: [n_pts] host.  Synchronous. */
+ * evaluation per point: device E-integral (Eq. (fT) summed per source over
+ * the reachable nodes, as suffix sums of the per-node Laurent coefficients
+ * in T), weights, HBM-streaming fold and likelihood reduction.  Successive
+ * points overlap: one launch folds point p while it forms the weights of
+ * p + 1, the node table of p + 2 and the likelihood of p - 1.  nll:
+ * [n_pts] host.  Synchronous. */
 int nr_eval_nll(nr_ctx *ctx, const double *theta, int n_pts, double *nll);
 
 /* -2lnL and its gradient d(-2lnL)/d theta ([n_pts][7]) per point, through
@@ -130,9 +134,10 @@ int nr_eval_nll_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
 /* Batched form: n_pts points of one analysis at once.  The weights of all
  * points (from the theta-independent recoil basis, exact for Eq. (fT)) form
  * a matrix W[p][l] = m_l w_l(theta_p), and the fold of Eq. (mu_total)
- * becomes the dense product W R on FP32 matrix cores with the Poisson
- * reduction of Eq. (logL) fused into its epilogue.  Synchronous; theta and
- * nll are host arrays as in nr_eval_nll. */
+ * becomes the dense product W R on the FP64 matrix cores (R widened from
+ * FP32 as it is staged) with the Poisson reduction of Eq. (logL) fused into
+ * its epilogue.  Synchronous; theta and nll are host arrays as in
+ * nr_eval_nll. */
 int nr_eval_nll_batched(nr_ctx *ctx, const double *theta, int n_pts,
                         double *nll);
 
@@ -176,13 +181,19 @@ void *nr_stream(nr_ctx *ctx);
 
 /* Average device time in milliseconds of one stage of the single-point
  * path, launched `iters` times back to back on the context stream between
- * HIP events (stage 1: E-integral + weights, 2: fold + likelihood,
- * 3: adjoint, 4: the R-streaming fold kernel alone).  The last evaluated
- * point's inputs are reused.  For roofline measurements. */
+ * HIP events (stage 1: E-integral node table + weights, 2: fold +
+ * likelihood, 3: adjoint, 4: the R-streaming fold alone, 5: the
+ * steady-state launch of the point pipeline, all four roles at once).  The
+ * last evaluated point's inputs are reused; the timing launches write only
+ * library-internal buffers.  For roofline measurements.  NR_ESTATE before
+ * any evaluation (stage 3: before any gradient evaluation). */
 int nr_time_stage(nr_ctx *ctx, int stage, int iters, double *avg_ms);
 
-/* Tuning knobs of the fold kernel (0 keeps the current value): rows per
- * work-group and column chunks; for sweeps. */
+/* Tuning knobs for sweeps.  rows_per_wg > 0: recoil rows per fold tile (a
+ * multiple of 8, at most 2048; 0 keeps the current value; NR_ESTATE before
+ * nr_set_response).  use_graph: 1 replays cached HIP graphs of repeated
+ * (pointer, n_pts) calls, 0 launches every kernel directly, -1 keeps the
+ * current setting.  Drops every cached graph. */
 int nr_set_fold_tiling(nr_ctx *ctx, int rows_per_wg, int use_graph);
 
 /* ---- Learned surrogate (not in the paper): an MLP theta -> log mu_j,

@@ -124,6 +124,78 @@ def time_batched(ctxs, ths, reps=3, grad=False):
                                                 [g.cpu().numpy() for g in gr])
 
 
+def surrogate_form(ctx, train_seconds=20.0):
+    """The learned surrogate at the paper-scale binning: 7 -> 256 -> 256 ->
+    256 -> 4096 SiLU MLP trained on 2^18 spectra from the batched method
+    (prior box), validated on 2^14 held-out points against the exact
+    batched -2lnL, then timed on a batch of 65 536 points with 1 % spot
+    checks and fallback, beside the exact batched method on the same batch."""
+    import torch
+    import synth
+    import paper_2607_00488_amd as nr
+    from paper_2607_00488_amd.surrogate import Surrogate
+    dev = torch.device("cuda:0")
+    lo, hi = synth.theta_box()
+    sur = Surrogate(ctx.n_reco, lo, hi, hidden=256, seed=4001)
+    t0 = time.perf_counter()
+    th_tr = sur.sample_box(1 << 18, 4001)
+    tg = sur.make_targets(ctx, th_tr)
+    t_data = time.perf_counter() - t0
+    info = sur.train(th_tr, tg, epochs=10000, batch=2048, lr_max=1e-3,
+                     log_every=1000, time_limit=train_seconds)
+    del tg
+    th_val = sur.sample_box(1 << 14, 4002)
+    ex_val = torch.empty(1 << 14, dtype=torch.float64, device=dev)
+    nr.eval_nll_multi_dev([ctx], [th_val], [ex_val])
+    nl_val, _ = sur.nll(ctx, th_val)
+    d = (nl_val - ex_val).abs().cpu().numpy()
+    B = 1 << 16
+    th = sur.sample_box(B, 4005)
+    ex = torch.empty(B, dtype=torch.float64, device=dev)
+    s = torch.cuda.current_stream(dev)
+    nr.eval_nll_multi_dev([ctx], [th], [ex], stream=s)   # capture + run
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nr.eval_nll_multi_dev([ctx], [th], [ex], stream=s)
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - t1
+    sur.nll(ctx, th)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sur.nll(ctx, th)
+    torch.cuda.synchronize()
+    t_net = time.perf_counter() - t1
+    out, ev = sur.evaluate(ctx, th, seed=1)              # warm the spot graph
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    out, ev = sur.evaluate(ctx, th, seed=2)
+    torch.cuda.synchronize()
+    t_eval = time.perf_counter() - t1
+    worst_returned = float((out - ex).abs().max().item())
+    sur.close()
+    q = lambda x: float(np.quantile(d, x))
+    return dict(
+        evals_per_s=round(B / t_eval, 1), points=B,
+        ms=round(t_eval * 1e3, 3), fallback=ev["fallback"],
+        fallback_fraction=ev["fallback_fraction"],
+        spot_checks=ev["spot"], spot_worst=ev["spot_worst"],
+        max_abs_dnll_returned=worst_returned,
+        exact_batched_evals_per_s=round(B / t_exact, 1),
+        gain_vs_exact_batched=round(t_exact / t_eval, 3),
+        network_only_evals_per_s=round(B / t_net, 1),
+        network_tflops_bf16=round(B * 2.36e6 / t_net / 1e12, 2),
+        val_abs_dnll=dict(median=q(0.5), q90=q(0.9), max=float(d.max()),
+                          frac_le_0p1=float(np.mean(d <= 0.1)),
+                          frac_le_1=float(np.mean(d <= 1.0))),
+        train=dict(samples=1 << 18, steps=info["steps"],
+                   seconds=round(info["seconds"], 2),
+                   data_seconds=round(t_data, 2),
+                   final_loss=info["losses"][-1][1] if info["losses"] else None),
+        what="MLP 7-256-256-256-4096 SiLU on BF16 matrix cores; -2lnL "
+             "with 1% exact spot checks, fallback to the exact batched "
+             "method when a check misses by more than 0.1")
+
+
 def cpu_baseline(p, n_eval, gpu_ctx):
     """The FP64 oracle on the host cores for a bounded sample of points, and
     the GPU's -2lnL on the same inputs for the |Delta| column."""
@@ -159,6 +231,8 @@ def main():
     ap.add_argument("--cpu-evals", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--surrogate-seconds", type=float, default=20.0)
     ap.add_argument("--counter-pass", action="store_true",
                     help="short run for hardware-counter collection: 20 "
                          "single-point evaluations, then 20 plain 256 MiB "
@@ -279,6 +353,13 @@ def main():
             f"{flops / dt2 / 1e12:.1f} TFLOP/s")
         for cx in ctxs:
             cx.close()
+    if not args.no_surrogate:
+        forms["surrogate"] = sf = surrogate_form(ctx, args.surrogate_seconds)
+        log(f"[bench] surrogate: {sf['evals_per_s']:.0f} evals/s with "
+            f"fallback {sf['fallback']} ({sf['fallback_fraction']:.2f}); "
+            f"network alone {sf['network_only_evals_per_s']:.0f} evals/s; "
+            f"gain {sf['gain_vs_exact_batched']}x; median |d| "
+            f"{sf['val_abs_dnll']['median']:.3g}")
     res["forms"] = forms
     if not args.no_cpu_baseline:
         cb, dmax = cpu_baseline(p, args.cpu_evals, ctx)

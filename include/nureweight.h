@@ -39,7 +39,10 @@
  * points borrow device pointers, enqueue on the given stream and do not
  * synchronise; a NULL stream means the HIP default stream (the work is
  * ordered after what is already on it, and later work on it waits for the
- * results).  A context is not thread-safe.
+ * results).  A context is not thread-safe, and the evaluations of one
+ * context share its device work buffers: work enqueued on different streams
+ * must not overlap in time (the synchronous entry points use the context
+ * stream and wait for it).
  */
 #ifndef NUREWEIGHT_H
 #define NUREWEIGHT_H
@@ -170,6 +173,20 @@ int nr_eval_nll_multi_dev(nr_ctx *const *ctx, int n_ctx,
 /* Weights w_l = S_theta(T_l) / S_SM(T_l) ([n_pts][n_t], host) as the
  * single-point path forms them before the fold.  Synchronous. */
 int nr_eval_weights(nr_ctx *ctx, const double *theta, int n_pts, double *w);
+
+/* Monte-Carlo events generated in each true recoil bin (n_events [n_t],
+ * finite, >= 0): the counts N_lj = R_lj n_events[l] behind the response,
+ * for the effective-sample-size diagnostic.  Needs nr_set_response. */
+int nr_set_mc_events(nr_ctx *ctx, const double *n_events, int n_t);
+
+/* Effective sample size of the reweighted Monte Carlo in every observed
+ * bin, ESS_j = (sum_l N_lj w_l)^2 / sum_l N_lj w_l^2 (0 where no weighted
+ * event lands), with the weights w_l of the single-point path: how many
+ * unweighted events the reweighted prediction of bin j is worth (the
+ * reweighting's statistical support, Sec. V.A).  ESS_j = sum_l N_lj at
+ * theta_SM.  ess: [n_pts][n_reco] host.  NR_ESTATE before
+ * nr_set_mc_events.  Synchronous. */
+int nr_eval_ess(nr_ctx *ctx, const double *theta, int n_pts, double *ess);
 
 /* Copies the recoil spectra the context holds: S_SM [n_t] (device FP64
  * E-integral at theta_SM) and the row factors m [n_t] in use. */

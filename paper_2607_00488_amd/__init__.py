@@ -24,6 +24,7 @@ EXPORTS = (
     "nr_create", "nr_destroy", "nr_set_sources", "nr_set_response",
     "nr_set_data", "nr_eval_nll", "nr_eval_nll_grad", "nr_eval_mu",
     "nr_eval_nll_dev", "nr_eval_weights", "nr_get_reference", "nr_stream",
+    "nr_set_mc_events", "nr_eval_ess",
     "nr_time_stage", "nr_set_fold_tiling", "nr_last_error",
     "nr_eval_nll_batched", "nr_eval_nll_grad_batched", "nr_eval_mu_batched",
     "nr_eval_nll_multi", "nr_eval_nll_multi_dev",
@@ -88,6 +89,8 @@ def load():
     L.nr_eval_nll_grad.argtypes = [P, pD, I, pD, pD]
     L.nr_eval_mu.argtypes = [P, pD, I, pD]
     L.nr_eval_weights.argtypes = [P, pD, I, pD]
+    L.nr_set_mc_events.argtypes = [P, pD, I]
+    L.nr_eval_ess.argtypes = [P, pD, I, pD]
     L.nr_eval_nll_dev.argtypes = [P, P, I, P, P, P]
     L.nr_get_reference.argtypes = [P, pD, pD]
     L.nr_stream.argtypes = [P]
@@ -208,6 +211,18 @@ def nr_eval_mu(h, theta, n_reco):
     th = _f64(theta, (-1, NR_NTHETA))
     out = np.empty((th.shape[0], n_reco))
     _check(load().nr_eval_mu(h, _dp(th), th.shape[0], _dp(out)))
+    return out
+
+
+def nr_set_mc_events(h, n_events):
+    ev = _f64(n_events)
+    _check(load().nr_set_mc_events(h, _dp(ev), int(ev.shape[0])))
+
+
+def nr_eval_ess(h, theta, n_reco):
+    th = _f64(theta, (-1, NR_NTHETA))
+    out = np.empty((th.shape[0], n_reco))
+    _check(load().nr_eval_ess(h, _dp(th), th.shape[0], _dp(out)))
     return out
 
 
@@ -423,6 +438,12 @@ class Context:
 
     def eval_weights(self, theta):
         return nr_eval_weights(self.h, theta, self.n_t)
+
+    def set_mc_events(self, n_events):
+        nr_set_mc_events(self.h, n_events)
+
+    def eval_ess(self, theta):
+        return nr_eval_ess(self.h, theta, self.n_reco)
 
     def reference(self):
         return nr_get_reference(self.h, self.n_t)

@@ -56,23 +56,31 @@ def nll(theta: torch.Tensor, context: Context, batched: bool = True):
 
 
 def lbfgs_fit(context: Context, theta0: torch.Tensor, iters: int = 100,
-              history: int = 10, gtol: float = 1e-5, batched: bool = True):
+              history: int = 10, gtol: float = 1e-5, batched: bool = True,
+              free=None):
     """Independent L-BFGS minimisations of -2lnL from every row of theta0
     ([S, 7]), advanced together: one batched likelihood+gradient call per
     line-search trial for all starts.  Two-loop recursion per start and a
-    backtracking Armijo line search per start.
+    backtracking Armijo line search per start.  ``free``: the indices of the
+    parameters that move (default all seven); the others keep the values
+    theta0 gives them.
 
-    Returns (theta_min [S, 7], nll_min [S], grad_norm [S], n_calls).
+    Returns (theta_min [S, 7], nll_min [S], grad_norm [S], n_calls); the
+    gradient norm is over the free parameters.
     """
     x = theta0.detach().to(torch.float64).clone()
     S, D = x.shape
     dev = x.device
+    mask = torch.ones(D, dtype=torch.float64, device=dev)
+    if free is not None:
+        mask.zero_()
+        mask[list(free)] = 1.0
 
     def fg(th):
         t = th.detach().clone().requires_grad_(True)
         v = nll(t, context, batched)
         v.sum().backward()
-        return v.detach(), t.grad.detach()
+        return v.detach(), t.grad.detach() * mask
 
     f, g = fg(x)
     calls = 1

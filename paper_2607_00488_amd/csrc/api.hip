@@ -2,6 +2,7 @@
 // paragraph and Sec. III.B: the SM reference and the response are built once
 // and kept resident), stream-ordered launches, HIP-graph replay, errors.
 #include "batched.h"
+#include "ess.h"
 #include "mlp.h"
 #include "../../include/nureweight.h"
 
@@ -162,6 +163,8 @@ struct nr_ctx {
     size_t cap_pts = 0, cap_mu = 0, cap_w = 0;
     double* d_thsm = nullptr;
     double* d_tnll = nullptr;  // [1] output of timing-only launches
+    double* d_nev = nullptr;   // [n_t] MC events per true recoil row
+    bool have_nev = false;
     // graphs
     bool use_graph = true;
     std::map<GraphKey, hipGraphExec_t> graphs;
@@ -971,7 +974,7 @@ void nr_destroy(nr_ctx* c) {
     (void)hipDeviceSynchronize();
     clear_graphs(c);
     dfree(&c->d_E); dfree(&c->d_W); dfree(&c->d_Pe); dfree(&c->d_tc);
-    dfree(&c->d_ssm); dfree(&c->d_basis); dfree(&c->d_tnll);
+    dfree(&c->d_ssm); dfree(&c->d_basis); dfree(&c->d_tnll); dfree(&c->d_nev);
     dfree(&c->d_group); dfree(&c->d_jmin); dfree(&c->d_srcoff);
     dfree(&c->d_table[0]); dfree(&c->d_table[1]); dfree(&c->d_R); dfree(&c->d_mrow);
     dfree(&c->d_n); dfree(&c->d_b); dfree(&c->d_colpart);
@@ -1262,6 +1265,56 @@ int nr_eval_nll_grad(nr_ctx* c, const double* theta, int n_pts, double* nll,
 int nr_eval_mu(nr_ctx* c, const double* theta, int n_pts, double* mu) {
     if (!mu) return fail(NR_EINVAL, "mu is null");
     return eval_sync(c, theta, n_pts, nullptr, nullptr, mu, nullptr);
+}
+
+int nr_set_mc_events(nr_ctx* c, const double* n_events, int n_t) {
+    if (!c || !n_events || n_t <= 0) return fail(NR_EINVAL, "null argument or n_t <= 0");
+    if (!c->have_rsp) return fail(NR_ESTATE, "nr_set_mc_events needs nr_set_response first");
+    if (n_t != c->n_t) return fail(NR_EINVAL, "n_t %d differs from the response (%d)", n_t, c->n_t);
+    for (int l = 0; l < n_t; ++l)
+        if (!(std::isfinite(n_events[l]) && n_events[l] >= 0))
+            return fail(NR_EINVAL, "n_events[%d] must be finite and >= 0", l);
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    if ((rc = dalloc(&c->d_nev, n_t))) return rc;
+    HIPCHK(hipMemcpy(c->d_nev, n_events, sizeof(double) * n_t, hipMemcpyHostToDevice));
+    c->have_nev = true;
+    return 0;
+}
+
+int nr_eval_ess(nr_ctx* c, const double* theta, int n_pts, double* ess) {
+    int rc;
+    if (!ess) return fail(NR_EINVAL, "ess is null");
+    if ((rc = check_ready(c))) return rc;
+    if (!c->have_nev) return fail(NR_ESTATE, "nr_eval_ess needs nr_set_mc_events first");
+    if ((rc = check_theta(theta, n_pts))) return rc;
+    if ((rc = set_device(c))) return rc;
+    if ((rc = ensure_stage(c, n_pts, (size_t)n_pts * c->n_reco, c->n_t))) return rc;
+    HIPCHK(hipMemcpyAsync(c->d_th, theta, sizeof(double) * n_pts * NR_NTHETA,
+                          hipMemcpyHostToDevice, c->stream));
+    for (int p = 0; p < n_pts; ++p) {
+        const nr::ScanArgs a1 = scan_args(c, c->d_th + (size_t)p * NR_NTHETA, 0);
+        const nr::RowArgs a2 = row_args(c, 0, c->d_v[0], c->d_w, nullptr);
+        if ((rc = step(c, nullptr, nullptr, &a1, nullptr, c->stream))) return rc;
+        if ((rc = step(c, nullptr, &a2, nullptr, nullptr, c->stream))) return rc;
+        nr::EssArgs ea{};
+        ea.R = c->d_R;
+        ea.ldr = c->ldr;
+        ea.n_t = c->n_t;
+        ea.n_reco = c->n_reco;
+        ea.w = c->d_w;
+        ea.nev = c->d_nev;
+        ea.colpart = c->d_colpart;
+        ea.rows_per_wg = c->rows_per_wg;
+        ea.n_rb = c->n_rb;
+        ea.n_cc = c->n_cc;
+        ea.out = c->d_mu + (size_t)p * c->n_reco;
+        HIPCHK(nr::launch_ess(ea, c->stream));
+    }
+    HIPCHK(hipMemcpyAsync(ess, c->d_mu, sizeof(double) * n_pts * c->n_reco,
+                          hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return 0;
 }
 
 int nr_eval_weights(nr_ctx* c, const double* theta, int n_pts, double* w) {

@@ -24,7 +24,7 @@ def inputs(n_t, n_reco, n_e, n_mc, seed_rsp, seed_data, n_sig=1.0e4,
     n = synth.poisson_data(sig_sm + b, seed_data)
     o.set_data(n, b)
     return dict(src=src, R=rsp.R, b=b, n=n, oracle=o, n_t=n_t, n_reco=n_reco,
-                n_sig=n_sig, t_hi=t_hi)
+                n_sig=n_sig, t_hi=t_hi, row_events=rsp.row_events)
 
 
 def config_inputs(cfg: int):

@@ -25,6 +25,9 @@
  * eps_ee^{L,R} and eps_tautau^{L,R} of Eq. (g_tilde) (eps_mumu = 0),
  * m2 = (mu_nu / 1e-11 mu_B)^2 (the square of the moment of Eq. (xs_mm)),
  * f_8B scales every source with group = 1, f_bkg scales the background b.
+ * A context in the multi-component form (nr_set_components) takes
+ * nr_num_theta(ctx) doubles per point instead; every theta array below has
+ * rows of that length.
  *
  * Status codes: 0 ok; NR_EINVAL (-1) bad argument (null pointer, size <= 0,
  * non-finite value, negative counts, size mismatch between the set_* calls);
@@ -104,8 +107,9 @@ int nr_set_response(nr_ctx *ctx, const float *R, int n_t, int n_reco,
                     const double *m, double n_sig);
 
 /* Binned data n_j >= 0 (real values allowed: Asimov data), background
- * template b_j >= 0 (scaled by f_bkg), and optional Gaussian pulls on the
- * seven parameters (pull_sigma[i] <= 0: no pull on i; both NULL: none). */
+ * template b_j >= 0 (scaled by f_bkg; ignored, and may be NULL, in the
+ * multi-component form), and optional Gaussian pulls on the nr_num_theta
+ * parameters (pull_sigma[i] <= 0: no pull on i; both NULL: none). */
 int nr_set_data(nr_ctx *ctx, const double *n, const double *b, int n_reco,
                 const double *pull_mean, const double *pull_sigma);
 
@@ -174,6 +178,52 @@ int nr_eval_nll_multi_dev(nr_ctx *const *ctx, int n_ctx,
  * single-point path forms them before the fold.  Synchronous. */
 int nr_eval_weights(nr_ctx *ctx, const double *theta, int n_pts, double *w);
 
+/* ---- Multi-component form (Sec. III.B-C, the paper's production
+ * likelihood).  Signal component k (a set of sources) has its own SM Monte
+ * Carlo histogram N^(k)_ij over (true recoil bin i, observed bin j), live-time
+ * mask M^(k)_j and scale s^(k); its response is Eq. (Rij),
+ *   R^(k)_ij = (N^(k)_ij / M^(k)_j) / sum_{i'j'} (N^(k)_i'j' / M^(k)_j') s^(k),
+ * and with the component's recoil spectrum f^(k)_T (Eq. (fT) over its
+ * sources) the prediction of Eqs. (fNp_reweight), (mu_total) is
+ *   mu_j = MT M_j [ sum_k r_k Rate_k sum_i R^(k)_ij w^(k)_i
+ *                   + sum_b r_b Rate_b pdf_b(j) ],
+ * w^(k)_i = f^(k)_T(T_i; theta) / f^(k)_T(T_i; SM) (1 where the SM spectrum
+ * is zero): the rate of a signal component carries its integrated cross
+ * section, so the normalisation of Eq. (fNp_reweight) cancels.  The
+ * parameter vector becomes
+ *   theta = [eps_eL, eps_eR, eps_tauL, eps_tauR, m2, r_1..r_K, r_b1..r_bB]
+ * (nr_num_theta entries; no f_8B / f_bkg: every component has its own rate
+ * r and source groups are ignored).  The fold streams the K responses
+ * stacked row-wise (K N_T rows), so an evaluation reads K times the bytes of
+ * the single-component form. */
+typedef struct {
+    int n_comp;                  /* K >= 1 signal components */
+    const int *comp_of_source;   /* [n_src] component of every source */
+    const float *hist;           /* [K][n_t][n_reco] SM MC histograms, >= 0 */
+    const double *comp_mask;     /* [K][n_reco] M^(k)_j > 0, or NULL (1) */
+    const double *scale;         /* [K] s^(k) > 0 */
+    const double *rate_sm;       /* [K] SM rates Rate_k >= 0 */
+    int n_bkg;                   /* B >= 0 background components */
+    const double *bkg_pdf;       /* [B][n_reco] 1D PDFs pdf_b(j) >= 0 */
+    const double *bkg_rate;      /* [B] rates Rate_b >= 0 */
+    const double *mask;          /* [n_reco] common mask M_j >= 0, or NULL */
+    double exposure;             /* MT > 0 */
+} nr_components;
+
+/* Switch the context to the multi-component form (needs nr_set_sources;
+ * 5 + K + B <= 32).  Replaces any response; the data must be set again
+ * (nr_set_data with b = NULL allowed and pulls of nr_num_theta entries).
+ * Available afterwards: nr_eval_nll, nr_eval_mu, nr_eval_nll_dev without a
+ * gradient, nr_time_stage; the gradient, batched, weights, ESS, reference
+ * and surrogate entry points return NR_ESTATE.  nr_set_response returns to
+ * the single-component form; nr_set_sources drops the components. */
+int nr_set_components(nr_ctx *ctx, const nr_components *cmp, int n_reco);
+
+/* Parameters per point of the context's current form (7 for the
+ * single-component form, 5 + K + B for the multi-component one): the row
+ * length of every theta array and of the pull arrays. */
+int nr_num_theta(nr_ctx *ctx);
+
 /* Monte-Carlo events generated in each true recoil bin (n_events [n_t],
  * finite, >= 0): the counts N_lj = R_lj n_events[l] behind the response,
  * for the effective-sample-size diagnostic.  Needs nr_set_response. */
@@ -201,9 +251,10 @@ void *nr_stream(nr_ctx *ctx);
  * HIP events (stage 1: E-integral node table + weights, 2: fold +
  * likelihood, 3: adjoint, 4: the R-streaming fold alone, 5: the
  * steady-state launch of the point pipeline, all four roles at once).  The
- * last evaluated point's inputs are reused; the timing launches write only
- * library-internal buffers.  For roofline measurements.  NR_ESTATE before
- * any evaluation (stage 3: before any gradient evaluation). */
+ * launches run on the context's own inputs at the SM point (no stage's work
+ * depends on theta) and write only library-internal buffers.  For roofline
+ * measurements.  NR_ESTATE before set_sources, set_response and set_data
+ * (stage 3: also for a multi-component context). */
 int nr_time_stage(nr_ctx *ctx, int stage, int iters, double *avg_ms);
 
 /* Tuning knobs for sweeps.  rows_per_wg > 0: recoil rows per fold tile (a

@@ -24,7 +24,7 @@ EXPORTS = (
     "nr_create", "nr_destroy", "nr_set_sources", "nr_set_response",
     "nr_set_data", "nr_eval_nll", "nr_eval_nll_grad", "nr_eval_mu",
     "nr_eval_nll_dev", "nr_eval_weights", "nr_get_reference", "nr_stream",
-    "nr_set_mc_events", "nr_eval_ess",
+    "nr_set_mc_events", "nr_eval_ess", "nr_set_components", "nr_num_theta",
     "nr_time_stage", "nr_set_fold_tiling", "nr_last_error",
     "nr_eval_nll_batched", "nr_eval_nll_grad_batched", "nr_eval_mu_batched",
     "nr_eval_nll_multi", "nr_eval_nll_multi_dev",
@@ -51,6 +51,17 @@ class nr_source(C.Structure):
 class nr_physics(C.Structure):
     _fields_ = [("me", C.c_double), ("gf", C.c_double), ("sw2", C.c_double),
                 ("alpha_em", C.c_double), ("tau_frac", C.c_double)]
+
+
+class nr_components(C.Structure):
+    _fields_ = [("n_comp", C.c_int), ("comp_of_source", C.POINTER(C.c_int)),
+                ("hist", C.POINTER(C.c_float)),
+                ("comp_mask", C.POINTER(C.c_double)),
+                ("scale", C.POINTER(C.c_double)),
+                ("rate_sm", C.POINTER(C.c_double)), ("n_bkg", C.c_int),
+                ("bkg_pdf", C.POINTER(C.c_double)),
+                ("bkg_rate", C.POINTER(C.c_double)),
+                ("mask", C.POINTER(C.c_double)), ("exposure", C.c_double)]
 
 
 _lib = None
@@ -90,6 +101,8 @@ def load():
     L.nr_eval_mu.argtypes = [P, pD, I, pD]
     L.nr_eval_weights.argtypes = [P, pD, I, pD]
     L.nr_set_mc_events.argtypes = [P, pD, I]
+    L.nr_set_components.argtypes = [P, C.POINTER(nr_components), I]
+    L.nr_num_theta.argtypes = [P]
     L.nr_eval_ess.argtypes = [P, pD, I, pD]
     L.nr_eval_nll_dev.argtypes = [P, P, I, P, P, P]
     L.nr_get_reference.argtypes = [P, pD, pD]
@@ -183,24 +196,75 @@ def nr_set_response(h, R, m=None, n_sig=1.0e4):
                                   R.shape[0], R.shape[1], pm, float(n_sig)))
 
 
+def nr_num_theta(h) -> int:
+    return int(load().nr_num_theta(h))
+
+
 def nr_set_data(h, n, b, pull_mean=None, pull_sigma=None):
-    n, b = _f64(n), _f64(b)
+    n = _f64(n)
+    pb = None
+    if b is not None:
+        b = _f64(b)
+        pb = _dp(b)
     pm = ps = None
     if pull_mean is not None:
+        k = nr_num_theta(h)
         pmv, psv = _f64(pull_mean), _f64(pull_sigma)
+        if pmv.shape != (k,) or psv.shape != (k,):
+            raise ValueError(f"pulls need {k} entries each")
         pm, ps = _dp(pmv), _dp(psv)
-    _check(load().nr_set_data(h, _dp(n), _dp(b), len(n), pm, ps))
+    _check(load().nr_set_data(h, _dp(n), pb, len(n), pm, ps))
+
+
+def nr_set_components(h, comp_of_source, hist, scale, rate_sm, bkg_pdf=None,
+                      bkg_rate=None, comp_mask=None, mask=None, exposure=1.0):
+    """hist: [K, n_t, n_reco] float32; bkg_pdf: [B, n_reco]."""
+    hist = np.ascontiguousarray(hist, dtype=np.float32)
+    K, n_t, n_reco = hist.shape
+    cs = np.ascontiguousarray(comp_of_source, dtype=np.int32)
+    sc, rs = _f64(scale), _f64(rate_sm)
+    if sc.shape != (K,) or rs.shape != (K,):
+        raise ValueError("scale and rate_sm need one entry per component")
+    B = 0 if bkg_pdf is None else int(np.shape(bkg_pdf)[0])
+    keep = [hist, cs, sc, rs]
+    st = nr_components()
+    st.n_comp = K
+    st.comp_of_source = cs.ctypes.data_as(C.POINTER(C.c_int))
+    st.hist = hist.ctypes.data_as(C.POINTER(C.c_float))
+    st.scale, st.rate_sm = _dp(sc), _dp(rs)
+    st.n_bkg = B
+    if B:
+        bp, br = _f64(bkg_pdf), _f64(bkg_rate)
+        if bp.shape != (B, n_reco) or br.shape != (B,):
+            raise ValueError("bkg_pdf is [B, n_reco], bkg_rate [B]")
+        keep += [bp, br]
+        st.bkg_pdf, st.bkg_rate = _dp(bp), _dp(br)
+    if comp_mask is not None:
+        cm = _f64(comp_mask)
+        if cm.shape != (K, n_reco):
+            raise ValueError("comp_mask is [K, n_reco]")
+        keep.append(cm)
+        st.comp_mask = _dp(cm)
+    if mask is not None:
+        m = _f64(mask)
+        if m.shape != (n_reco,):
+            raise ValueError("mask is [n_reco]")
+        keep.append(m)
+        st.mask = _dp(m)
+    st.exposure = float(exposure)
+    _check(load().nr_set_components(h, C.byref(st), n_reco))
+    del keep
 
 
 def nr_eval_nll(h, theta):
-    th = _f64(theta, (-1, NR_NTHETA))
+    th = _f64(theta, (-1, nr_num_theta(h)))
     out = np.empty(th.shape[0])
     _check(load().nr_eval_nll(h, _dp(th), th.shape[0], _dp(out)))
     return out
 
 
 def nr_eval_nll_grad(h, theta):
-    th = _f64(theta, (-1, NR_NTHETA))
+    th = _f64(theta, (-1, nr_num_theta(h)))
     out = np.empty(th.shape[0])
     g = np.empty((th.shape[0], NR_NTHETA))
     _check(load().nr_eval_nll_grad(h, _dp(th), th.shape[0], _dp(out), _dp(g)))
@@ -208,7 +272,7 @@ def nr_eval_nll_grad(h, theta):
 
 
 def nr_eval_mu(h, theta, n_reco):
-    th = _f64(theta, (-1, NR_NTHETA))
+    th = _f64(theta, (-1, nr_num_theta(h)))
     out = np.empty((th.shape[0], n_reco))
     _check(load().nr_eval_mu(h, _dp(th), th.shape[0], _dp(out)))
     return out
@@ -220,14 +284,14 @@ def nr_set_mc_events(h, n_events):
 
 
 def nr_eval_ess(h, theta, n_reco):
-    th = _f64(theta, (-1, NR_NTHETA))
+    th = _f64(theta, (-1, nr_num_theta(h)))
     out = np.empty((th.shape[0], n_reco))
     _check(load().nr_eval_ess(h, _dp(th), th.shape[0], _dp(out)))
     return out
 
 
 def nr_eval_weights(h, theta, n_t):
-    th = _f64(theta, (-1, NR_NTHETA))
+    th = _f64(theta, (-1, nr_num_theta(h)))
     out = np.empty((th.shape[0], n_t))
     _check(load().nr_eval_weights(h, _dp(th), th.shape[0], _dp(out)))
     return out
@@ -263,14 +327,14 @@ def nr_set_fold_tiling(h, rows_per_wg=0, use_graph=-1):
 
 
 def nr_eval_nll_batched(h, theta):
-    th = _f64(theta, (-1, NR_NTHETA))
+    th = _f64(theta, (-1, nr_num_theta(h)))
     out = np.empty(th.shape[0])
     _check(load().nr_eval_nll_batched(h, _dp(th), th.shape[0], _dp(out)))
     return out
 
 
 def nr_eval_nll_grad_batched(h, theta):
-    th = _f64(theta, (-1, NR_NTHETA))
+    th = _f64(theta, (-1, nr_num_theta(h)))
     out = np.empty(th.shape[0])
     g = np.empty((th.shape[0], NR_NTHETA))
     _check(load().nr_eval_nll_grad_batched(h, _dp(th), th.shape[0], _dp(out),
@@ -279,7 +343,7 @@ def nr_eval_nll_grad_batched(h, theta):
 
 
 def nr_eval_mu_batched(h, theta, n_reco):
-    th = _f64(theta, (-1, NR_NTHETA))
+    th = _f64(theta, (-1, nr_num_theta(h)))
     out = np.empty((th.shape[0], n_reco))
     _check(load().nr_eval_mu_batched(h, _dp(th), th.shape[0], _dp(out)))
     return out
@@ -287,7 +351,7 @@ def nr_eval_mu_batched(h, theta, n_reco):
 
 def nr_eval_nll_multi(handles, thetas):
     n = len(handles)
-    ths = [_f64(t, (-1, NR_NTHETA)) for t in thetas]
+    ths = [_f64(t, (-1, nr_num_theta(h))) for h, t in zip(handles, thetas)]
     outs = [np.empty(t.shape[0]) for t in ths]
     H = (C.c_void_p * n)(*[h.value if hasattr(h, "value") else h
                             for h in handles])
@@ -424,6 +488,16 @@ class Context:
         nr_set_response(self.h, R, m, n_sig)
         self.n_t, self.n_reco = int(R.shape[0]), int(R.shape[1])
 
+    def set_components(self, comp_of_source, hist, scale, rate_sm, **kw):
+        """Multi-component form; hist [K, n_t, n_reco]; keywords as in
+        nr_set_components.  The data must be set again afterwards."""
+        nr_set_components(self.h, comp_of_source, hist, scale, rate_sm, **kw)
+        self.n_reco = int(np.shape(hist)[2])
+
+    @property
+    def n_theta(self) -> int:
+        return nr_num_theta(self.h)
+
     def set_data(self, n, b, pull_mean=None, pull_sigma=None):
         nr_set_data(self.h, n, b, pull_mean, pull_sigma)
 
@@ -467,11 +541,16 @@ class Context:
         return nr_eval_mu_batched(self.h, theta, self.n_reco)
 
     def eval_nll_dev(self, theta_t, nll_t, grad_t=None, stream=None):
-        """torch tensors on this device: theta [P,7] f64, nll [P] f64,
-        grad [P,7] f64 or None; enqueued on `stream` (torch stream or None
-        for the context stream)."""
+        """torch tensors on this device: theta [P, n_theta] f64, nll [P]
+        f64, grad [P, 7] f64 or None; enqueued on `stream` (a torch stream,
+        or None for the HIP default stream)."""
         assert theta_t.dtype == nll_t.dtype and str(theta_t.dtype).endswith("float64")
         assert theta_t.is_contiguous() and nll_t.is_contiguous()
+        if theta_t.dim() != 2 or theta_t.shape[1] != self.n_theta:
+            raise ValueError(f"theta must be [P, {self.n_theta}]")
+        if nll_t.numel() < theta_t.shape[0] or (
+                grad_t is not None and grad_t.numel() < 7 * theta_t.shape[0]):
+            raise ValueError("output tensors are too small")
         sp = None if stream is None else stream.cuda_stream
         nr_eval_nll_dev(self.h, theta_t.data_ptr(), theta_t.shape[0],
                         nll_t.data_ptr(),

@@ -149,7 +149,14 @@ struct nr_ctx {
     // data
     double *d_n = nullptr, *d_b = nullptr;
     double cdata = 0;
-    double pull_mean[NR_NTHETA] = {0}, pull_sigma[NR_NTHETA] = {0};
+    double pull_mean[nr::kMaxTheta] = {0}, pull_sigma[nr::kMaxTheta] = {0};
+    // multi-component form (Eqs. (Rij), (fNp_reweight), (mu_total)): the
+    // component responses are stacked row-wise in d_R, n_rows = n_comp * n_t
+    bool multi = false;
+    int n_theta = NR_NTHETA, n_comp = 1, n_bkg = 1, n_rows = 0;
+    std::vector<int> comp_off, comp_src;
+    int *d_compoff = nullptr, *d_compsrc = nullptr, *d_group0 = nullptr;
+    double *d_ssmc = nullptr, *d_bkg = nullptr, *d_mask = nullptr;
     // fold / adjoint scratch
     int rows_per_wg = 0, n_rb = 0, n_cc = 0, adj_grid = 0;
     double *d_colpart = nullptr;  // [2][n_rb][ldr]
@@ -168,12 +175,6 @@ struct nr_ctx {
     // graphs
     bool use_graph = true;
     std::map<GraphKey, hipGraphExec_t> graphs;
-    // last launch arguments (for nr_time_stage)
-    nr::ScanArgs last_s{};
-    nr::RowArgs last_r{};
-    nr::FoldArgs last_f{};
-    nr::AdjArgs last_a{};
-    bool have_last = false, have_last_adj = false;
     // batched (GEMM) path workspace
     int b_cap = 0, b_ldw = 0, b_nnt = 0;
     bool b_grad = false;
@@ -243,7 +244,7 @@ inline bool reach(double me, double E, double T) {
 }
 
 void recompute_mrow(nr_ctx* c) {
-    if (c->m_user || !c->have_src) return;
+    if (c->m_user || !c->have_src || c->multi) return;
     double tot = 0;
     for (int l = 0; l < c->n_t; ++l) tot += c->ssm[l];
     c->mrow.assign(c->n_t, 0.0);
@@ -252,7 +253,7 @@ void recompute_mrow(nr_ctx* c) {
 }
 
 int upload_mrow(nr_ctx* c) {
-    if (!c->have_rsp) return 0;
+    if (!c->have_rsp || c->multi) return 0;
     HIPCHK(hipMemcpy(c->d_mrow, c->mrow.data(), sizeof(double) * c->n_t,
                      hipMemcpyHostToDevice));
     return 0;
@@ -267,15 +268,15 @@ int choose_tiling(nr_ctx* c, int rows_req) {
         // measured on MI355X at 16384 x 4096: 1024-row tiles (16 x 16
         // work-groups) stream fastest and leave 16 partial rows per column
         rows = 1024;
-        if (c->n_t < 16 * 1024) {
+        if (c->n_rows < 16 * 1024) {
             int target_rb = std::max(1, 256 / c->n_cc);
-            rows = (c->n_t + target_rb - 1) / target_rb;
+            rows = (c->n_rows + target_rb - 1) / target_rb;
             rows = std::min(1024, ((rows + 63) / 64) * 64);
         }
     }
     rows = std::max(8, std::min(rows, 2048));
     c->rows_per_wg = rows;
-    c->n_rb = (c->n_t + rows - 1) / rows;
+    c->n_rb = (c->n_rows + rows - 1) / rows;
     int rc;
     if ((rc = dalloc(&c->d_colpart, (size_t)2 * c->n_rb * c->ldr))) return rc;
     if ((rc = dalloc(&c->d_chunk_dev, (size_t)c->n_cc))) return rc;
@@ -292,7 +293,7 @@ int ensure_stage(nr_ctx* c, size_t pts, size_t mu_elems, size_t w_elems) {
     int rc;
     if (pts > c->cap_pts) {
         size_t n = std::max(pts, (size_t)64);
-        if ((rc = dalloc(&c->d_th, n * NR_NTHETA))) return rc;
+        if ((rc = dalloc(&c->d_th, n * nr::kMaxTheta))) return rc;  // any form's theta
         if ((rc = dalloc(&c->d_out, n))) return rc;
         if ((rc = dalloc(&c->d_grad, n * NR_NTHETA))) return rc;
         c->cap_pts = n;
@@ -316,7 +317,8 @@ nr::ScanArgs scan_args(nr_ctx* c, const double* d_theta, int par) {
     a.nodeW = c->d_W;
     a.nodePe = c->d_Pe;
     a.srcOff = c->d_srcoff;
-    a.srcGroup = c->d_group;
+    // the multi-component form scales components by their rates instead
+    a.srcGroup = c->multi ? c->d_group0 : c->d_group;
     a.theta = d_theta;
     a.ph = c->ph;
     a.table = reinterpret_cast<double4*>(c->d_table[par]);
@@ -324,15 +326,20 @@ nr::ScanArgs scan_args(nr_ctx* c, const double* d_theta, int par) {
 }
 
 nr::RowArgs row_args(nr_ctx* c, int par, double* v, double* out_w,
-                     double* out_s) {
+                     double* out_s, const double* d_theta) {
     nr::RowArgs a{};
     a.table = reinterpret_cast<const double4*>(c->d_table[par]);
     a.jmin = c->d_jmin;
     a.tc = c->d_tc;
     a.n_t = c->n_t;
-    a.n_src = c->n_src;
-    a.ssm = c->d_ssm;
+    a.n_comp = c->multi ? c->n_comp : 1;
+    a.compOff = c->d_compoff;
+    a.compSrc = c->d_compsrc;
+    a.ssm = c->multi ? c->d_ssmc : c->d_ssm;
     a.mrow = c->d_mrow;
+    a.theta = nullptr;
+    a.rate_index = c->multi ? 5 : -1;
+    a.theta = d_theta;
     a.v = v;
     a.out_w = out_w;
     a.out_s = out_s;
@@ -344,11 +351,15 @@ nr::FoldArgs fold_args(nr_ctx* c, const double* thp, const double* v,
     nr::FoldArgs fa{};
     fa.R = c->d_R;
     fa.ldr = c->ldr;
-    fa.n_t = c->n_t;
+    fa.n_t = c->n_rows;
     fa.n_reco = c->n_reco;
     fa.v = v;
     fa.n = c->d_n;
-    fa.b = c->d_b;
+    fa.b = c->multi ? c->d_bkg : c->d_b;
+    fa.n_bkg = c->multi ? c->n_bkg : 1;
+    fa.bkg_index = c->multi ? 5 + c->n_comp : 6;
+    fa.mask = c->multi ? c->d_mask : nullptr;
+    fa.n_theta = c->n_theta;
     fa.theta = thp;
     fa.colpart = colpart;
     fa.ctr = c->d_ctr;
@@ -359,7 +370,7 @@ nr::FoldArgs fold_args(nr_ctx* c, const double* thp, const double* v,
     fa.out_a = grad ? c->d_a : nullptr;
     fa.out_gb = grad ? c->d_gb : nullptr;
     fa.cdata = c->cdata;
-    for (int i = 0; i < NR_NTHETA; ++i) {
+    for (int i = 0; i < c->n_theta; ++i) {
         fa.pull_mean[i] = c->pull_mean[i];
         fa.pull_sigma[i] = c->pull_sigma[i];
     }
@@ -378,7 +389,7 @@ int step(nr_ctx* c, const nr::FoldArgs* fold, const nr::RowArgs* rows,
     }
     if (rows) {
         a.rows = *rows;
-        a.nb_rows = c->n_blocks;
+        a.nb_rows = (rows->n_comp * c->n_t + nr::kStepRows - 1) / nr::kStepRows;
     }
     if (scan) {
         a.scan = *scan;
@@ -403,11 +414,11 @@ int step(nr_ctx* c, const nr::FoldArgs* fold, const nr::RowArgs* rows,
 int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
                    double* grad, double* mu, double* w, hipStream_t s) {
     const size_t cp = (size_t)c->n_rb * c->ldr;
-    auto thp = [&](int p) { return th + (size_t)p * NR_NTHETA; };
+    auto thp = [&](int p) { return th + (size_t)p * c->n_theta; };
     auto sa = [&](int p) { return scan_args(c, thp(p), p & 1); };
     auto ra = [&](int p) {
         return row_args(c, p & 1, c->d_v[p & 1],
-                        w ? w + (size_t)p * c->n_t : nullptr, nullptr);
+                        w ? w + (size_t)p * c->n_rows : nullptr, nullptr, thp(p));
     };
     auto fa = [&](int p) {
         return fold_args(c, thp(p), c->d_v[p & 1], c->d_colpart + (p & 1) * cp,
@@ -429,10 +440,6 @@ int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
                            in(k) ? &a1 : nullptr, in(k - 3) ? &a4 : nullptr, s)))
                 return rc;
         }
-        c->last_s = sa(n_pts - 1);
-        c->last_r = ra(n_pts - 1);
-        c->last_f = fa(n_pts - 1);
-        c->have_last = true;
         return 0;
     }
     for (int p = 0; p < n_pts; ++p) {
@@ -463,12 +470,6 @@ int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
         }
         aa.ph = c->ph;
         HIPCHK(nr::launch_adjoint(aa, c->adj_grid, s));
-        c->last_s = a1;
-        c->last_r = a2;
-        c->last_f = f;
-        c->last_a = aa;
-        c->have_last = true;
-        c->have_last_adj = true;
     }
     return 0;
 }
@@ -509,10 +510,18 @@ int check_ready(nr_ctx* c) {
     return 0;
 }
 
-int check_theta(const double* th, int n_pts) {
+int check_theta(const double* th, int n_pts, int n_theta = NR_NTHETA) {
     if (!th || n_pts <= 0) return fail(NR_EINVAL, "theta null or n_pts <= 0");
-    if (!finite_all(th, (size_t)n_pts * NR_NTHETA))
+    if (!finite_all(th, (size_t)n_pts * n_theta))
         return fail(NR_EINVAL, "non-finite theta");
+    return 0;
+}
+
+// Entry points of the single-component form only (gradient, batched,
+// diagnostics, surrogate) refuse a multi-component context.
+int check_single(nr_ctx* c) {
+    if (c && c->multi)
+        return fail(NR_ESTATE, "not available for a multi-component context");
     return 0;
 }
 
@@ -896,6 +905,7 @@ int check_multi(nr_ctx* const* ctx, int n_ctx, const int* n_pts) {
     for (int d = 0; d < n_ctx; ++d) {
         int rc;
         if ((rc = check_ready(ctx[d]))) return rc;
+        if ((rc = check_single(ctx[d]))) return rc;
         if (n_pts[d] <= 0) return fail(NR_EINVAL, "n_pts[%d] <= 0", d);
         if (ctx[d]->device != ctx[0]->device)
             return fail(NR_EINVAL, "all contexts of a grouped call share one device");
@@ -907,6 +917,7 @@ int batched_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
                  double* grad, double* mu) {
     int rc;
     if ((rc = check_ready(c))) return rc;
+    if ((rc = check_single(c))) return rc;
     if ((rc = check_theta(theta, n_pts))) return rc;
     if ((rc = set_device(c))) return rc;
     if ((rc = ensure_batch(c, n_pts, grad != nullptr, mu ? (size_t)n_pts * c->n_reco : 0)))
@@ -956,13 +967,15 @@ int nr_create(int device, nr_ctx** out) {
         delete c;
         return fail(NR_EHIP, "stream creation: %s", hipGetErrorString(e));
     }
-    if (dalloc(&c->d_a, 1) || dalloc(&c->d_gb, 1) || dalloc(&c->d_thsm, NR_NTHETA) ||
-        dalloc(&c->d_gctr, 4) || dalloc(&c->d_tnll, 1)) {
+    if (dalloc(&c->d_a, 1) || dalloc(&c->d_gb, 1) || dalloc(&c->d_thsm, nr::kMaxTheta) ||
+        dalloc(&c->d_gctr, 4) || dalloc(&c->d_tnll, 1 + NR_NTHETA)) {
         delete c;
         return NR_ENOMEM;
     }
     (void)hipMemset(c->d_gctr, 0, 4 * sizeof(unsigned));
-    const double sm[NR_NTHETA] = {0, 0, 0, 0, 0, 1, 1};
+    // the SM point of either form: NSI and m2 zero, every rate one
+    double sm[nr::kMaxTheta];
+    for (int i = 0; i < nr::kMaxTheta; ++i) sm[i] = i < 5 ? 0.0 : 1.0;
     (void)hipMemcpy(c->d_thsm, sm, sizeof(sm), hipMemcpyHostToDevice);
     *out = c;
     return 0;
@@ -975,6 +988,8 @@ void nr_destroy(nr_ctx* c) {
     clear_graphs(c);
     dfree(&c->d_E); dfree(&c->d_W); dfree(&c->d_Pe); dfree(&c->d_tc);
     dfree(&c->d_ssm); dfree(&c->d_basis); dfree(&c->d_tnll); dfree(&c->d_nev);
+    dfree(&c->d_compoff); dfree(&c->d_compsrc); dfree(&c->d_group0);
+    dfree(&c->d_ssmc); dfree(&c->d_bkg); dfree(&c->d_mask);
     dfree(&c->d_group); dfree(&c->d_jmin); dfree(&c->d_srcoff);
     dfree(&c->d_table[0]); dfree(&c->d_table[1]); dfree(&c->d_R); dfree(&c->d_mrow);
     dfree(&c->d_n); dfree(&c->d_b); dfree(&c->d_colpart);
@@ -1044,10 +1059,17 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
     if (!(wmax > 0)) return fail(NR_EINVAL, "all source weights are zero");
     // S is linear in the weights and only ratios enter w; scale to O(1).
     for (double& w : c->hW) w /= wmax;
+    if (c->multi) {  // new sources drop the components built on the old ones
+        c->multi = false;
+        c->have_rsp = c->have_data = false;
+        c->n_theta = NR_NTHETA;
+        c->n_comp = c->n_bkg = 1;
+    }
     c->n_src = n_src;
     c->n_nodes = (int)c->hE.size();
     c->src_off[n_src] = c->n_nodes;
     c->n_t = n_t;
+    c->n_rows = n_t;
     c->t_lo = t_lo;
     c->t_hi = t_hi;
     c->tc.resize(n_t);
@@ -1099,6 +1121,8 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
         (rc = dalloc(&c->d_ssm, n_t)) || (rc = dalloc(&c->d_group, n_src)) ||
         (rc = dalloc(&c->d_jmin, (size_t)n_src * n_t)) ||
         (rc = dalloc(&c->d_srcoff, n_src + 1)) ||
+        (rc = dalloc(&c->d_compoff, n_src + 1)) || (rc = dalloc(&c->d_compsrc, n_src)) ||
+        (rc = dalloc(&c->d_group0, n_src)) ||
         (rc = dalloc(&c->d_table[0], (size_t)4 * (c->n_nodes + n_src))) ||
         (rc = dalloc(&c->d_table[1], (size_t)4 * (c->n_nodes + n_src))) ||
         (rc = dalloc(&c->d_basis, (size_t)nr::kNBasis * n_t)) ||
@@ -1115,12 +1139,19 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
     HIPCHK(hipMemcpy(c->d_group, c->src_group.data(), sizeof(int) * n_src, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_jmin, c->jmin.data(), sizeof(int) * c->jmin.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_srcoff, c->src_off.data(), sizeof(int) * (n_src + 1), hipMemcpyHostToDevice));
+    // the single-component form: one component holding every source
+    c->comp_off = {0, n_src};
+    c->comp_src.resize(n_src);
+    for (int k = 0; k < n_src; ++k) c->comp_src[k] = k;
+    HIPCHK(hipMemcpy(c->d_compoff, c->comp_off.data(), sizeof(int) * 2, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_compsrc, c->comp_src.data(), sizeof(int) * n_src, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(c->d_group0, 0, sizeof(int) * n_src));
     HIPCHK(hipMemcpy(c->d_basis, c->basis.data(), sizeof(double) * c->basis.size(), hipMemcpyHostToDevice));
     // SM reference on the device with the same E-integral code the
     // evaluations use, so that w = S_theta / S_SM is exactly 1 at theta_SM.
     {
         const nr::ScanArgs sa = scan_args(c, c->d_thsm, 0);
-        const nr::RowArgs ra = row_args(c, 0, nullptr, nullptr, c->d_ssm);
+        const nr::RowArgs ra = row_args(c, 0, nullptr, nullptr, c->d_ssm, c->d_thsm);
         if ((rc = step(c, nullptr, nullptr, &sa, nullptr, c->stream))) return rc;
         if ((rc = step(c, nullptr, &ra, nullptr, nullptr, c->stream))) return rc;
     }
@@ -1153,7 +1184,24 @@ int nr_set_response(nr_ctx* c, const float* R, int n_t, int n_reco,
         if (!std::isfinite(R[i])) return fail(NR_EINVAL, "non-finite R at %zu", i);
     int rc;
     if ((rc = set_device(c))) return rc;
+    if (c->multi) {  // back to the single-component form
+        c->multi = false;
+        c->have_data = false;
+        c->n_theta = NR_NTHETA;
+        c->n_comp = c->n_bkg = 1;
+        if (c->have_src) {
+            if ((rc = dalloc(&c->d_v[0], n_t)) || (rc = dalloc(&c->d_v[1], n_t))) return rc;
+            c->comp_off = {0, c->n_src};
+            c->comp_src.resize(c->n_src);
+            for (int q = 0; q < c->n_src; ++q) c->comp_src[q] = q;
+            HIPCHK(hipMemcpy(c->d_compoff, c->comp_off.data(), sizeof(int) * 2,
+                             hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(c->d_compsrc, c->comp_src.data(), sizeof(int) * c->n_src,
+                             hipMemcpyHostToDevice));
+        }
+    }
     c->n_t = n_t;
+    c->n_rows = n_t;
     c->n_reco = n_reco;
     c->ldr = (n_reco + 3) / 4 * 4;
     if ((rc = dalloc(&c->d_R, (size_t)n_t * c->ldr))) return rc;
@@ -1175,31 +1223,33 @@ int nr_set_response(nr_ctx* c, const float* R, int n_t, int n_reco,
 
 int nr_set_data(nr_ctx* c, const double* n, const double* b, int n_reco,
                 const double* pull_mean, const double* pull_sigma) {
-    if (!c || !n || !b || n_reco <= 0) return fail(NR_EINVAL, "null argument or n_reco <= 0");
+    if (!c || !n || n_reco <= 0) return fail(NR_EINVAL, "null argument or n_reco <= 0");
+    if (!b && !c->multi) return fail(NR_EINVAL, "b is null");
     if (c->have_rsp && n_reco != c->n_reco)
         return fail(NR_EINVAL, "n_reco %d differs from the response (%d)", n_reco, c->n_reco);
     if ((pull_mean == nullptr) != (pull_sigma == nullptr))
         return fail(NR_EINVAL, "pull_mean and pull_sigma must both be given or both NULL");
     for (int j = 0; j < n_reco; ++j) {
         if (!(std::isfinite(n[j]) && n[j] >= 0)) return fail(NR_EINVAL, "n[%d] must be finite and >= 0", j);
-        if (!(std::isfinite(b[j]) && b[j] >= 0)) return fail(NR_EINVAL, "b[%d] must be finite and >= 0", j);
+        if (b && !(std::isfinite(b[j]) && b[j] >= 0)) return fail(NR_EINVAL, "b[%d] must be finite and >= 0", j);
     }
-    if (pull_mean && (!finite_all(pull_mean, NR_NTHETA) || !finite_all(pull_sigma, NR_NTHETA)))
+    if (pull_mean && (!finite_all(pull_mean, c->n_theta) || !finite_all(pull_sigma, c->n_theta)))
         return fail(NR_EINVAL, "non-finite pulls");
     int rc;
     if ((rc = set_device(c))) return rc;
     if ((rc = dalloc(&c->d_n, n_reco)) || (rc = dalloc(&c->d_b, n_reco))) return rc;
     HIPCHK(hipMemcpy(c->d_n, n, sizeof(double) * n_reco, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(c->d_b, b, sizeof(double) * n_reco, hipMemcpyHostToDevice));
+    if (b) HIPCHK(hipMemcpy(c->d_b, b, sizeof(double) * n_reco, hipMemcpyHostToDevice));
+    else HIPCHK(hipMemset(c->d_b, 0, sizeof(double) * n_reco));
     // data-only constant of Eq. (logL): the device reduces the deviance
     // mu - n + n ln(n/mu); -2lnL = 2 (deviance + C_data) + pulls.
     double cd = 0;
     for (int j = 0; j < n_reco; ++j)
         cd += n[j] - (n[j] > 0 ? n[j] * std::log(n[j]) : 0.0) + std::lgamma(n[j] + 1.0);
     c->cdata = cd;
-    for (int i = 0; i < NR_NTHETA; ++i) {
-        c->pull_mean[i] = pull_mean ? pull_mean[i] : 0.0;
-        c->pull_sigma[i] = pull_sigma ? pull_sigma[i] : 0.0;
+    for (int i = 0; i < nr::kMaxTheta; ++i) {
+        c->pull_mean[i] = pull_mean && i < c->n_theta ? pull_mean[i] : 0.0;
+        c->pull_sigma[i] = pull_sigma && i < c->n_theta ? pull_sigma[i] : 0.0;
     }
     c->n_reco = n_reco;
     c->have_data = true;
@@ -1213,6 +1263,7 @@ int nr_eval_nll_dev(nr_ctx* c, const double* d_theta, int n_pts, double* d_nll,
     if ((rc = check_ready(c))) return rc;
     if (!d_theta || !d_nll || n_pts <= 0)
         return fail(NR_EINVAL, "null device pointer or n_pts <= 0");
+    if (d_grad && (rc = check_single(c))) return rc;
     if ((rc = set_device(c))) return rc;
     Bridge br;
     if ((rc = bridge_begin(br, stream, c->stream, c->ev_in, c->ev_out))) return rc;
@@ -1225,12 +1276,13 @@ static int eval_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
                      double* grad, double* mu, double* w) {
     int rc;
     if ((rc = check_ready(c))) return rc;
-    if ((rc = check_theta(theta, n_pts))) return rc;
+    if ((grad || w) && (rc = check_single(c))) return rc;
+    if ((rc = check_theta(theta, n_pts, c->n_theta))) return rc;
     if ((rc = set_device(c))) return rc;
     if ((rc = ensure_stage(c, n_pts, mu ? (size_t)n_pts * c->n_reco : 0,
                            w ? (size_t)n_pts * c->n_t : 0)))
         return rc;
-    HIPCHK(hipMemcpyAsync(c->d_th, theta, sizeof(double) * n_pts * NR_NTHETA,
+    HIPCHK(hipMemcpyAsync(c->d_th, theta, sizeof(double) * n_pts * c->n_theta,
                           hipMemcpyHostToDevice, c->stream));
     rc = run_points(c, c->d_th, n_pts, c->d_out, grad ? c->d_grad : nullptr,
                     mu ? c->d_mu : nullptr, w ? c->d_w : nullptr, c->stream);
@@ -1269,6 +1321,7 @@ int nr_eval_mu(nr_ctx* c, const double* theta, int n_pts, double* mu) {
 
 int nr_set_mc_events(nr_ctx* c, const double* n_events, int n_t) {
     if (!c || !n_events || n_t <= 0) return fail(NR_EINVAL, "null argument or n_t <= 0");
+    if (int rc = check_single(c)) return rc;
     if (!c->have_rsp) return fail(NR_ESTATE, "nr_set_mc_events needs nr_set_response first");
     if (n_t != c->n_t) return fail(NR_EINVAL, "n_t %d differs from the response (%d)", n_t, c->n_t);
     for (int l = 0; l < n_t; ++l)
@@ -1286,6 +1339,7 @@ int nr_eval_ess(nr_ctx* c, const double* theta, int n_pts, double* ess) {
     int rc;
     if (!ess) return fail(NR_EINVAL, "ess is null");
     if ((rc = check_ready(c))) return rc;
+    if ((rc = check_single(c))) return rc;
     if (!c->have_nev) return fail(NR_ESTATE, "nr_eval_ess needs nr_set_mc_events first");
     if ((rc = check_theta(theta, n_pts))) return rc;
     if ((rc = set_device(c))) return rc;
@@ -1294,7 +1348,8 @@ int nr_eval_ess(nr_ctx* c, const double* theta, int n_pts, double* ess) {
                           hipMemcpyHostToDevice, c->stream));
     for (int p = 0; p < n_pts; ++p) {
         const nr::ScanArgs a1 = scan_args(c, c->d_th + (size_t)p * NR_NTHETA, 0);
-        const nr::RowArgs a2 = row_args(c, 0, c->d_v[0], c->d_w, nullptr);
+        const nr::RowArgs a2 = row_args(c, 0, c->d_v[0], c->d_w, nullptr,
+                                        c->d_th + (size_t)p * NR_NTHETA);
         if ((rc = step(c, nullptr, nullptr, &a1, nullptr, c->stream))) return rc;
         if ((rc = step(c, nullptr, &a2, nullptr, nullptr, c->stream))) return rc;
         nr::EssArgs ea{};
@@ -1317,6 +1372,137 @@ int nr_eval_ess(nr_ctx* c, const double* theta, int n_pts, double* ess) {
     return 0;
 }
 
+int nr_num_theta(nr_ctx* c) { return c ? c->n_theta : NR_EINVAL; }
+
+int nr_set_components(nr_ctx* c, const nr_components* k, int n_reco) {
+    if (!c || !k || n_reco <= 0) return fail(NR_EINVAL, "null argument or n_reco <= 0");
+    if (!c->have_src) return fail(NR_ESTATE, "nr_set_components needs nr_set_sources first");
+    const int K = k->n_comp, B = k->n_bkg, n_t = c->n_t, n_src = c->n_src;
+    if (K <= 0 || B < 0 || 5 + K + B > nr::kMaxTheta)
+        return fail(NR_EINVAL, "need n_comp >= 1, n_bkg >= 0 and 5 + n_comp + n_bkg <= %d",
+                    nr::kMaxTheta);
+    if (!k->comp_of_source || !k->hist || !k->scale || !k->rate_sm ||
+        (B > 0 && (!k->bkg_pdf || !k->bkg_rate)))
+        return fail(NR_EINVAL, "null component or background array");
+    if (!(std::isfinite(k->exposure) && k->exposure > 0))
+        return fail(NR_EINVAL, "exposure must be finite and > 0");
+    // sources grouped by component, in source order within a component
+    std::vector<int> off(K + 1, 0), src(n_src);
+    for (int s = 0; s < n_src; ++s) {
+        const int q = k->comp_of_source[s];
+        if (q < 0 || q >= K) return fail(NR_EINVAL, "source %d: component %d out of range", s, q);
+        ++off[q + 1];
+    }
+    for (int q = 0; q < K; ++q) {
+        if (off[q + 1] == 0) return fail(NR_EINVAL, "component %d has no source", q);
+        off[q + 1] += off[q];
+    }
+    {
+        std::vector<int> fill(off.begin(), off.end() - 1);
+        for (int s = 0; s < n_src; ++s) src[fill[k->comp_of_source[s]]++] = s;
+    }
+    for (int q = 0; q < K; ++q) {
+        if (!(std::isfinite(k->scale[q]) && k->scale[q] > 0))
+            return fail(NR_EINVAL, "scale[%d] must be finite and > 0", q);
+        if (!(std::isfinite(k->rate_sm[q]) && k->rate_sm[q] >= 0))
+            return fail(NR_EINVAL, "rate_sm[%d] must be finite and >= 0", q);
+    }
+    for (int b = 0; b < B; ++b) {
+        if (!(std::isfinite(k->bkg_rate[b]) && k->bkg_rate[b] >= 0))
+            return fail(NR_EINVAL, "bkg_rate[%d] must be finite and >= 0", b);
+        for (int j = 0; j < n_reco; ++j) {
+            const double v = k->bkg_pdf[(size_t)b * n_reco + j];
+            if (!(std::isfinite(v) && v >= 0))
+                return fail(NR_EINVAL, "bkg_pdf[%d][%d] must be finite and >= 0", b, j);
+        }
+    }
+    if (k->mask)
+        for (int j = 0; j < n_reco; ++j)
+            if (!(std::isfinite(k->mask[j]) && k->mask[j] >= 0))
+                return fail(NR_EINVAL, "mask[%d] must be finite and >= 0", j);
+    // Eq. (Rij): R^(k)_ij = (N^(k)_ij / M^(k)_j) / sum_{i'j'} (N^(k)_i'j' / M^(k)_j')
+    // x s^(k), formed in FP64 and stored in FP32, the components stacked
+    // row-wise
+    const int ldr = (n_reco + 3) / 4 * 4;
+    const size_t n_rows = (size_t)K * n_t;
+    std::vector<float> Rs(n_rows * ldr, 0.0f);
+    for (int q = 0; q < K; ++q) {
+        const float* N = k->hist + (size_t)q * n_t * n_reco;
+        const double* M = k->comp_mask ? k->comp_mask + (size_t)q * n_reco : nullptr;
+        double tot = 0.0;
+        for (int i = 0; i < n_t; ++i)
+            for (int j = 0; j < n_reco; ++j) {
+                const double v = N[(size_t)i * n_reco + j];
+                if (!(std::isfinite(v) && v >= 0))
+                    return fail(NR_EINVAL, "hist[%d][%d][%d] must be finite and >= 0", q, i, j);
+                if (v == 0.0) continue;
+                if (M && !(std::isfinite(M[j]) && M[j] > 0))
+                    return fail(NR_EINVAL, "comp_mask[%d][%d] must be > 0 where the histogram is not", q, j);
+                tot += M ? v / M[j] : v;
+            }
+        if (!(tot > 0)) return fail(NR_EINVAL, "component %d: empty histogram", q);
+        const double f = k->scale[q] / tot;
+        for (int i = 0; i < n_t; ++i)
+            for (int j = 0; j < n_reco; ++j) {
+                const double v = N[(size_t)i * n_reco + j];
+                if (v != 0.0)
+                    Rs[((size_t)q * n_t + i) * ldr + j] = (float)((M ? v / M[j] : v) * f);
+            }
+    }
+    // Eq. (mu_total): MT x rate; the signal rows carry MT Rate_SM,k (the
+    // theta-dependent share of the rate comes with the unnormalised weights
+    // and the component's rate parameter), the templates MT Rate_b f_b,j.
+    std::vector<double> mrow(n_rows), bkg((size_t)std::max(B, 1) * n_reco, 0.0);
+    for (int q = 0; q < K; ++q)
+        for (int i = 0; i < n_t; ++i) mrow[(size_t)q * n_t + i] = k->exposure * k->rate_sm[q];
+    for (int b = 0; b < B; ++b)
+        for (int j = 0; j < n_reco; ++j)
+            bkg[(size_t)b * n_reco + j] =
+                k->exposure * k->bkg_rate[b] * k->bkg_pdf[(size_t)b * n_reco + j];
+    int rc;
+    if ((rc = set_device(c))) return rc;
+    clear_graphs(c);
+    if ((rc = dalloc(&c->d_R, n_rows * ldr)) || (rc = dalloc(&c->d_mrow, n_rows)) ||
+        (rc = dalloc(&c->d_bkg, bkg.size())) || (rc = dalloc(&c->d_ssmc, n_rows)) ||
+        (rc = dalloc(&c->d_v[0], n_rows)) || (rc = dalloc(&c->d_v[1], n_rows)) ||
+        (rc = dalloc(&c->d_compoff, K + 1)) || (rc = dalloc(&c->d_compsrc, n_src)) ||
+        (rc = dalloc(&c->d_a, ldr)))
+        return rc;
+    dfree(&c->d_mask);
+    if (k->mask) {
+        if ((rc = dalloc(&c->d_mask, n_reco))) return rc;
+        HIPCHK(hipMemcpy(c->d_mask, k->mask, sizeof(double) * n_reco, hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemcpy(c->d_R, Rs.data(), sizeof(float) * Rs.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_mrow, mrow.data(), sizeof(double) * n_rows, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_bkg, bkg.data(), sizeof(double) * bkg.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_compoff, off.data(), sizeof(int) * (K + 1), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->d_compsrc, src.data(), sizeof(int) * n_src, hipMemcpyHostToDevice));
+    c->comp_off = off;
+    c->comp_src = src;
+    c->multi = true;
+    c->n_comp = K;
+    c->n_bkg = B;
+    c->n_theta = 5 + K + B;
+    c->n_rows = (int)n_rows;
+    c->n_reco = n_reco;
+    c->ldr = ldr;
+    c->m_user = true;
+    c->have_rsp = true;
+    c->have_data = false;  // data and pulls follow the new parameter layout
+    // per-component SM spectra with the code the evaluations use (w = 1
+    // exactly at the SM point)
+    {
+        const nr::ScanArgs sa = scan_args(c, c->d_thsm, 0);
+        const nr::RowArgs ra = row_args(c, 0, nullptr, nullptr, c->d_ssmc, c->d_thsm);
+        if ((rc = step(c, nullptr, nullptr, &sa, nullptr, c->stream))) return rc;
+        if ((rc = step(c, nullptr, &ra, nullptr, nullptr, c->stream))) return rc;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if ((rc = choose_tiling(c, 0))) return rc;
+    return 0;
+}
+
 int nr_eval_weights(nr_ctx* c, const double* theta, int n_pts, double* w) {
     if (!w) return fail(NR_EINVAL, "w is null");
     return eval_sync(c, theta, n_pts, nullptr, nullptr, nullptr, w);
@@ -1324,6 +1510,7 @@ int nr_eval_weights(nr_ctx* c, const double* theta, int n_pts, double* w) {
 
 int nr_get_reference(nr_ctx* c, double* s_sm, double* m) {
     if (!c) return fail(NR_EINVAL, "null context");
+    if (int rc = check_single(c)) return rc;
     if (s_sm) {
         if (!c->have_src) return fail(NR_ESTATE, "no sources set");
         std::memcpy(s_sm, c->ssm.data(), sizeof(double) * c->n_t);
@@ -1353,31 +1540,42 @@ int nr_set_fold_tiling(nr_ctx* c, int rows_per_wg, int use_graph) {
 
 int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
     if (!c || !avg_ms || iters <= 0) return fail(NR_EINVAL, "bad argument");
-    if (!c->have_last || (stage == 3 && !c->have_last_adj))
-        return fail(NR_ESTATE, "no previous evaluation to time");
     if (stage < 1 || stage > 5) return fail(NR_EINVAL, "stage must be 1 to 5");
     int rc;
+    if ((rc = check_ready(c))) return rc;
+    if (stage == 3 && (rc = check_single(c))) return rc;
     if ((rc = set_device(c))) return rc;
-    // Timing launches write only internal buffers: the table and weights go
-    // to the buffers the last fold did not read, the likelihood to a scratch
-    // word.
-    const nr::FoldArgs f = c->last_f;
-    const int par = f.v == c->d_v[1];
-    nr::ScanArgs sa = c->last_s;
-    sa.table = reinterpret_cast<double4*>(c->d_table[par ^ 1]);
-    nr::RowArgs ra = c->last_r;
-    ra.table = reinterpret_cast<const double4*>(c->d_table[par]);
-    ra.v = c->d_v[par ^ 1];
-    ra.out_w = nullptr;
-    ra.out_s = nullptr;
-    nr::FoldArgs g = f;
-    g.colpart = c->d_colpart + (size_t)(par ^ 1) * c->n_rb * c->ldr;
-    g.out_nll = c->d_tnll;
-    g.out_mu = nullptr;
-    g.out_a = nullptr;
-    g.out_gb = nullptr;
-    nr::FoldArgs fo = f;
-    fo.colpart = g.colpart;
+    // Timing launches read the context's own inputs at the SM point (the
+    // work of every stage does not depend on theta) and write only internal
+    // buffers: the fold reads fold vector 0 and writes partial sums 0, the
+    // table and weights of the same launch go to copy 1, the likelihood
+    // reads partial sums 1 and lands in a scratch word.
+    const size_t cp = (size_t)c->n_rb * c->ldr;
+    const double* th = c->d_thsm;
+    const nr::FoldArgs f = fold_args(c, th, c->d_v[0], c->d_colpart, c->d_tnll,
+                                     nullptr, false);
+    const nr::ScanArgs sa = scan_args(c, th, 1);
+    const nr::RowArgs ra = row_args(c, 0, c->d_v[1], nullptr, nullptr, th);
+    const nr::FoldArgs g = fold_args(c, th, c->d_v[1], c->d_colpart + cp, c->d_tnll,
+                                     nullptr, false);
+    const nr::FoldArgs fo = g;
+    nr::AdjArgs aa{};
+    if (stage == 3) {
+        aa.R = c->d_R;
+        aa.ldr = c->ldr;
+        aa.n_t = c->n_t;
+        aa.n_reco = c->n_reco;
+        aa.a = c->d_a;
+        aa.ssm = c->d_ssm;
+        aa.mrow = c->d_mrow;
+        aa.basis = c->d_basis;
+        aa.theta = th;
+        aa.gb = c->d_gb;
+        aa.jpart = c->d_jpart;
+        aa.ctr = c->d_ctr + c->n_cc + 1;
+        aa.out_grad = c->d_tnll + 1;
+        aa.ph = c->ph;
+    }
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
@@ -1391,7 +1589,7 @@ int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
             rc = step(c, &fo, nullptr, nullptr, nullptr, c->stream);
             if (!rc) rc = step(c, nullptr, nullptr, nullptr, &g, c->stream);
         }
-        if (stage == 3) HIPCHK(nr::launch_adjoint(c->last_a, c->adj_grid, c->stream));
+        if (stage == 3) HIPCHK(nr::launch_adjoint(aa, c->adj_grid, c->stream));
         if (stage == 4) rc = step(c, &fo, nullptr, nullptr, nullptr, c->stream);
         if (stage == 5) rc = step(c, &f, &ra, &sa, &g, c->stream);
         if (rc) return rc;
@@ -1807,6 +2005,7 @@ int nr_mlp_nll_dev(nr_mlp* q, nr_ctx* c, const double* d_theta, int B,
     if (!q || !d_theta || !d_nll || B <= 0 || B % 8)
         return fail(NR_EINVAL, "batch must be a positive multiple of 8");
     if ((rc = check_ready(c))) return rc;
+    if ((rc = check_single(c))) return rc;
     if (c->n_reco != q->n_out) return fail(NR_EINVAL, "surrogate outputs %d bins, data has %d", q->n_out, c->n_reco);
     HIPCHK(hipSetDevice(q->device));
     if ((rc = mlp_alloc_batch(q, B, false))) return rc;
@@ -1845,6 +2044,7 @@ int nr_eval_mu_batched_dev(nr_ctx* c, const double* d_theta, int n_pts,
                            double* d_mu, void* stream) {
     int rc;
     if ((rc = check_ready(c))) return rc;
+    if ((rc = check_single(c))) return rc;
     if (!d_theta || !d_mu || n_pts <= 0) return fail(NR_EINVAL, "bad argument");
     if ((rc = set_device(c))) return rc;
     if ((rc = ensure_batch(c, n_pts, false, 0))) return rc;

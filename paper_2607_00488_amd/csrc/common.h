@@ -7,6 +7,7 @@
 namespace nr {
 
 constexpr int kNTheta = 7;
+constexpr int kMaxTheta = 32;       // parameters of the multi-component form
 constexpr int kStepRows = 512;      // recoil rows per weights work-group
 constexpr int kNBasis = 20;         // theta-independent recoil basis spectra
 
@@ -36,17 +37,25 @@ struct ScanArgs {
     double4* table;        // [n_nodes + n_src]
 };
 
-// Weights of one point from its node table, one thread per recoil row.
+// Weights of one point from its node table, one thread per row of the
+// (stacked) response: row r = k * n_t + l is recoil bin l of signal
+// component k, whose spectrum sums the sources compSrc[compOff[k] ..
+// compOff[k+1]).  The single-component form has one component holding every
+// source.
 struct RowArgs {
     const double4* table;
     const int* jmin;      // [n_src][n_t] first reachable global node index
     const double* tc;     // [n_t] recoil-bin centres
-    int n_t, n_src;
-    const double* ssm;    // [n_t] S_SM (this same computation at theta_SM)
-    const double* mrow;   // [n_t] row factors m_l
-    double* v;            // [n_t] m_l w_l
-    double* out_w;        // [n_t] or null: weights w_l
-    double* out_s;        // [n_t] or null: write S_theta itself and stop
+    int n_t, n_comp;
+    const int* compOff;   // [n_comp+1]
+    const int* compSrc;   // [n_src] source indices grouped by component
+    const double* ssm;    // [n_comp*n_t] S_SM per component (this code at theta_SM)
+    const double* mrow;   // [n_comp*n_t] row factors
+    const double* theta;  // device, the point (for the component rates)
+    int rate_index;       // theta index of component 0's rate; -1: none
+    double* v;            // [n_comp*n_t] row factor x weight (x rate)
+    double* out_w;        // [n_comp*n_t] or null: weights w
+    double* out_s;        // [n_comp*n_t] or null: write S_theta itself and stop
 };
 
 struct FoldArgs {
@@ -66,8 +75,12 @@ struct FoldArgs {
     double* out_a;        // [ldr] or null: d(-2lnL)/d mu_j
     double* out_gb;       // [1] or null: sum_j a_j b_j
     double cdata;
-    double pull_mean[kNTheta];
-    double pull_sigma[kNTheta];
+    double pull_mean[kMaxTheta];
+    double pull_sigma[kMaxTheta];
+    int n_theta;          // parameters per point
+    int bkg_index;        // theta index of the first background rate
+    int n_bkg;            // background templates: mu_j += theta[bkg_index+b] b[b][j]
+    const double* mask;   // [n_reco] or null: mu_j = mask_j (fold_j + backgrounds)
     int rows_per_wg, n_rb, n_cc;
 };
 

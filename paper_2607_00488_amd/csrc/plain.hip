@@ -94,10 +94,10 @@ __device__ inline void suffix_scan_wave(double& x, int lane) {
 __device__ void scan_role(const ScanArgs& a, int k, double* smem) {
     double4* wt = reinterpret_cast<double4*>(smem);          // [8]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double th[kNTheta];
+    double th[5];
 #pragma unroll
-    for (int i = 0; i < kNTheta; ++i) th[i] = a.theta[i];
-    const double f = a.srcGroup[k] ? th[5] : 1.0;
+    for (int i = 0; i < 5; ++i) th[i] = a.theta[i];
+    const double f = a.srcGroup[k] ? a.theta[5] : 1.0;
     const int off = a.srcOff[k], end = a.srcOff[k + 1];
     double4* tab = a.table + k;  // entry j + k for global node j
     if (threadIdx.x == 0) tab[end] = make_double4(0.0, 0.0, 0.0, 0.0);
@@ -145,10 +145,12 @@ __device__ void scan_role(const ScanArgs& a, int k, double* smem) {
 // S_SM, w_l := 1 where S_SM = 0, and the fold vector v_l = m_l w_l.  The SM
 // reference is formed by this same code, so w = 1 exactly at theta_SM.
 __device__ void rows_role(const RowArgs& a, int blk) {
-    const int l = blk * kStepThreads + (int)threadIdx.x;
-    if (l >= a.n_t) return;
+    const int r = blk * kStepThreads + (int)threadIdx.x;
+    if (r >= a.n_comp * a.n_t) return;
+    const int c = r / a.n_t, l = r - c * a.n_t;
     double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
-    for (int k = 0; k < a.n_src; ++k) {
+    for (int q = a.compOff[c]; q < a.compOff[c + 1]; ++q) {
+        const int k = a.compSrc[q];
         const double4 t = a.table[a.jmin[(size_t)k * a.n_t + l] + k];
         s.x += t.x;
         s.y += t.y;
@@ -158,13 +160,16 @@ __device__ void rows_role(const RowArgs& a, int blk) {
     const double T = a.tc[l];
     const double S = fma(T, fma(T, s.z, s.y), s.x) + s.w / T;
     if (a.out_s) {
-        a.out_s[l] = S;
+        a.out_s[r] = S;
         return;
     }
-    const double ssm = a.ssm[l];
+    const double ssm = a.ssm[r];
     const double w = ssm > 0.0 ? S / ssm : 1.0;
-    if (a.out_w) a.out_w[l] = w;
-    a.v[l] = a.mrow[l] * w;
+    if (a.out_w) a.out_w[r] = w;
+    // multi-component form: the component's rate nuisance scales its rows
+    const double mr = a.rate_index >= 0 ? a.mrow[r] * a.theta[a.rate_index + c]
+                                        : a.mrow[r];
+    a.v[r] = mr * w;
 }
 
 // ------------------------------------------------------------------ a3
@@ -280,8 +285,13 @@ __device__ void finish_role(const FoldArgs& a, int cc, double* smem,
     double dev = 0.0, gb = 0.0;
     if (qd == 0 && col < a.n_reco) {
         const double fold = ps[0][ci] + ps[1][ci];
-        const double bj = a.b[col];
-        const double mu = fold + a.theta[6] * bj;
+        double mu = fold, bj = 0.0;
+        for (int q = 0; q < a.n_bkg; ++q) {
+            const double t = a.b[(size_t)q * a.n_reco + col];
+            mu += a.theta[a.bkg_index + q] * t;
+            bj = t;  // the single-template form's b_j (gradient of f_bkg)
+        }
+        if (a.mask) mu *= a.mask[col];
         const double nj = a.n[col];
         if (a.out_mu) a.out_mu[col] = mu;
         if (nj > 0.0)
@@ -327,7 +337,7 @@ __device__ void finish_role(const FoldArgs& a, int cc, double* smem,
             g += a.chunk_gb[q];
         }
         double pulls = 0.0;
-        for (int i = 0; i < kNTheta; ++i)
+        for (int i = 0; i < a.n_theta; ++i)
             if (a.pull_sigma[i] > 0.0) {
                 const double z = (a.theta[i] - a.pull_mean[i]) / a.pull_sigma[i];
                 pulls += z * z;
@@ -506,7 +516,8 @@ hipError_t launch_step(const StepArgs& a, hipStream_t s) {
                           a.nb_fold != a.fold.n_rb * a.fold.n_cc))
         return hipErrorInvalidValue;
     if (a.nb_fin > 0 && a.nb_fin != a.fin.n_cc) return hipErrorInvalidValue;
-    if (a.nb_rows > 0 && a.nb_rows != (a.rows.n_t + kStepThreads - 1) / kStepThreads)
+    if (a.nb_rows > 0 &&
+        a.nb_rows != (a.rows.n_comp * a.rows.n_t + kStepThreads - 1) / kStepThreads)
         return hipErrorInvalidValue;
     const int grid = a.nb_fold + a.nb_rows + a.nb_scan + a.nb_fin;
     if (grid <= 0) return hipSuccess;

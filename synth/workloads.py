@@ -29,7 +29,7 @@ __all__ = [
     "survival_prob", "beta_shape", "source_nodes", "response_mc",
     "poisson_data", "theta_prior", "theta_corners", "theta_sm",
     "theta_grid_scan", "theta_box", "Config", "CONFIGS", "batched_schedule",
-    "rng",
+    "rng", "component_inputs",
 ]
 
 T_LO, T_HI = 0.0, 16.0          # recoil-energy histogram range [MeV]
@@ -231,3 +231,36 @@ def batched_schedule(n_datasets: int = 64):
                         seed_response=1000 * 2 + d, seed_data=2000 * 2 + d,
                         seed_theta=3000 * 2 + d))
     return out
+
+
+# rough recoil endpoints [MeV] of the five sources (shape parameters of the
+# synthetic per-component histograms only) and an exponential slope each
+COMPONENT_SHAPES = ((0.26, 0.08), (0.67, 0.3), (1.22, 0.5), (1.52, 0.5),
+                    (15.8, 4.0))
+
+
+def component_inputs(n_t, n_reco, n_mc, seed, shapes=COMPONENT_SHAPES):
+    """Seeded inputs of the multi-component form: one SM Monte-Carlo
+    histogram per component (its own flat-T detector MC, seed + k, rows
+    weighted by a falling profile up to an endpoint), two background PDFs
+    (flat and falling), per-component live-time masks in [0.9, 1] and a
+    common mask with a few dead bins at 0.5."""
+    K = len(shapes)
+    T = (np.arange(n_t) + 0.5) * (T_HI - T_LO) / n_t + T_LO
+    hist = np.zeros((K, n_t, n_reco), dtype=np.float32)
+    for k, (tend, tau) in enumerate(shapes):
+        rsp = response_mc(n_t, n_reco, n_mc, seed=seed + k, keep_counts=False)
+        prof = np.where(T < tend, np.exp(-T / tau), 0.0)
+        hist[k] = (rsp.R * (n_mc / n_t) * prof[:, None]).astype(np.float32)
+    g = rng(seed + 100)
+    E = (np.arange(n_reco) + 0.5) * (RECO_HI - RECO_LO) / n_reco + RECO_LO
+    flat = np.full(n_reco, 1.0 / n_reco)
+    fall = np.exp(-E / 2.0)
+    fall /= fall.sum()
+    comp_mask = g.uniform(0.9, 1.0, (K, n_reco))
+    mask = np.ones(n_reco)
+    mask[g.choice(n_reco, size=max(1, n_reco // 64), replace=False)] = 0.5
+    return dict(hist=hist, comp_of_source=np.arange(K, dtype=np.int32),
+                scale=g.uniform(0.8, 1.2, K), rate_sm=np.array([1.3e3, 5.0e2, 3.0e1, 6.0e1, 4.0e1]),
+                bkg_pdf=np.vstack([flat, fall]), bkg_rate=np.array([2.0e3, 8.0e2]),
+                comp_mask=comp_mask, mask=mask, exposure=1.5)

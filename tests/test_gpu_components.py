@@ -1,0 +1,115 @@
+"""The multi-component form (Sec. III.B-C: per-component responses from
+separate MC, live-time masks, scales, per-component rates, 1D background
+templates) on the GPU against the multi-component oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.components import ComponentOracle
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def points(K, B, n, seed):
+    g = synth.rng(seed)
+    th = np.concatenate([g.uniform(-0.5, 0.5, (n, 4)), g.uniform(0, 25, (n, 1)),
+                         g.uniform(0.8, 1.2, (n, K + B))], axis=1)
+    sm = np.concatenate([np.zeros(5), np.ones(K + B)])
+    return np.vstack([sm, th])
+
+
+@pytest.fixture(scope="module", params=[(512, 256, 256), (333, 77, 37)],
+                ids=["config0", "ragged"])
+def setup(request):
+    import paper_2607_00488_amd as nr
+    n_t, n_reco, n_e = request.param
+    src = synth.source_nodes(n_e)
+    d = synth.component_inputs(n_t, n_reco, 200_000, 61)
+    co = ComponentOracle(src, d["comp_of_source"], n_t, d["hist"], d["scale"],
+                         d["rate_sm"], d["bkg_pdf"], d["bkg_rate"],
+                         d["comp_mask"], d["mask"], d["exposure"])
+    K, B = len(d["scale"]), 2
+    th_sm = np.concatenate([np.zeros(5), np.ones(K + B)])
+    n = synth.poisson_data(co.mu(th_sm), 62)
+    pm = np.concatenate([np.zeros(5), np.ones(K + B)])
+    ps = np.concatenate([np.zeros(5), np.full(K + B, 0.1)])
+    co.set_data(n, pm, ps)
+    ctx = nr.Context(0)
+    ctx.set_sources(src, n_t, 0.0, 16.0)
+    ctx.set_components(d["comp_of_source"], d["hist"], d["scale"], d["rate_sm"],
+                       bkg_pdf=d["bkg_pdf"], bkg_rate=d["bkg_rate"],
+                       comp_mask=d["comp_mask"], mask=d["mask"],
+                       exposure=d["exposure"])
+    assert ctx.n_theta == 5 + K + B
+    ctx.set_data(n, None, pm, ps)
+    yield co, ctx, K, B, n_t, n_reco
+    ctx.close()
+    co.close()
+
+
+def test_mu_and_nll_parity(setup):
+    co, ctx, K, B, n_t, n_reco = setup
+    th = points(K, B, 96, 63)
+    log(f"[gpu] multi-component {n_t}x{n_reco}: {K} components, {B} backgrounds, "
+        f"{len(th)} points")
+    mu = ctx.eval_mu(th)
+    nll = ctx.eval_nll(th)
+    worst_mu = worst_nll = 0.0
+    for i in range(len(th)):
+        ref = co.mu(th[i])
+        scale = np.maximum(np.abs(ref), 1e-9 * np.abs(ref).max())
+        r = np.max(np.abs(mu[i] - ref) / scale)
+        assert r <= 1e-5, (i, r)
+        worst_mu = max(worst_mu, r)
+        v = co.nll(th[i])
+        assert abs(nll[i] - v) <= 1e-3, (i, nll[i], v)
+        worst_nll = max(worst_nll, abs(nll[i] - v))
+    log(f"[gpu] max rel dmu {worst_mu:.2e}, max |dnll| {worst_nll:.2e}")
+
+
+def test_device_path_graph_replay_and_guards(setup):
+    import torch
+    import paper_2607_00488_amd as nr
+    co, ctx, K, B, n_t, n_reco = setup
+    dev = torch.device("cuda:0")
+    th = points(K, B, 40, 64)
+    tt = torch.tensor(th, dtype=torch.float64, device=dev)
+    out = torch.empty(len(th), dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream(device=dev)
+    ref = ctx.eval_nll(th)
+    for _ in range(3):                       # capture, then two replays
+        out.zero_()
+        ctx.eval_nll_dev(tt, out, stream=s)
+        s.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref)
+    with pytest.raises(ValueError):          # rows of the wrong length
+        ctx.eval_nll_dev(tt[:, :7].contiguous(), out, stream=s)
+    with pytest.raises(nr.NrError):          # no gradient in this form
+        ctx.eval_nll_grad(th[:2])
+    with pytest.raises(nr.NrError):
+        ctx.eval_nll_batched(th[:2])
+
+
+def test_back_to_single_component():
+    """nr_set_response after the multi-component form restores the
+    single-component path exactly."""
+    from problems import config_inputs, gpu_context
+    p = config_inputs(0)
+    ctx = gpu_context(p)
+    th = synth.theta_prior(8, 71)
+    before = ctx.eval_nll(th)
+    d = synth.component_inputs(p["n_t"], p["n_reco"], 50_000, 72)
+    ctx.set_components(d["comp_of_source"], d["hist"], d["scale"], d["rate_sm"])
+    assert ctx.n_theta == 5 + 5
+    ctx.set_response(p["R"], n_sig=p["n_sig"])
+    ctx.set_data(p["n"], p["b"])
+    assert ctx.n_theta == 7
+    assert np.array_equal(ctx.eval_nll(th), before)
+    ctx.close()

@@ -196,6 +196,57 @@ def surrogate_form(ctx, train_seconds=20.0):
              "method when a check misses by more than 0.1")
 
 
+def components_form(n_pts=400):
+    """The multi-component form at the paper-scale binning: five signal
+    components (one per solar source) with their own 16384 x 4096 responses
+    stacked row-wise (1.25 GiB of FP32 read per evaluation), two background
+    templates, masks; single-point evaluations through the step-kernel
+    pipeline, timed as one graph replay."""
+    import torch
+    import synth
+    import paper_2607_00488_amd as nr
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    src = synth.source_nodes(2048)
+    d = synth.component_inputs(16384, 4096, 20_000_000, 8001, shared_mc=True)
+    ctx = nr.Context(0)
+    ctx.set_sources(src, 16384, 0.0, 16.0)
+    ctx.set_components(d["comp_of_source"], d["hist"], d["scale"], d["rate_sm"],
+                       bkg_pdf=d["bkg_pdf"], bkg_rate=d["bkg_rate"],
+                       comp_mask=d["comp_mask"], mask=d["mask"],
+                       exposure=d["exposure"])
+    K = len(d["scale"])
+    del d
+    g = synth.rng(8002)
+    n_theta = ctx.n_theta
+    ctx.set_data(np.full(4096, 20.0), None)
+    th = np.concatenate([g.uniform(-0.5, 0.5, (n_pts, 4)), g.uniform(0, 25, (n_pts, 1)),
+                         g.uniform(0.8, 1.2, (n_pts, n_theta - 5))], axis=1)
+    t_setup = time.perf_counter() - t0
+    tt = torch.tensor(th, dtype=torch.float64, device=dev)
+    out = torch.empty(n_pts, dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream(device=dev)
+    ctx.eval_nll_dev(tt, out, stream=s)
+    s.synchronize()
+    t1 = time.perf_counter()
+    ctx.eval_nll_dev(tt, out, stream=s)
+    s.synchronize()
+    dt = time.perf_counter() - t1
+    step_ms = ctx.time_stage(5, 100)
+    alg = 4 * K * 16384 * 4096 + 16 * K * 16384 + 16 * 4096
+    ctx.close()
+    return dict(evals_per_s=round(n_pts / dt, 1), points=n_pts,
+                us_per_eval=round(dt / n_pts * 1e6, 2), components=K,
+                backgrounds=2, n_theta=n_theta, algorithmic_bytes=alg,
+                step_kernel_us=round(step_ms * 1e3, 2),
+                achieved_gbs=round(alg / (step_ms * 1e-3) / 1e9, 1),
+                frac_hbm=round(alg / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                setup_seconds=round(t_setup, 1),
+                what="Eqs. (Rij), (fNp_reweight), (mu_total): 5 components x "
+                     "16384 x 4096 FP32 responses stacked, one R stream per "
+                     "evaluation through the step kernel")
+
+
 def cpu_baseline(p, n_eval, gpu_ctx):
     """The FP64 oracle on the host cores for a bounded sample of points, and
     the GPU's -2lnL on the same inputs for the |Delta| column."""
@@ -232,6 +283,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-components", action="store_true")
     ap.add_argument("--surrogate-seconds", type=float, default=20.0)
     ap.add_argument("--counter-pass", action="store_true",
                     help="short run for hardware-counter collection: 20 "
@@ -360,6 +412,10 @@ def main():
             f"network alone {sf['network_only_evals_per_s']:.0f} evals/s; "
             f"gain {sf['gain_vs_exact_batched']}x; median |d| "
             f"{sf['val_abs_dnll']['median']:.3g}")
+    if not args.no_components:
+        forms["multi_component"] = mc = components_form()
+        log(f"[bench] multi-component: {mc['evals_per_s']:.0f} evals/s, "
+            f"{mc['achieved_gbs']:.0f} GB/s ({mc['frac_hbm']:.3f} of peak)")
     res["forms"] = forms
     if not args.no_cpu_baseline:
         cb, dmax = cpu_baseline(p, args.cpu_evals, ctx)

@@ -239,17 +239,21 @@ COMPONENT_SHAPES = ((0.26, 0.08), (0.67, 0.3), (1.22, 0.5), (1.52, 0.5),
                     (15.8, 4.0))
 
 
-def component_inputs(n_t, n_reco, n_mc, seed, shapes=COMPONENT_SHAPES):
+def component_inputs(n_t, n_reco, n_mc, seed, shapes=COMPONENT_SHAPES,
+                     shared_mc=False):
     """Seeded inputs of the multi-component form: one SM Monte-Carlo
-    histogram per component (its own flat-T detector MC, seed + k, rows
-    weighted by a falling profile up to an endpoint), two background PDFs
-    (flat and falling), per-component live-time masks in [0.9, 1] and a
-    common mask with a few dead bins at 0.5."""
+    histogram per component (its own flat-T detector MC, seed + k, or one MC
+    shared by all with ``shared_mc``, rows weighted by a falling profile up
+    to an endpoint), two background PDFs (flat and falling), per-component
+    live-time masks in [0.9, 1] and a common mask with a few dead bins at
+    0.5."""
     K = len(shapes)
     T = (np.arange(n_t) + 0.5) * (T_HI - T_LO) / n_t + T_LO
     hist = np.zeros((K, n_t, n_reco), dtype=np.float32)
+    rsp = None
     for k, (tend, tau) in enumerate(shapes):
-        rsp = response_mc(n_t, n_reco, n_mc, seed=seed + k, keep_counts=False)
+        if rsp is None or not shared_mc:
+            rsp = response_mc(n_t, n_reco, n_mc, seed=seed + k, keep_counts=False)
         prof = np.where(T < tend, np.exp(-T / tau), 0.0)
         hist[k] = (rsp.R * (n_mc / n_t) * prof[:, None]).astype(np.float32)
     g = rng(seed + 100)

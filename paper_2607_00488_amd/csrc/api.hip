@@ -158,7 +158,7 @@ struct nr_ctx {
     int *d_compoff = nullptr, *d_compsrc = nullptr, *d_group0 = nullptr;
     double *d_ssmc = nullptr, *d_bkg = nullptr, *d_mask = nullptr;
     // fold / adjoint scratch
-    int rows_per_wg = 0, n_rb = 0, n_cc = 0, adj_grid = 0;
+    int rows_per_wg = 0, n_rb = 0, n_fc = 0, n_cc = 0, adj_grid = 0;
     double *d_colpart = nullptr;  // [2][n_rb][ldr]
     double *d_chunk_dev = nullptr, *d_chunk_gb = nullptr;
     unsigned* d_ctr = nullptr;  // [n_cc + 1] fold, [1] adjoint after that
@@ -260,27 +260,25 @@ int upload_mrow(nr_ctx* c) {
 }
 
 int choose_tiling(nr_ctx* c, int rows_req) {
-    c->n_cc = (c->ldr / 4 + 63) / 64;
+    c->n_fc = (c->ldr / 4 + 511) / 512;   // fold tiles are 2048 columns wide
+    c->n_cc = (c->n_reco + 63) / 64;      // reduction groups of 64 columns
     int rows;
     if (rows_req > 0) {
         rows = rows_req;
     } else {
-        // measured on MI355X at 16384 x 4096: 1024-row tiles (16 x 16
-        // work-groups) stream fastest and leave 16 partial rows per column
-        rows = 1024;
-        if (c->n_rows < 16 * 1024) {
-            int target_rb = std::max(1, 256 / c->n_cc);
-            rows = (c->n_rows + target_rb - 1) / target_rb;
-            rows = std::min(1024, ((rows + 63) / 64) * 64);
-        }
+        // one fold tile per compute unit: measured on MI355X at 16384 x 4096,
+        // 128-row x 2048-column tiles (128 x 2 work-groups) stream fastest
+        const int target_rb = std::max(1, 256 / c->n_fc);
+        rows = (c->n_rows + target_rb - 1) / target_rb;
+        rows = (rows + 7) / 8 * 8;
     }
     rows = std::max(8, std::min(rows, 2048));
     c->rows_per_wg = rows;
     c->n_rb = (c->n_rows + rows - 1) / rows;
     int rc;
     if ((rc = dalloc(&c->d_colpart, (size_t)2 * c->n_rb * c->ldr))) return rc;
-    if ((rc = dalloc(&c->d_chunk_dev, (size_t)c->n_cc))) return rc;
-    if ((rc = dalloc(&c->d_chunk_gb, (size_t)c->n_cc))) return rc;
+    if ((rc = dalloc(&c->d_chunk_dev, (size_t)2 * c->n_cc))) return rc;
+    if ((rc = dalloc(&c->d_chunk_gb, (size_t)2 * c->n_cc))) return rc;
     if ((rc = dalloc(&c->d_ctr, (size_t)c->n_cc + 2))) return rc;
     HIPCHK(hipMemset(c->d_ctr, 0, sizeof(unsigned) * (c->n_cc + 2)));
     c->adj_grid = nr::adjoint_grid(c->n_t);
@@ -347,7 +345,8 @@ nr::RowArgs row_args(nr_ctx* c, int par, double* v, double* out_w,
 }
 
 nr::FoldArgs fold_args(nr_ctx* c, const double* thp, const double* v,
-                       double* colpart, double* nll, double* mu, bool grad) {
+                       double* colpart, double* nll, double* mu, bool grad,
+                       int cpar = 0) {
     nr::FoldArgs fa{};
     fa.R = c->d_R;
     fa.ldr = c->ldr;
@@ -362,9 +361,8 @@ nr::FoldArgs fold_args(nr_ctx* c, const double* thp, const double* v,
     fa.n_theta = c->n_theta;
     fa.theta = thp;
     fa.colpart = colpart;
-    fa.ctr = c->d_ctr;
-    fa.chunk_dev = c->d_chunk_dev;
-    fa.chunk_gb = c->d_chunk_gb;
+    fa.chunk_dev = c->d_chunk_dev + (size_t)cpar * c->n_cc;  // group sums, by parity
+    fa.chunk_gb = c->d_chunk_gb + (size_t)cpar * c->n_cc;
     fa.out_nll = nll;
     fa.out_mu = mu;
     fa.out_a = grad ? c->d_a : nullptr;
@@ -376,16 +374,18 @@ nr::FoldArgs fold_args(nr_ctx* c, const double* thp, const double* v,
     }
     fa.rows_per_wg = c->rows_per_wg;
     fa.n_rb = c->n_rb;
+    fa.n_fc = c->n_fc;
     fa.n_cc = c->n_cc;
     return fa;
 }
 
 int step(nr_ctx* c, const nr::FoldArgs* fold, const nr::RowArgs* rows,
-         const nr::ScanArgs* scan, const nr::FoldArgs* fin, hipStream_t s) {
+         const nr::ScanArgs* scan, const nr::FoldArgs* fin, hipStream_t s,
+         const nr::FoldArgs* fnl = nullptr) {
     nr::StepArgs a{};
     if (fold) {
         a.fold = *fold;
-        a.nb_fold = c->n_rb * c->n_cc;
+        a.nb_fold = c->n_rb * c->n_fc;
     }
     if (rows) {
         a.rows = *rows;
@@ -398,6 +398,10 @@ int step(nr_ctx* c, const nr::FoldArgs* fold, const nr::RowArgs* rows,
     if (fin) {
         a.fin = *fin;
         a.nb_fin = c->n_cc;
+    }
+    if (fnl) {
+        a.fnl = *fnl;
+        a.nb_final = 1;
     }
     HIPCHK(nr::launch_step(a, s));
     return 0;
@@ -423,21 +427,23 @@ int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
     auto fa = [&](int p) {
         return fold_args(c, thp(p), c->d_v[p & 1], c->d_colpart + (p & 1) * cp,
                          nll + p, mu ? mu + (size_t)p * c->n_reco : nullptr,
-                         grad != nullptr);
+                         grad != nullptr, p & 1);
     };
     auto in = [&](int p) { return p >= 0 && p < n_pts; };
     int rc;
     if (!grad) {
-        for (int k = 0; k <= n_pts + 2; ++k) {
+        for (int k = 0; k <= n_pts + 3; ++k) {
             nr::ScanArgs a1;
             nr::RowArgs a2;
-            nr::FoldArgs a3, a4;
+            nr::FoldArgs a3, a4, a5;
             if (in(k)) a1 = sa(k);
             if (in(k - 1)) a2 = ra(k - 1);
             if (in(k - 2)) a3 = fa(k - 2);
             if (in(k - 3)) a4 = fa(k - 3);
+            if (in(k - 4)) a5 = fa(k - 4);
             if ((rc = step(c, in(k - 2) ? &a3 : nullptr, in(k - 1) ? &a2 : nullptr,
-                           in(k) ? &a1 : nullptr, in(k - 3) ? &a4 : nullptr, s)))
+                           in(k) ? &a1 : nullptr, in(k - 3) ? &a4 : nullptr, s,
+                           in(k - 4) ? &a5 : nullptr)))
                 return rc;
         }
         return 0;
@@ -450,6 +456,7 @@ int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
         if ((rc = step(c, nullptr, &a2, nullptr, nullptr, s))) return rc;
         if ((rc = step(c, &f, nullptr, nullptr, nullptr, s))) return rc;
         if ((rc = step(c, nullptr, nullptr, nullptr, &f, s))) return rc;
+        if ((rc = step(c, nullptr, nullptr, nullptr, nullptr, s, &f))) return rc;
         nr::AdjArgs aa{};
         aa.R = c->d_R;
         aa.ldr = c->ldr;
@@ -1362,7 +1369,7 @@ int nr_eval_ess(nr_ctx* c, const double* theta, int n_pts, double* ess) {
         ea.colpart = c->d_colpart;
         ea.rows_per_wg = c->rows_per_wg;
         ea.n_rb = c->n_rb;
-        ea.n_cc = c->n_cc;
+        ea.n_cc = (c->ldr / 4 + 63) / 64;  // the ESS fold's own 256-column tiles
         ea.out = c->d_mu + (size_t)p * c->n_reco;
         HIPCHK(nr::launch_ess(ea, c->stream));
     }
@@ -1548,16 +1555,17 @@ int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
     // Timing launches read the context's own inputs at the SM point (the
     // work of every stage does not depend on theta) and write only internal
     // buffers: the fold reads fold vector 0 and writes partial sums 0, the
-    // table and weights of the same launch go to copy 1, the likelihood
-    // reads partial sums 1 and lands in a scratch word.
+    // table and weights of the same launch go to copy 1, the reduction reads
+    // partial sums 1 into group sums 1, the final role adds group sums 0
+    // into a scratch word.
     const size_t cp = (size_t)c->n_rb * c->ldr;
     const double* th = c->d_thsm;
     const nr::FoldArgs f = fold_args(c, th, c->d_v[0], c->d_colpart, c->d_tnll,
-                                     nullptr, false);
+                                     nullptr, false, 0);
     const nr::ScanArgs sa = scan_args(c, th, 1);
     const nr::RowArgs ra = row_args(c, 0, c->d_v[1], nullptr, nullptr, th);
     const nr::FoldArgs g = fold_args(c, th, c->d_v[1], c->d_colpart + cp, c->d_tnll,
-                                     nullptr, false);
+                                     nullptr, false, 1);
     const nr::FoldArgs fo = g;
     nr::AdjArgs aa{};
     if (stage == 3) {
@@ -1588,10 +1596,11 @@ int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
         if (stage == 2) {
             rc = step(c, &fo, nullptr, nullptr, nullptr, c->stream);
             if (!rc) rc = step(c, nullptr, nullptr, nullptr, &g, c->stream);
+            if (!rc) rc = step(c, nullptr, nullptr, nullptr, nullptr, c->stream, &g);
         }
         if (stage == 3) HIPCHK(nr::launch_adjoint(aa, c->adj_grid, c->stream));
         if (stage == 4) rc = step(c, &fo, nullptr, nullptr, nullptr, c->stream);
-        if (stage == 5) rc = step(c, &f, &ra, &sa, &g, c->stream);
+        if (stage == 5) rc = step(c, &f, &ra, &sa, &g, c->stream, &f);
         if (rc) return rc;
     }
     HIPCHK(hipEventRecord(e1, c->stream));

@@ -66,10 +66,9 @@ struct FoldArgs {
     const double* n;      // [n_reco]
     const double* b;      // [n_reco]
     const double* theta;  // device, 7 doubles
-    double* colpart;      // [n_rb][ldr]
-    unsigned* ctr;        // [n_cc + 1], zero between launches
-    double* chunk_dev;    // [n_cc]
-    double* chunk_gb;     // [n_cc]
+    double* colpart;      // [n_rb][ldr] partial rows of the fold tiles
+    double* chunk_dev;    // [n_cc] group sums of the deviance
+    double* chunk_gb;     // [n_cc] group sums of a_j b_j
     double* out_nll;      // [1]
     double* out_mu;       // [n_reco] or null
     double* out_a;        // [ldr] or null: d(-2lnL)/d mu_j
@@ -81,20 +80,25 @@ struct FoldArgs {
     int bkg_index;        // theta index of the first background rate
     int n_bkg;            // background templates: mu_j += theta[bkg_index+b] b[b][j]
     const double* mask;   // [n_reco] or null: mu_j = mask_j (fold_j + backgrounds)
-    int rows_per_wg, n_rb, n_cc;
+    int rows_per_wg;      // recoil rows per fold tile
+    int n_rb;             // fold row tiles = partial rows
+    int n_fc;             // fold column tiles (2048 columns each)
+    int n_cc;             // reduction groups (64 columns each)
 };
 
-// One launch of the single-point step kernel: nb_fold = n_rb * n_cc
+// One launch of the single-point step kernel: nb_fold = n_rb * n_fc
 // work-groups fold the point `fold` describes, nb_rows form the weights of
 // the point `rows` describes (512 rows each), nb_scan = n_src build the
-// node table of the point `scan` describes and nb_fin = n_cc finish the
-// point `fin` describes.  Any of the counts may be zero.
+// node table of the point `scan` describes, nb_fin = n_cc reduce the fold of
+// the point `fin` describes into group sums, and nb_final (0 or 1) adds the
+// group sums of the point `fnl` describes.  Any of the counts may be zero.
 struct StepArgs {
     FoldArgs fold;
     FoldArgs fin;
+    FoldArgs fnl;
     RowArgs rows;
     ScanArgs scan;
-    int nb_fold, nb_rows, nb_scan, nb_fin;
+    int nb_fold, nb_rows, nb_scan, nb_fin, nb_final;
 };
 
 struct AdjArgs {

@@ -61,12 +61,14 @@ __device__ inline NodeCoef node_coef(double iE, double nu, double pe,
 // reduces point k - 3; stream order is the only synchronisation.
 constexpr int kStepThreads = 512;          // 8 waves in every role
 constexpr int kStepWaves = kStepThreads / 64;
-constexpr int kFoldCols = 256;             // 64 lanes x float4
+constexpr int kFoldTile4 = kStepThreads;   // float4 columns per fold tile
 constexpr int kFoldUnroll = 8;
 constexpr int kFoldMaxRows = 2048;
-constexpr int kSmemFold = kFoldMaxRows + kStepWaves * (kFoldCols + 1);
+constexpr int kFinCols = 64;               // columns per reduction group
+constexpr int kFinSplit = kStepThreads / kFinCols;  // threads per column
+constexpr int kSmemFold = kFoldMaxRows;
 constexpr int kSmemScan = 4 * kStepWaves;
-constexpr int kSmemFin = 2 * kFoldCols + 2 * kStepWaves;
+constexpr int kSmemFin = kFinSplit * kFinCols;
 constexpr int kSmemDoubles = kSmemFold > kSmemFin ? kSmemFold : kSmemFin;
 static_assert(kSmemScan <= kSmemDoubles, "scan scratch");
 static_assert(kStepRows == kStepThreads, "one recoil row per thread");
@@ -102,14 +104,27 @@ __device__ void scan_role(const ScanArgs& a, int k, double* smem) {
     double4* tab = a.table + k;  // entry j + k for global node j
     if (threadIdx.x == 0) tab[end] = make_double4(0.0, 0.0, 0.0, 0.0);
     double4 carry = make_double4(0.0, 0.0, 0.0, 0.0);
+    // node data of the next tile are loaded while this tile is scanned
+    int j = end - kStepThreads + (int)threadIdx.x;
+    double ie = 0.0, nw = 0.0, pe = 0.0;
+    if (j >= off) {
+        ie = a.nodeIE[j];
+        nw = a.nodeW[j];
+        pe = a.nodePe[j];
+    }
     for (int hi = end; hi > off; hi -= kStepThreads) {
         // node j = hi - 512 + tid; wave 7 holds the highest 64 nodes
-        const int j = hi - kStepThreads + (int)threadIdx.x;
+        const bool have = j >= off;
         double4 c = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (j >= off) {
-            const NodeCoef q = node_coef(a.nodeIE[j], a.nodeW[j] * f,
-                                         a.nodePe[j], th, a.ph);
+        if (have) {
+            const NodeCoef q = node_coef(ie, nw * f, pe, th, a.ph);
             c = make_double4(q.a0, q.a1, q.a2, q.am);
+        }
+        const int jn = j - kStepThreads;
+        if (jn >= off) {
+            ie = a.nodeIE[jn];
+            nw = a.nodeW[jn];
+            pe = a.nodePe[jn];
         }
         suffix_scan_wave(c.x, lane);
         suffix_scan_wave(c.y, lane);
@@ -125,7 +140,7 @@ __device__ void scan_role(const ScanArgs& a, int k, double* smem) {
             add.z += t.z;
             add.w += t.w;
         }
-        if (j >= off)
+        if (have)
             tab[j] = make_double4(c.x + add.x, c.y + add.y, c.z + add.z,
                                   c.w + add.w);
         for (int w = kStepWaves - 1; w >= 0; --w) {
@@ -136,6 +151,7 @@ __device__ void scan_role(const ScanArgs& a, int k, double* smem) {
             carry.w += t.w;
         }
         __syncthreads();
+        j = jn;
     }
 }
 
@@ -174,117 +190,106 @@ __device__ void rows_role(const RowArgs& a, int blk) {
 
 // ------------------------------------------------------------------ a3
 // Fold through the response (Eqs. (Rij), (fNp_reweight), (mu_total)).
-// Tile (rb, cc) streams rows [rb*rows, +rows) and columns [cc*256, +256) of
-// R with 16-byte streaming loads, eight rows in flight per wave (the first
-// eight are issued before the weights are staged); the per-row weights
-// v_l = m_l w_l sit in LDS.  R is FP32 in HBM; products and sums are FP64,
-// which the full-rate FP64 vector units of gfx950 absorb at no cost to this
-// bandwidth-bound loop.  The tile writes its column partial sums; they are
-// reduced by the finish role of the next launch.
+// Tile (rb, cc) covers rows [rb*rows, +rows) and 2048 columns: wave w owns
+// the 64 float4 columns cc*512 + w*64 + lane and walks every row of the
+// tile, eight rows in flight (the first eight issued before the weights are
+// staged), so each row of the tile is read as one contiguous 8 KB run by
+// the work-group.  The per-row weights v_l = m_l w_l sit in LDS.  R is FP32
+// in HBM; products and sums are FP64, which the full-rate FP64 vector units
+// of gfx950 absorb at no cost to this bandwidth-bound loop.  Every lane
+// writes its four column sums as the tile's partial row; no cross-work-group
+// synchronisation happens here (the reduction role of the next launch adds
+// the partial rows).
 __device__ void fold_role(const FoldArgs& a, int rb, int cc, double* smem) {
     double* vs = smem;                                         // [2048]
-    double (*red)[kFoldCols + 1] =
-        reinterpret_cast<double (*)[kFoldCols + 1]>(smem + kFoldMaxRows);
     const int row0 = rb * a.rows_per_wg;
     int nrows = a.n_t - row0;
     if (nrows > a.rows_per_wg) nrows = a.rows_per_wg;
     const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-
     const int ld4 = a.ldr >> 2;
-    const int c4 = cc * 64 + lane;
+    const int c4 = cc * kFoldTile4 + tid;
     const bool colok = c4 < ld4;
     const float4* __restrict__ Rp =
         reinterpret_cast<const float4*>(a.R) + (size_t)row0 * ld4 + c4;
     constexpr int U = kFoldUnroll;
     float4 x[U];
-    int r = wave;
-    bool full = colok && r + kStepWaves * (U - 1) < nrows;
+    int r = 0;
+    bool full = colok && U <= nrows;
     if (full) {
 #pragma unroll
-        for (int q = 0; q < U; ++q)
-            x[q] = ld_stream(Rp + (size_t)(r + q * kStepWaves) * ld4);
+        for (int q = 0; q < U; ++q) x[q] = ld_stream(Rp + (size_t)q * ld4);
     }
     for (int q = tid; q < nrows; q += kStepThreads) vs[q] = a.v[row0 + q];
     __syncthreads();
+    if (!colok) return;
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     while (full) {
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const double v = vs[r + q * kStepWaves];
+            const double v = vs[r + q];
             acc0 = fma((double)x[q].x, v, acc0);
             acc1 = fma((double)x[q].y, v, acc1);
             acc2 = fma((double)x[q].z, v, acc2);
             acc3 = fma((double)x[q].w, v, acc3);
         }
-        r += kStepWaves * U;
-        full = r + kStepWaves * (U - 1) < nrows;
+        r += U;
+        full = r + U <= nrows;
         if (full) {
 #pragma unroll
-            for (int q = 0; q < U; ++q)
-                x[q] = ld_stream(Rp + (size_t)(r + q * kStepWaves) * ld4);
+            for (int q = 0; q < U; ++q) x[q] = ld_stream(Rp + (size_t)(r + q) * ld4);
         }
     }
-    if (colok) {
-        for (; r < nrows; r += kStepWaves) {
-            const float4 z = ld_stream(Rp + (size_t)r * ld4);
-            const double v = vs[r];
-            acc0 = fma((double)z.x, v, acc0);
-            acc1 = fma((double)z.y, v, acc1);
-            acc2 = fma((double)z.z, v, acc2);
-            acc3 = fma((double)z.w, v, acc3);
-        }
+    for (; r < nrows; ++r) {
+        const float4 z = ld_stream(Rp + (size_t)r * ld4);
+        const double v = vs[r];
+        acc0 = fma((double)z.x, v, acc0);
+        acc1 = fma((double)z.y, v, acc1);
+        acc2 = fma((double)z.z, v, acc2);
+        acc3 = fma((double)z.w, v, acc3);
     }
-    red[wave][4 * lane + 0] = acc0;
-    red[wave][4 * lane + 1] = acc1;
-    red[wave][4 * lane + 2] = acc2;
-    red[wave][4 * lane + 3] = acc3;
-    __syncthreads();
-    if (tid < kFoldCols) {
-        const int col = cc * kFoldCols + tid;
-        if (col < a.ldr) {
-            double s = 0.0;
-            for (int w = 0; w < kStepWaves; ++w) s += red[w][tid];
-            a.colpart[(size_t)rb * a.ldr + col] = s;
-        }
-    }
+    double* o = a.colpart + (size_t)rb * a.ldr + 4 * c4;
+    o[0] = acc0;
+    o[1] = acc1;
+    o[2] = acc2;
+    o[3] = acc3;
 }
 
 // ------------------------------------------------------------- a4, a5
-// Poisson likelihood (Eq. (logL)) from the fold partials.  Chunk cc owns
-// 256 columns; two threads per column add the row-block partials in a
-// fixed order, then mu_j, the deviance mu - n + n ln(n/mu) and
-// a_j = d(-2lnL)/d mu_j.  The chunk sums meet in the last work-group of the
-// role (arrival counter; only the writing wave fences), which adds the data
-// constant and the pulls.  Deterministic: no float atomics.
-__device__ void finish_role(const FoldArgs& a, int cc, double* smem,
-                            int* s_last) {
-    double (*ps)[kFoldCols] = reinterpret_cast<double (*)[kFoldCols]>(smem);
-    double* dred = smem + 2 * kFoldCols;
-    double* gred = dred + kStepWaves;
+// Poisson likelihood (Eq. (logL)) from the fold partials.  Group cc owns 64
+// columns; eight threads per column add every eighth partial row, the eight
+// sums meet in LDS in a fixed order, and wave 0 forms mu_j (backgrounds and
+// mask of the multi-component form included), the deviance
+// mu - n + n ln(n/mu) and a_j = d(-2lnL)/d mu_j, and writes the group's
+// sums.  No fence and no counter: the final role of the next launch adds
+// the group sums.  Deterministic: no float atomics.
+__device__ void finish_role(const FoldArgs& a, int cc, double* smem) {
+    double (*ps)[kFinCols] = reinterpret_cast<double (*)[kFinCols]>(smem);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int ci = tid & (kFoldCols - 1), qd = tid >> 8;
-    const int col = cc * kFoldCols + ci;
+    const int ci = tid % kFinCols, qd = tid / kFinCols;
+    const int col = cc * kFinCols + ci;
+    // up to 16 partial rows per thread are loaded before any is added
     double s = 0.0;
     if (col < a.n_reco) {
-        int q = qd;
-        for (; q + 6 < a.n_rb; q += 8) {
-            const double v0 = a.colpart[(size_t)q * a.ldr + col];
-            const double v1 = a.colpart[(size_t)(q + 2) * a.ldr + col];
-            const double v2 = a.colpart[(size_t)(q + 4) * a.ldr + col];
-            const double v3 = a.colpart[(size_t)(q + 6) * a.ldr + col];
-            s += v0;
-            s += v1;
-            s += v2;
-            s += v3;
+        constexpr int G = 16;
+        for (int q0 = qd; q0 < a.n_rb; q0 += G * kFinSplit) {
+            double v[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int q = q0 + k * kFinSplit;
+                v[k] = q < a.n_rb ? a.colpart[(size_t)q * a.ldr + col] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < G; ++k) s += v[k];
         }
-        for (; q < a.n_rb; q += 2) s += a.colpart[(size_t)q * a.ldr + col];
     }
     ps[qd][ci] = s;
     __syncthreads();
+    if (wave != 0) return;
     double dev = 0.0, gb = 0.0;
-    if (qd == 0 && col < a.n_reco) {
-        const double fold = ps[0][ci] + ps[1][ci];
+    if (col < a.n_reco) {
+        double fold = 0.0;
+#pragma unroll
+        for (int k = 0; k < kFinSplit; ++k) fold += ps[k][ci];
         double mu = fold, bj = 0.0;
         for (int q = 0; q < a.n_bkg; ++q) {
             const double t = a.b[(size_t)q * a.n_reco + col];
@@ -301,41 +306,31 @@ __device__ void finish_role(const FoldArgs& a, int cc, double* smem,
         const double aj = 2.0 * (1.0 - nj / mu);
         if (a.out_a) a.out_a[col] = aj;
         gb = aj * bj;
-    } else if (qd == 0 && col < a.ldr && a.out_a) {
+    } else if (col < a.ldr && a.out_a) {
         a.out_a[col] = 0.0;
     }
     dev = wave_sum(dev);
     gb = wave_sum(gb);
     if (lane == 0) {
-        dred[wave] = dev;
-        gred[wave] = gb;
+        a.chunk_dev[cc] = dev;
+        a.chunk_gb[cc] = gb;
     }
-    __syncthreads();
-    if (wave == 0) {
-        double d = 0.0, g = 0.0;
-        if (lane == 0) {
-            for (int w = 0; w < kStepWaves; ++w) {
-                d += dred[w];
-                g += gred[w];
-            }
-            a.chunk_dev[cc] = d;
-            a.chunk_gb[cc] = g;
-        }
-        __threadfence();
-        if (lane == 0) {
-            const unsigned prev = atomicAdd(&a.ctr[0], 1u);
-            *s_last = prev == (unsigned)(a.n_cc - 1);
-        }
+}
+
+// a5: -2lnL = 2 (sum of the group deviances + C_data) + pulls, and
+// sum_j a_j b_j for the gradient.  Lane q adds the group sums q, q + 64, ...;
+// the butterfly then adds the lanes in a fixed order.
+__device__ void final_role(const FoldArgs& a) {
+    if (threadIdx.x >= 64) return;
+    const int lane = threadIdx.x;
+    double d = 0.0, g = 0.0;
+    for (int q = lane; q < a.n_cc; q += 64) {
+        d += a.chunk_dev[q];
+        g += a.chunk_gb[q];
     }
-    __syncthreads();
-    if (!*s_last || wave != 0) return;
-    __threadfence();
+    d = wave_sum(d);
+    g = wave_sum(g);
     if (lane == 0) {
-        double d = 0.0, g = 0.0;
-        for (int q = 0; q < a.n_cc; ++q) {
-            d += a.chunk_dev[q];
-            g += a.chunk_gb[q];
-        }
         double pulls = 0.0;
         for (int i = 0; i < a.n_theta; ++i)
             if (a.pull_sigma[i] > 0.0) {
@@ -344,35 +339,41 @@ __device__ void finish_role(const FoldArgs& a, int cc, double* smem,
             }
         a.out_nll[0] = 2.0 * d + 2.0 * a.cdata + pulls;
         if (a.out_gb) a.out_gb[0] = g;
-        a.ctr[0] = 0u;
     }
 }
 
-// Work-groups [0, nb_fold) fold one point, the next nb_rows form the
-// weights of another, the next nb_scan (one per source) build the node
-// table of a third and the last nb_fin finish a fourth.  Fold tiles come
-// first so that every compute unit starts streaming R at once; the short
-// work-groups of the other roles fill the remaining slots.  The role branch
-// is uniform over the work-group.
+// Work-group 0 (when nb_final = 1) completes the likelihood of one point,
+// the next nb_fin reduce the fold of another, the next nb_scan (one per
+// source) build the node table of a third, the next nb_rows form the
+// weights of a fourth and the rest fold a fifth.  The short roles come
+// first: their few dependent loads go out before the fold tiles saturate
+// HBM, and every work-group of a launch is resident at once, so they finish
+// well inside the fold.  No role of a launch waits for another: nothing in
+// the kernel fences.  The role branch is uniform over the work-group.
 __device__ __forceinline__ void step_body(const StepArgs& a) {
     __shared__ __attribute__((aligned(16))) double smem[kSmemDoubles];
-    __shared__ int s_last;
     int b = blockIdx.x;
-    if (b < a.nb_fold) {
-        fold_role(a.fold, b % a.fold.n_rb, b / a.fold.n_rb, smem);
+    if (b < a.nb_final) {
+        final_role(a.fnl);
         return;
     }
-    b -= a.nb_fold;
+    b -= a.nb_final;
+    if (b < a.nb_fin) {
+        finish_role(a.fin, b, smem);
+        return;
+    }
+    b -= a.nb_fin;
+    if (b < a.nb_scan) {
+        scan_role(a.scan, b, smem);
+        return;
+    }
+    b -= a.nb_scan;
     if (b < a.nb_rows) {
         rows_role(a.rows, b);
         return;
     }
     b -= a.nb_rows;
-    if (b < a.nb_scan) {
-        scan_role(a.scan, b, smem);
-        return;
-    }
-    finish_role(a.fin, b - a.nb_scan, smem, &s_last);
+    fold_role(a.fold, b % a.fold.n_rb, b / a.fold.n_rb, smem);
 }
 
 // The steady-state launch of the pipeline (all four roles) and every other
@@ -512,16 +513,23 @@ __global__ __launch_bounds__(256) void k_adjoint_finish(AdjArgs a, int grid) {
 }  // namespace
 
 hipError_t launch_step(const StepArgs& a, hipStream_t s) {
-    if (a.nb_fold > 0 && (a.fold.rows_per_wg > kFoldMaxRows || a.fold.rows_per_wg <= 0 ||
-                          a.nb_fold != a.fold.n_rb * a.fold.n_cc))
+    if (a.nb_fold > 0 &&
+        (a.fold.rows_per_wg > kFoldMaxRows || a.fold.rows_per_wg <= 0 ||
+         a.fold.n_fc != (a.fold.ldr / 4 + kFoldTile4 - 1) / kFoldTile4 ||
+         a.nb_fold != a.fold.n_rb * a.fold.n_fc ||
+         (size_t)a.fold.n_rb * a.fold.rows_per_wg < (size_t)a.fold.n_t))
         return hipErrorInvalidValue;
-    if (a.nb_fin > 0 && a.nb_fin != a.fin.n_cc) return hipErrorInvalidValue;
+    if (a.nb_fin > 0 && (a.nb_fin != a.fin.n_cc ||
+                         a.fin.n_cc != (a.fin.n_reco + kFinCols - 1) / kFinCols))
+        return hipErrorInvalidValue;
     if (a.nb_rows > 0 &&
         a.nb_rows != (a.rows.n_comp * a.rows.n_t + kStepThreads - 1) / kStepThreads)
         return hipErrorInvalidValue;
-    const int grid = a.nb_fold + a.nb_rows + a.nb_scan + a.nb_fin;
+    if (a.nb_final < 0 || a.nb_final > 1) return hipErrorInvalidValue;
+    const int grid = a.nb_fold + a.nb_rows + a.nb_scan + a.nb_fin + a.nb_final;
     if (grid <= 0) return hipSuccess;
-    const bool full = a.nb_fold > 0 && a.nb_rows > 0 && a.nb_scan > 0 && a.nb_fin > 0;
+    const bool full = a.nb_fold > 0 && a.nb_rows > 0 && a.nb_scan > 0 && a.nb_fin > 0 &&
+                      a.nb_final > 0;
     if (full)
         hipLaunchKernelGGL(k_step, dim3(grid), dim3(kStepThreads), 0, s, a);
     else

@@ -113,6 +113,23 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_gemm(MlpGemm g) {
     // Output (i, j) of a 32x32 block: lane j + 32 * ((i / 4) % 2),
     // register (i / 8) * 4 + i % 4.
     double lsum = 0.0;
+    // fused likelihood: a lane always sees the same two columns, so their
+    // data terms are formed once; ln mu is the network output itself, so
+    // n ln(n/mu) = n ln n - n ln mu needs one exponential per output and no
+    // logarithm
+    double cn[2] = {0.0, 0.0}, nob[2] = {0.0, 0.0}, mn[2] = {0.0, 0.0}, sd[2] = {0.0, 0.0};
+    if (MODE == kMlpNll) {
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int n = n0 + wn * 64 + bj * 32 + li;
+            if (n < g.N) {
+                nob[bj] = g.nobs[n];
+                cn[bj] = nob[bj] > 0.0 ? nob[bj] * log(nob[bj]) - nob[bj] : 0.0;
+                mn[bj] = g.mean[n];
+                sd[bj] = g.stdv[n];
+            }
+        }
+    }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
@@ -141,9 +158,10 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_gemm(MlpGemm g) {
                 } else if (MODE == kMlpLogMu) {
                     g.C32[(long)m * g.ldc + n] = g.mean[n] + g.stdv[n] * v;
                 } else if (MODE == kMlpNll) {
-                    const double mu = exp((double)g.mean[n] + (double)g.stdv[n] * (double)v);
-                    const double nj = g.nobs[n];
-                    rowpart += nj > 0.0 ? (mu - nj + nj * log(nj / mu)) : mu;
+                    // deviance mu - n + n ln(n / mu), ln mu kept in FP64
+                    const double lm = fma(sd[bj], (double)v, mn[bj]);
+                    const double mu = (double)__expf((float)lm);
+                    rowpart += mu + cn[bj] - nob[bj] * lm;
                 }
             }
             if (MODE == kMlpNll) {

@@ -70,3 +70,45 @@ def test_batched_gradient_paper_scale(cfg1):
         assert abs(nl[i] - v) <= 1e-3
         scale = np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())
         assert np.all(np.abs(gr[i] - rg) <= 1e-4 * scale + 1e-6), (i, gr[i], rg)
+
+
+def test_plain_nll_paper_scale_sampled(cfg1):
+    """The benchmark's path (device pointers, graph replay of the step-kernel
+    chain) at the paper-scale shapes, sampled points against the oracle."""
+    import torch
+    p, ctx = cfg1
+    o = p["oracle"]
+    dev = torch.device("cuda:0")
+    th = np.vstack([synth.theta_sm()[None], synth.theta_corners()[[0, 31]],
+                    synth.theta_prior(29, 3005, f_range=(0.8, 1.2))])
+    tt = torch.tensor(th, dtype=torch.float64, device=dev)
+    out = torch.empty(len(th), dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream(device=dev)
+    for _ in range(2):                      # capture, then a replay
+        ctx.eval_nll_dev(tt, out, stream=s)
+        s.synchronize()
+    got = out.cpu().numpy()
+    worst = 0.0
+    for i in range(0, len(th), 4):
+        d = abs(got[i] - o.nll(th[i]))
+        worst = max(worst, d)
+        assert d <= 1e-3, (i, got[i])
+    log(f"[gpu] paper scale (device path): max |d(-2lnL)| {worst:.2e} over "
+        f"{len(range(0, len(th), 4))} sampled points")
+
+
+def test_batched_mu_paper_scale(cfg1):
+    """Expected spectra at the paper-scale shapes through the batched
+    method, bin by bin against the oracle."""
+    p, ctx = cfg1
+    o = p["oracle"]
+    th = np.vstack([synth.theta_sm()[None], synth.theta_prior(3, 3006, f_range=(0.8, 1.2))])
+    mu = ctx.eval_mu_batched(th)
+    worst = 0.0
+    for i in range(len(th)):
+        ref = o.mu(th[i])
+        scale = np.maximum(np.abs(ref), 1e-9 * np.abs(ref).max())
+        r = float(np.max(np.abs(mu[i] - ref) / scale))
+        worst = max(worst, r)
+        assert r <= 1e-5, (i, r)
+    log(f"[gpu] paper scale batched mu: max rel diff {worst:.2e}")

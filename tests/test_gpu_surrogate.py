@@ -93,6 +93,18 @@ def test_surrogate_accuracy_and_fallback(trained, torch_dev):
     log(f"[gpu] surrogate |d(-2lnL)| on validation: median {np.median(d):.3g}, "
         f"90% {np.quantile(d, 0.9):.3g}, max {d.max():.3g}; "
         f"within 0.1: {np.mean(d <= 0.1):.3f}")
+    # the fused output layer + likelihood kernel against -2lnL formed on the
+    # host from the network's own log mu (no pulls on this context)
+    import math
+    nobs = p["n"]
+    cdata = float(np.sum(nobs - np.where(nobs > 0, nobs * np.log(np.where(nobs > 0, nobs, 1)), 0)
+                         + np.array([math.lgamma(x + 1.0) for x in nobs])))
+    lm = s.logmu(th_val[:256]).cpu().numpy().astype(np.float64)
+    mu_h = np.exp(lm)
+    dvs = np.sum(mu_h - nobs + np.where(nobs > 0, nobs * (np.log(np.where(nobs > 0, nobs, 1)) - lm), 0.0), axis=1)
+    ref = 2.0 * (dvs + cdata)
+    fused = nll_s[:256].cpu().numpy()
+    assert np.all(np.abs(fused - ref) <= 1e-2 + 1e-6 * np.abs(ref)), np.max(np.abs(fused - ref))
     # the exact reference itself against the oracle on a few points
     ev = exact.cpu().numpy()
     tv = th_val.cpu().numpy()

@@ -128,10 +128,10 @@ def test_grouped_graph_replay_and_grad(multi):
             assert np.all(np.abs(g[i] - rg) <= 1e-4 * scale + 1e-6), (d, i)
 
 
-@pytest.mark.parametrize("cfg", ["0", "1", "2", "3"])
+@pytest.mark.parametrize("cfg", [str(c) for c in range(4)])
 def test_every_tile_configuration(cfg, monkeypatch):
-    """Each GEMM tile shape the autotuner may pick gives the same results
-    (tile edges in M, N and K included)."""
+    """Each GEMM tile shape the autotuner may pick gives the same
+    likelihoods and gradients (tile edges in M, N and K included)."""
     import paper_2607_00488_amd as nr
     monkeypatch.setenv("NR_GEMM_CONFIG", cfg)
     probs, ctxs, ths = [], [], []
@@ -144,6 +144,14 @@ def test_every_tile_configuration(cfg, monkeypatch):
     for d, (p, th, out) in enumerate(zip(probs, ths, outs)):
         for i in range(0, len(th), max(1, len(th) // 8)):
             assert abs(out[i] - p["oracle"].nll(th[i])) <= 1e-3, (cfg, d, i)
+    # the adjoint product on the same configuration
+    th = ths[1][:24]
+    nll, g = ctxs[1].eval_nll_grad_batched(th)
+    for i in range(0, len(th), 6):
+        v, rg = probs[1]["oracle"].nll_grad(th[i])
+        assert abs(nll[i] - v) <= 1e-3
+        scale = np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())
+        assert np.all(np.abs(g[i] - rg) <= 1e-4 * scale + 1e-6), (cfg, i)
     for c in ctxs:
         c.close()
 

@@ -118,8 +118,8 @@ int nr_set_data(nr_ctx *ctx, const double *n, const double *b, int n_reco,
  * the reachable nodes, as suffix sums of the per-node Laurent coefficients
  * in T), weights, HBM-streaming fold and likelihood reduction.  Successive
  * points overlap: one launch folds point p while it forms the weights of
- * p + 1, the node table of p + 2 and the likelihood of p - 1.  nll:
- * [n_pts] host.  Synchronous. */
+ * p + 1, the node table of p + 2, reduces the fold of p - 1 and completes
+ * the likelihood of p - 2.  nll: [n_pts] host.  Synchronous. */
 int nr_eval_nll(nr_ctx *ctx, const double *theta, int n_pts, double *nll);
 
 /* -2lnL and its gradient d(-2lnL)/d theta ([n_pts][7]) per point, through

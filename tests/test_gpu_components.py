@@ -113,3 +113,47 @@ def test_back_to_single_component():
     assert ctx.n_theta == 7
     assert np.array_equal(ctx.eval_nll(th), before)
     ctx.close()
+
+
+def test_component_argument_errors():
+    """Host-side validation of the multi-component setup: every error is a
+    status code, before any device work."""
+    import paper_2607_00488_amd as nr
+    n_t, n_reco = 64, 32
+    src = synth.source_nodes(16)
+    d = synth.component_inputs(n_t, n_reco, 20_000, 81)
+    ctx = nr.Context(0)
+    with pytest.raises(nr.NrError):                  # before set_sources
+        ctx.set_components(d["comp_of_source"], d["hist"], d["scale"], d["rate_sm"])
+    ctx.set_sources(src, n_t)
+    bad = d["comp_of_source"].copy()
+    bad[0] = 7                                       # component out of range
+    with pytest.raises(nr.NrError):
+        ctx.set_components(bad, d["hist"], d["scale"], d["rate_sm"])
+    bad = np.zeros(5, np.int32)                      # components 1..4 empty
+    with pytest.raises(nr.NrError):
+        ctx.set_components(bad, d["hist"][:2], d["scale"][:2], d["rate_sm"][:2])
+    h = d["hist"].copy()
+    h[2] = 0.0                                       # an empty histogram
+    with pytest.raises(nr.NrError):
+        ctx.set_components(d["comp_of_source"], h, d["scale"], d["rate_sm"])
+    h = d["hist"].copy()
+    h[1, 3, 4] = np.nan
+    with pytest.raises(nr.NrError):
+        ctx.set_components(d["comp_of_source"], h, d["scale"], d["rate_sm"])
+    with pytest.raises(nr.NrError):                  # 5 + 5 + 23 > 32 parameters
+        ctx.set_components(d["comp_of_source"], d["hist"], d["scale"], d["rate_sm"],
+                           bkg_pdf=np.ones((23, n_reco)), bkg_rate=np.ones(23))
+    with pytest.raises(nr.NrError):                  # non-positive exposure
+        ctx.set_components(d["comp_of_source"], d["hist"], d["scale"], d["rate_sm"],
+                           exposure=0.0)
+    ctx.set_components(d["comp_of_source"], d["hist"], d["scale"], d["rate_sm"],
+                       bkg_pdf=d["bkg_pdf"], bkg_rate=d["bkg_rate"])
+    with pytest.raises(nr.NrError):                  # data not set again yet
+        ctx.eval_nll(np.concatenate([np.zeros(5), np.ones(7)])[None])
+    with pytest.raises(ValueError):                  # pulls of the old length
+        ctx.set_data(np.ones(n_reco), None, np.zeros(7), np.ones(7))
+    ctx.set_data(np.ones(n_reco), None)
+    v = ctx.eval_nll(np.concatenate([np.zeros(5), np.ones(7)])[None])
+    assert np.isfinite(v).all()
+    ctx.close()

@@ -369,13 +369,15 @@ def main():
     # the same launch after 512 MiB have been written over the device's
     # caches (the 256 MB Infinity Cache included): the cold-cache figure
     flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)
-    cold = []
+    cold, warm = [], []
     for i in range(20):
         flush.fill_(float(i))
         torch.cuda.synchronize()
         cold.append(ctx.time_stage(5, 1))
+        warm.append(ctx.time_stage(5, 1))   # the same single launch, warm
     del flush
     step_cold_ms = float(np.mean(cold))
+    step_warm1_ms = float(np.mean(warm))
     fold_ms = ctx.time_stage(4, 200)
     fold_lik_ms = ctx.time_stage(2, 200)
     eint_ms = ctx.time_stage(1, 200)
@@ -400,6 +402,7 @@ def main():
                            sync_latency_ms_std=round(float(lat.std()), 4),
                            eint_weights_us=round(eint_ms * 1e3, 2),
                            step_back_to_back_us=round(step_bb_ms * 1e3, 2),
+                           step_single_launch_us=round(step_warm1_ms * 1e3, 2),
                            step_after_cache_flush_us=round(step_cold_ms * 1e3, 2),
                            fold_alone_us=round(fold_ms * 1e3, 2),
                            fold_plus_likelihood_us=round(fold_lik_ms * 1e3, 2)))

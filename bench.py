@@ -366,12 +366,14 @@ def main():
     # for the breakdown
     step_ms = dev_ms / K
     step_bb_ms = ctx.time_stage(5, 200)
-    # the same launch after 512 MiB have been written over the device's
-    # caches (the 256 MB Infinity Cache included): the cold-cache figure
-    flush = torch.empty(1 << 27, dtype=torch.float32, device=dev)
+    # the same launch after 512 MiB of other data have been read through the
+    # device's caches (the 256 MB Infinity Cache included): the cold-cache
+    # figure (a read, so no dirty lines are left to write back)
+    flush = torch.ones(1 << 27, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
     cold, warm = [], []
     for i in range(20):
-        flush.fill_(float(i))
+        flush.sum()
         torch.cuda.synchronize()
         cold.append(ctx.time_stage(5, 1))
         warm.append(ctx.time_stage(5, 1))   # the same single launch, warm

@@ -376,6 +376,9 @@ nr::FoldArgs fold_args(nr_ctx* c, const double* thp, const double* v,
     fa.n_rb = c->n_rb;
     fa.n_fc = c->n_fc;
     fa.n_cc = c->n_cc;
+    fa.reverse = 0;
+    // responses beyond twice the 256 MB Infinity Cache stream past it
+    fa.stream_nt = (double)c->n_rows * c->ldr * sizeof(float) > 512.0e6;
     return fa;
 }
 
@@ -425,9 +428,14 @@ int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
                         w ? w + (size_t)p * c->n_rows : nullptr, nullptr, thp(p));
     };
     auto fa = [&](int p) {
-        return fold_args(c, thp(p), c->d_v[p & 1], c->d_colpart + (p & 1) * cp,
-                         nll + p, mu ? mu + (size_t)p * c->n_reco : nullptr,
-                         grad != nullptr, p & 1);
+        nr::FoldArgs f = fold_args(c, thp(p), c->d_v[p & 1],
+                                   c->d_colpart + (p & 1) * cp, nll + p,
+                                   mu ? mu + (size_t)p * c->n_reco : nullptr,
+                                   grad != nullptr, p & 1);
+        // a scan walks R forwards and backwards in turn, so each point starts
+        // on the rows the previous one left in the Infinity Cache
+        f.reverse = (grad || f.stream_nt) ? 0 : (p & 1);
+        return f;
     };
     auto in = [&](int p) { return p >= 0 && p < n_pts; };
     int rc;

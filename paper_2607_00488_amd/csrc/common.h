@@ -84,6 +84,8 @@ struct FoldArgs {
     int n_rb;             // fold row tiles = partial rows
     int n_fc;             // fold column tiles (2048 columns each)
     int n_cc;             // reduction groups (64 columns each)
+    int reverse;          // fold: walk the tile's rows last to first
+    int stream_nt;        // fold: read R without cache allocation
 };
 
 // One launch of the single-point step kernel: nb_fold = n_rb * n_fc

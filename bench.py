@@ -125,6 +125,53 @@ def time_batched(ctxs, ths, reps=3, grad=False):
                                                 [g.cpu().numpy() for g in gr])
 
 
+def templates_form(ctx, seed, n_pts=65536, reps=5):
+    """The template form at the paper-scale shapes: the 20 basis templates
+    and the S_SM = 0 rows folded once through R (one FP64 pass), then 21
+    products and one logarithm per (point, reco bin).  Timed with events on
+    the stream the kernels run on; a few points checked against the plain
+    (single-point streaming) method."""
+    import torch
+    import synth
+    dev = torch.device("cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.build_templates()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    th = synth.theta_prior(n_pts, seed, f_range=(0.8, 1.2))
+    tt = torch.tensor(th, dtype=torch.float64, device=dev)
+    nl = torch.empty(n_pts, dtype=torch.float64, device=dev)
+    gr = torch.empty(n_pts, 7, dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream(device=dev)
+    ms = {}
+    for mode, g in (("nll", None), ("nll_grad", gr)):
+        ctx.eval_nll_templates_dev(tt, nl, g, stream=s)
+        s.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            ctx.eval_nll_templates_dev(tt, nl, g, stream=s)
+        e1.record(s)
+        s.synchronize()
+        ms[mode] = e0.elapsed_time(e1) / reps
+    got = nl.cpu().numpy()
+    k = 16
+    plain = ctx.eval_nll(th[:k])
+    bins = float(n_pts) * ctx.n_reco
+    return dict(
+        evals_per_s=round(n_pts / (ms["nll"] * 1e-3), 1),
+        grad_evals_per_s=round(n_pts / (ms["nll_grad"] * 1e-3), 1),
+        points=n_pts, ms=round(ms["nll"], 3), grad_ms=round(ms["nll_grad"], 3),
+        ns_per_point_bin=round(ms["nll"] * 1e6 / bins, 4),
+        template_fold_ms=round(build_ms, 2),
+        max_abs_dnll_vs_plain=float(np.max(np.abs(got[:k] - plain))),
+        bound="alu",
+        what="exact template form: mu_j = f_bkg b_j + G0_j + sum_b c_b(theta) "
+             "G_bj with the 20 basis templates folded once through R; per "
+             "(point, bin) 21 FP64 products and one FP64 logarithm")
+
+
 def surrogate_form(ctx, train_seconds=20.0):
     """The learned surrogate at the paper-scale binning: 7 -> 256 -> 256 ->
     256 -> 4096 SiLU MLP trained on 2^18 spectra from the batched method
@@ -424,6 +471,11 @@ def main():
         tflops=round(2.0 * 1024 * c.n_t * c.n_reco / dtb / 1e12, 2))
     log(f"[bench] grad batched: {1024 / dtg:.0f} evals/s; nll batched "
         f"{1024 / dtb:.0f} evals/s")
+    forms["templates"] = tf = templates_form(ctx, p["seeds"]["theta"] + 7)
+    log(f"[bench] templates: {tf['evals_per_s']:.0f} evals/s "
+        f"({tf['grad_evals_per_s']:.0f} with gradient), fold "
+        f"{tf['template_fold_ms']:.1f} ms once, max |d| vs plain "
+        f"{tf['max_abs_dnll_vs_plain']:.2e}")
     if not args.no_batched:
         ctxs, ths, flops = build_batched()
         dt2, _, _ = time_batched(ctxs, ths, reps=2)

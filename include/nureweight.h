@@ -312,6 +312,41 @@ int nr_mlp_nll_dev(nr_mlp *mlp, nr_ctx *ctx, const double *d_theta, int B,
 int nr_eval_mu_batched_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
                            double *d_mu, void *stream);
 
+/* Template form (single-component contexts).  The cross section of
+ * Eqs. (xs_nsi) and (xs_mm) is linear in the coupling products, m2 and
+ * f_8B, so S_theta of Eq. (fT) is sum_b c_b(theta) I_b over 20
+ * theta-independent basis spectra, and the fold of Eq. (matrix_reweight)
+ * separates exactly:
+ *   mu_j = f_bkg b_j + G0_j + sum_b c_b(theta) G_bj,
+ *   G_bj = sum_l R_lj m_l I_b(T_l) / S_SM(T_l) over rows with S_SM > 0,
+ *   G0_j = sum_l R_lj m_l over rows with S_SM = 0 (weight 1).
+ * The templates G are folded once (one FP64 pass over R); a point then
+ * costs 21 products and one logarithm per reco bin.  Same results as the
+ * plain and batched forms up to rounding order.
+ *
+ * nr_build_templates folds them now (synchronous; allocates).  Any set_*
+ * call invalidates them, and the first evaluation after it folds them
+ * again (synchronising and allocating, so call nr_build_templates first
+ * when the evaluation is to be captured in a graph).  A multi-component
+ * context returns NR_ESTATE. */
+int nr_build_templates(nr_ctx *ctx);
+
+/* -2lnL ([n_pts], host) and, when grad is not NULL, its gradient
+ * ([n_pts][7], host) by the template form.  Synchronous. */
+int nr_eval_nll_templates(nr_ctx *ctx, const double *theta, int n_pts,
+                          double *nll, double *grad);
+
+/* Expected spectra ([n_pts][n_reco], host) by the template form. */
+int nr_eval_mu_templates(nr_ctx *ctx, const double *theta, int n_pts,
+                         double *mu);
+
+/* Device-pointer variant: d_theta [n_pts][7], d_nll [n_pts], d_grad
+ * [n_pts][7] or NULL, all FP64 on the context's device; enqueued on
+ * `stream` (NULL = the default stream), returns without waiting.  Calls
+ * that overlap on one context share its partial-sum buffers and race. */
+int nr_eval_nll_templates_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
+                              double *d_nll, double *d_grad, void *stream);
+
 /* Message for the last non-zero status on this thread. */
 const char *nr_last_error(void);
 

@@ -32,6 +32,8 @@ EXPORTS = (
     "nr_mlp_get_params", "nr_mlp_get_grads", "nr_mlp_set_box",
     "nr_mlp_set_output_norm", "nr_mlp_targets_dev", "nr_mlp_train_step_dev",
     "nr_mlp_logmu_dev", "nr_mlp_nll_dev", "nr_eval_mu_batched_dev",
+    "nr_build_templates", "nr_eval_nll_templates", "nr_eval_mu_templates",
+    "nr_eval_nll_templates_dev",
 )
 
 
@@ -135,6 +137,10 @@ def load():
     L.nr_mlp_logmu_dev.argtypes = [P, P, I, P, P]
     L.nr_mlp_nll_dev.argtypes = [P, P, P, I, P, P, P]
     L.nr_eval_mu_batched_dev.argtypes = [P, P, I, P, P]
+    L.nr_build_templates.argtypes = [P]
+    L.nr_eval_nll_templates.argtypes = [P, pD, I, pD, pD]
+    L.nr_eval_mu_templates.argtypes = [P, pD, I, pD]
+    L.nr_eval_nll_templates_dev.argtypes = [P, P, I, P, P, P]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("nr_destroy", "nr_stream", "nr_last_error",
@@ -303,6 +309,34 @@ def nr_eval_nll_dev(h, d_theta_ptr, n_pts, d_nll_ptr, d_grad_ptr=None,
                                   C.c_void_p(d_nll_ptr),
                                   C.c_void_p(d_grad_ptr or 0),
                                   C.c_void_p(stream_ptr or 0)))
+
+
+def nr_build_templates(h):
+    _check(load().nr_build_templates(h))
+
+
+def nr_eval_nll_templates(h, theta, grad=False):
+    th = _f64(theta, (-1, NR_NTHETA))
+    out = np.empty(th.shape[0])
+    g = np.empty((th.shape[0], NR_NTHETA)) if grad else None
+    _check(load().nr_eval_nll_templates(h, _dp(th), th.shape[0], _dp(out),
+                                        _dp(g) if grad else None))
+    return (out, g) if grad else out
+
+
+def nr_eval_mu_templates(h, theta, n_reco):
+    th = _f64(theta, (-1, NR_NTHETA))
+    out = np.empty((th.shape[0], n_reco))
+    _check(load().nr_eval_mu_templates(h, _dp(th), th.shape[0], _dp(out)))
+    return out
+
+
+def nr_eval_nll_templates_dev(h, d_theta_ptr, n_pts, d_nll_ptr, d_grad_ptr=None,
+                              stream_ptr=None):
+    _check(load().nr_eval_nll_templates_dev(h, C.c_void_p(d_theta_ptr), int(n_pts),
+                                            C.c_void_p(d_nll_ptr),
+                                            C.c_void_p(d_grad_ptr or 0),
+                                            C.c_void_p(stream_ptr or 0)))
 
 
 def nr_get_reference(h, n_t):
@@ -540,10 +574,7 @@ class Context:
     def eval_mu_batched(self, theta):
         return nr_eval_mu_batched(self.h, theta, self.n_reco)
 
-    def eval_nll_dev(self, theta_t, nll_t, grad_t=None, stream=None):
-        """torch tensors on this device: theta [P, n_theta] f64, nll [P]
-        f64, grad [P, 7] f64 or None; enqueued on `stream` (a torch stream,
-        or None for the HIP default stream)."""
+    def _dev_args(self, theta_t, nll_t, grad_t):
         assert theta_t.dtype == nll_t.dtype and str(theta_t.dtype).endswith("float64")
         assert theta_t.is_contiguous() and nll_t.is_contiguous()
         if theta_t.dim() != 2 or theta_t.shape[1] != self.n_theta:
@@ -551,10 +582,35 @@ class Context:
         if nll_t.numel() < theta_t.shape[0] or (
                 grad_t is not None and grad_t.numel() < 7 * theta_t.shape[0]):
             raise ValueError("output tensors are too small")
+        if grad_t is not None:
+            assert grad_t.dtype == nll_t.dtype and grad_t.is_contiguous()
+
+    def eval_nll_dev(self, theta_t, nll_t, grad_t=None, stream=None):
+        """torch tensors on this device: theta [P, n_theta] f64, nll [P]
+        f64, grad [P, 7] f64 or None; enqueued on `stream` (a torch stream,
+        or None for the HIP default stream)."""
+        self._dev_args(theta_t, nll_t, grad_t)
         sp = None if stream is None else stream.cuda_stream
         nr_eval_nll_dev(self.h, theta_t.data_ptr(), theta_t.shape[0],
                         nll_t.data_ptr(),
                         None if grad_t is None else grad_t.data_ptr(), sp)
+
+    def build_templates(self):
+        nr_build_templates(self.h)
+
+    def eval_nll_templates(self, theta, grad=False):
+        return nr_eval_nll_templates(self.h, theta, grad)
+
+    def eval_mu_templates(self, theta):
+        return nr_eval_mu_templates(self.h, theta, self.n_reco)
+
+    def eval_nll_templates_dev(self, theta_t, nll_t, grad_t=None, stream=None):
+        """The template form on torch tensors, as eval_nll_dev."""
+        self._dev_args(theta_t, nll_t, grad_t)
+        sp = None if stream is None else stream.cuda_stream
+        nr_eval_nll_templates_dev(self.h, theta_t.data_ptr(), theta_t.shape[0],
+                                  nll_t.data_ptr(),
+                                  None if grad_t is None else grad_t.data_ptr(), sp)
 
 
 def eval_nll_multi(contexts, thetas):

@@ -71,6 +71,67 @@ struct ContractArgs {
 };
 
 
+// Template form.  S_theta = sum_b c_b(theta) I_b with theta-independent
+// basis spectra I_b, so the fold separates into templates folded once:
+//   mu_j = f_bkg b_j + G0_j + sum_b c_b(theta) G_bj,
+//   G_bj = sum_{l: S_SM(T_l) > 0} F_bl R_lj,  F_bl = m_l I_b(T_l) / S_SM(T_l),
+//   G0_j = sum_{l: S_SM(T_l) = 0} m_l R_lj   (rows with w := 1).
+constexpr int kTmplCols = kNBasis + 1;     // G_0..G_19, G0
+constexpr int kTmplRec = 24;               // per reco bin: G_0..G_19, G0, b, n, ln n
+constexpr int kTmplSlabRows = 256;         // response rows per template-fold work-group
+constexpr int kTmplWave = 64;              // points per evaluation work-group
+
+struct TmplFoldArgs {
+    const float* R;
+    int ldr, n_t, n_reco;
+    const double* F;   // [n_t][kTmplCols] row factors
+    double* part;      // [n_slab][kTmplCols][n_reco]
+};
+
+struct TmplRecArgs {
+    const double* part;
+    int n_slab, n_reco;
+    const double* n;   // [n_reco] data
+    const double* b;   // [n_reco] background
+    double* rec;       // [n_reco][kTmplRec]
+};
+
+struct TmplEvalArgs {
+    const double* rec;    // [n_reco][kTmplRec]
+    const double* theta;  // [n_pts][7]
+    int n_reco, n_pts, cols_per;
+    Phys ph;
+    double* dpart;        // [n_split][n_pts] deviance partials
+    double* hpart;        // [n_split][kTmplCols][n_pts] or null (gradient)
+    double* mu;           // [n_pts][n_reco] or null
+};
+
+// Slice sums in slice order: red[0][p] = deviance, red[1 + b][p] = h_b.
+struct TmplReduceArgs {
+    const double* dpart;
+    const double* hpart;  // or null
+    int n_pts, n_split;
+    double* red;          // [1 + kTmplCols][n_pts] (first row only without hpart)
+};
+
+struct TmplFinalArgs {
+    const double* red;    // [1 + kTmplCols][n_pts] (first row only without grad)
+    const double* theta;
+    int n_pts;
+    double cdata;
+    double pull_mean[kNTheta];
+    double pull_sigma[kNTheta];
+    Phys ph;
+    double* nll;
+    double* grad;         // [n_pts][7] or null
+};
+
+hipError_t launch_tmpl_fold(const TmplFoldArgs& a, int n_slab, hipStream_t s);
+hipError_t launch_tmpl_records(const TmplRecArgs& a, hipStream_t s);
+hipError_t launch_tmpl_eval(const TmplEvalArgs& a, int n_split, hipStream_t s);
+hipError_t launch_tmpl_reduce(const TmplReduceArgs& a, hipStream_t s);
+hipError_t launch_tmpl_final(const TmplFinalArgs& a, hipStream_t s);
+
 hipError_t launch_wgen(const WgenArgs& a, hipStream_t s);
 // Tile configurations of the GEMM: 0: 128x128, 1: 64x128, 2: 128x64,
 // 3: 64x64 (M x N per work-group).

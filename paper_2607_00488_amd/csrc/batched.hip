@@ -7,6 +7,7 @@
 // matrix cores the -2lnL of prior-box corner points drifts by ~1.3e-3 from
 // the FP64 reference, above the 1e-3 budget.
 #include "batched.h"
+#include "lnpos.h"
 
 #include <cmath>
 
@@ -378,7 +379,175 @@ __global__ __launch_bounds__(256) void k_adj_contract(ContractArgs a) {
     }
 }
 
+// ------------------------------------------------------------ templates
+// One thread per reco bin, one work-group row per slab of response rows:
+// kTmplCols FP64 sums of F_bl R_lj.  The row factors are wave-uniform.
+__global__ __launch_bounds__(256) void k_tmpl_fold(TmplFoldArgs a) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.n_reco) return;
+    const int l0 = blockIdx.y * kTmplSlabRows;
+    const int l1 = min(l0 + kTmplSlabRows, a.n_t);
+    double acc[kTmplCols];
+#pragma unroll
+    for (int b = 0; b < kTmplCols; ++b) acc[b] = 0.0;
+    for (int l = l0; l < l1; ++l) {
+        const double r = a.R[(size_t)l * a.ldr + j];
+        const double* f = a.F + (size_t)l * kTmplCols;
+#pragma unroll
+        for (int b = 0; b < kTmplCols; ++b) acc[b] = fma(f[b], r, acc[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < kTmplCols; ++b)
+        a.part[((size_t)blockIdx.y * kTmplCols + b) * a.n_reco + j] = acc[b];
+}
+
+// Slab sums in slab order, then the data of the bin beside its templates.
+__global__ __launch_bounds__(256) void k_tmpl_records(TmplRecArgs a) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.n_reco) return;
+    double* r = a.rec + (size_t)j * kTmplRec;
+    for (int b = 0; b < kTmplCols; ++b) {
+        double s = 0.0;
+        for (int q = 0; q < a.n_slab; ++q) s += a.part[((size_t)q * kTmplCols + b) * a.n_reco + j];
+        r[b] = s;
+    }
+    const double nj = a.n[j];
+    r[kTmplCols] = a.b[j];
+    r[kTmplCols + 1] = nj;
+    r[kTmplCols + 2] = nj > 0.0 ? ln_pos(nj) : 0.0;
+}
+
+// One thread per point, one work-group column per slice of reco bins.  The
+// bin record is the same for every lane (scalar loads); each lane forms
+// mu_j, the deviance term of Eq. (logL) and, for the gradient, the
+// contractions h_b = sum_j a_j G_bj with a_j = 2 (1 - n_j / mu_j).  The
+// logarithm is the plain-FP64 series of lnpos.h (the library one spends
+// ~85 double-double operations per bin for accuracy the sum cannot use).
+template <bool GRAD, bool MU>
+__global__ __launch_bounds__(kTmplWave) void k_tmpl_eval(TmplEvalArgs a) {
+    const int p = blockIdx.x * kTmplWave + threadIdx.x;
+    const int sl = blockIdx.y;
+    const bool ok = p < a.n_pts;
+    const int pc = ok ? p : a.n_pts - 1;
+    double th[kNTheta], c[kNBasis];
+    for (int i = 0; i < kNTheta; ++i) th[i] = a.theta[(size_t)pc * kNTheta + i];
+    basis_coef(th, a.ph, c);
+    const double fb = th[6];
+    const int j0 = sl * a.cols_per;
+    const int j1 = min(j0 + a.cols_per, a.n_reco);
+    double dsum = 0.0;
+    double h[kTmplCols];
+#pragma unroll
+    for (int b = 0; b < kTmplCols; ++b) h[b] = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const double* __restrict__ r = a.rec + (size_t)j * kTmplRec;
+        double mu = fma(fb, r[kTmplCols], r[kNBasis]);
+#pragma unroll
+        for (int b = 0; b < kNBasis; ++b) mu = fma(c[b], r[b], mu);
+        const double nj = r[kTmplCols + 1];
+        double d;
+        if (nj > 0.0)
+            d = mu > 0.0 ? (mu - nj) + nj * (r[kTmplCols + 2] - ln_pos(mu)) : INFINITY;
+        else
+            d = mu;
+        dsum += d;
+        if (MU && ok) a.mu[(size_t)p * a.n_reco + j] = mu;
+        if (GRAD) {
+            const double aj = 2.0 * (1.0 - nj / mu);
+#pragma unroll
+            for (int b = 0; b < kNBasis; ++b) h[b] = fma(aj, r[b], h[b]);
+            h[kNBasis] = fma(aj, r[kTmplCols], h[kNBasis]);  // sum_j a_j b_j
+        }
+    }
+    if (!ok) return;
+    a.dpart[(size_t)sl * a.n_pts + p] = dsum;
+    if (GRAD) {
+#pragma unroll
+        for (int b = 0; b < kTmplCols; ++b)
+            a.hpart[((size_t)sl * kTmplCols + b) * a.n_pts + p] = h[b];
+    }
+}
+
+// Sums over the column slices, one (point, quantity) per thread, in slice
+// order (bitwise reproducible).
+__global__ __launch_bounds__(kTmplWave) void k_tmpl_reduce(TmplReduceArgs a) {
+    const int p = blockIdx.x * kTmplWave + threadIdx.x;
+    if (p >= a.n_pts) return;
+    const int v = blockIdx.y;
+    double s = 0.0;
+    if (v == 0) {
+        for (int q = 0; q < a.n_split; ++q) s += a.dpart[(size_t)q * a.n_pts + p];
+    } else {
+        for (int q = 0; q < a.n_split; ++q)
+            s += a.hpart[((size_t)q * kTmplCols + v - 1) * a.n_pts + p];
+    }
+    a.red[(size_t)v * a.n_pts + p] = s;
+}
+
+// -2lnL per point (Eq. (logL)) and, with the contractions, its gradient:
+// d mu_j / d theta_i = sum_b dc_ib G_bj + [i = f_bkg] b_j.
+__global__ __launch_bounds__(256) void k_tmpl_final(TmplFinalArgs a) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.n_pts) return;
+    const double d = a.red[p];
+    double th[kNTheta];
+    for (int i = 0; i < kNTheta; ++i) th[i] = a.theta[(size_t)p * kNTheta + i];
+    double pulls = 0.0;
+    for (int i = 0; i < kNTheta; ++i)
+        if (a.pull_sigma[i] > 0.0) {
+            const double z = (th[i] - a.pull_mean[i]) / a.pull_sigma[i];
+            pulls += z * z;
+        }
+    a.nll[p] = 2.0 * d + 2.0 * a.cdata + pulls;
+    if (!a.grad) return;
+    double h[kTmplCols];
+    for (int b = 0; b < kTmplCols; ++b) h[b] = a.red[(size_t)(1 + b) * a.n_pts + p];
+    double dc[kNTheta][kNBasis];
+    basis_dcoef(th, a.ph, dc);
+    for (int i = 0; i < kNTheta; ++i) {
+        double g = 0.0;
+        for (int b = 0; b < kNBasis; ++b) g += dc[i][b] * h[b];
+        if (i == 6) g += h[kNBasis];
+        if (a.pull_sigma[i] > 0.0)
+            g += 2.0 * (th[i] - a.pull_mean[i]) / (a.pull_sigma[i] * a.pull_sigma[i]);
+        a.grad[(size_t)p * kNTheta + i] = g;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_tmpl_fold(const TmplFoldArgs& a, int n_slab, hipStream_t s) {
+    hipLaunchKernelGGL(k_tmpl_fold, dim3((a.n_reco + 255) / 256, n_slab), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tmpl_records(const TmplRecArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_tmpl_records, dim3((a.n_reco + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tmpl_eval(const TmplEvalArgs& a, int n_split, hipStream_t s) {
+    const dim3 grid((a.n_pts + kTmplWave - 1) / kTmplWave, n_split);
+    if (a.hpart && a.mu) return hipErrorInvalidValue;
+    if (a.hpart)
+        hipLaunchKernelGGL((k_tmpl_eval<true, false>), grid, dim3(kTmplWave), 0, s, a);
+    else if (a.mu)
+        hipLaunchKernelGGL((k_tmpl_eval<false, true>), grid, dim3(kTmplWave), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_tmpl_eval<false, false>), grid, dim3(kTmplWave), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tmpl_reduce(const TmplReduceArgs& a, hipStream_t s) {
+    const dim3 grid((a.n_pts + kTmplWave - 1) / kTmplWave, a.hpart ? 1 + kTmplCols : 1);
+    hipLaunchKernelGGL(k_tmpl_reduce, grid, dim3(kTmplWave), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tmpl_final(const TmplFinalArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_tmpl_final, dim3((a.n_pts + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_wgen(const WgenArgs& a, hipStream_t s) {
     dim3 grid((a.ldw + 255) / 256, (a.n_t + kWgenRows - 1) / kWgenRows);

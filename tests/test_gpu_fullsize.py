@@ -112,3 +112,27 @@ def test_batched_mu_paper_scale(cfg1):
         worst = max(worst, r)
         assert r <= 1e-5, (i, r)
     log(f"[gpu] paper scale batched mu: max rel diff {worst:.2e}")
+
+
+def test_templates_paper_scale(cfg1):
+    """The template form at the paper-scale shapes: 4096 points in one
+    call, sampled points and gradients against the oracle."""
+    p, ctx = cfg1
+    o = p["oracle"]
+    th = synth.theta_prior(4096, 3007, f_range=(0.8, 1.2))
+    nll, g = ctx.eval_nll_templates(th, grad=True)
+    worst = 0.0
+    for i in (0, 1, 2047, 4095):
+        v = o.nll(th[i])
+        worst = max(worst, abs(nll[i] - v))
+        assert abs(nll[i] - v) <= 1e-3, (i, nll[i], v)
+    for i in (5, 3000):
+        v, rg = o.nll_grad(th[i])
+        scale = np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())
+        assert np.all(np.abs(g[i] - rg) <= 1e-4 * scale + 1e-6), (i, g[i], rg)
+    mu = ctx.eval_mu_templates(th[:2])
+    for i in range(2):
+        ref = o.mu(th[i])
+        scale = np.maximum(np.abs(ref), 1e-9 * np.abs(ref).max())
+        assert np.max(np.abs(mu[i] - ref) / scale) <= 1e-5
+    log(f"[gpu] paper scale templates: max |d(-2lnL)| {worst:.2e}")

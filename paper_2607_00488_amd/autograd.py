@@ -11,11 +11,26 @@ import torch
 from . import Context, eval_nll_multi_dev
 
 
-def _buffers(context: Context, P: int, dev, batched: bool):
+FORMS = ("batched", "plain", "templates")
+
+
+def _form(form) -> str:
+    """True / False select the batched / plain form (the older boolean
+    switch); the names of FORMS select themselves."""
+    if form is True:
+        return "batched"
+    if form is False:
+        return "plain"
+    if form not in FORMS:
+        raise ValueError(f"form must be one of {FORMS}, got {form!r}")
+    return form
+
+
+def _buffers(context: Context, P: int, dev, form: str):
     """Fixed input/output buffers per (context, P, form): the library then
     replays one cached graph for every call of a fit."""
     cache = context.__dict__.setdefault("_autograd_bufs", {})
-    key = (P, str(dev), batched)
+    key = (P, str(dev), form)
     b = cache.get(key)
     if b is None:
         b = (torch.empty(P, 7, dtype=torch.float64, device=dev),
@@ -27,18 +42,21 @@ def _buffers(context: Context, P: int, dev, batched: bool):
 
 class NllFunction(torch.autograd.Function):
     """nll[p] = -2lnL(theta[p]) for theta [P, 7] float64 on the context's
-    device.  ``batched`` selects the GEMM form (many points at once) instead
-    of P single-point evaluations."""
+    device.  ``form``: "batched" (the GEMM form, many points at once; also
+    True), "plain" (P single-point evaluations; also False) or "templates"
+    (the folded-template form)."""
 
     @staticmethod
-    def forward(fctx, theta: torch.Tensor, context: Context,
-                batched: bool = True):
+    def forward(fctx, theta: torch.Tensor, context: Context, form="batched"):
+        form = _form(form)
         P = theta.shape[0]
-        th, nll, grad = _buffers(context, P, theta.device, batched)
+        th, nll, grad = _buffers(context, P, theta.device, form)
         th.copy_(theta.detach())
         stream = torch.cuda.current_stream(th.device)
-        if batched:
+        if form == "batched":
             eval_nll_multi_dev([context], [th], [nll], [grad], stream=stream)
+        elif form == "templates":
+            context.eval_nll_templates_dev(th, nll, grad, stream=stream)
         else:
             context.eval_nll_dev(th, nll, grad, stream=stream)
         out, g = nll.clone(), grad.clone()
@@ -51,23 +69,24 @@ class NllFunction(torch.autograd.Function):
         return g[:, None].to(grad.dtype) * grad, None, None
 
 
-def nll(theta: torch.Tensor, context: Context, batched: bool = True):
-    return NllFunction.apply(theta, context, batched)
+def nll(theta: torch.Tensor, context: Context, form="batched"):
+    return NllFunction.apply(theta, context, form)
 
 
 def lbfgs_fit(context: Context, theta0: torch.Tensor, iters: int = 100,
-              history: int = 10, gtol: float = 1e-5, batched: bool = True,
+              history: int = 10, gtol: float = 1e-5, form="batched",
               free=None):
     """Independent L-BFGS minimisations of -2lnL from every row of theta0
     ([S, 7]), advanced together: one batched likelihood+gradient call per
     line-search trial for all starts.  Two-loop recursion per start and a
     backtracking Armijo line search per start.  ``free``: the indices of the
     parameters that move (default all seven); the others keep the values
-    theta0 gives them.
+    theta0 gives them.  ``form``: as for ``nll``.
 
     Returns (theta_min [S, 7], nll_min [S], grad_norm [S], n_calls); the
     gradient norm is over the free parameters.
     """
+    form = _form(form)
     x = theta0.detach().to(torch.float64).clone()
     S, D = x.shape
     dev = x.device
@@ -78,7 +97,7 @@ def lbfgs_fit(context: Context, theta0: torch.Tensor, iters: int = 100,
 
     def fg(th):
         t = th.detach().clone().requires_grad_(True)
-        v = nll(t, context, batched)
+        v = nll(t, context, form)
         v.sum().backward()
         return v.detach(), t.grad.detach() * mask
 

@@ -20,10 +20,12 @@ CHI2_1DOF_90 = 2.705543454095404
 
 def profile_scan(context: Context, index: int, values, base,
                  free=(5, 6), iters: int = 200, gtol: float = 1e-6,
-                 lower=None):
+                 lower=None, form="batched"):
     """-2lnL profiled over the parameters ``free`` at every value of
     parameter ``index`` (the others stay at ``base``).  ``lower`` optionally
     clamps the grid from below (a physical boundary such as m2 >= 0).
+    ``form``: the likelihood form the fits call ("batched", "plain",
+    "templates").
 
     Returns a dict with the grid, the profiled -2lnL, Delta(-2lnL) from the
     grid minimum, the fitted nuisances and the gradient norms."""
@@ -34,7 +36,7 @@ def profile_scan(context: Context, index: int, values, base,
     th0[:, index] = values
     dev = torch.device(f"cuda:{context.device}")
     x, f, gn, calls = lbfgs_fit(context, torch.tensor(th0, device=dev),
-                                iters=iters, gtol=gtol, free=free)
+                                iters=iters, gtol=gtol, free=free, form=form)
     f = f.cpu().numpy()
     d = f - f.min()
     return dict(values=values, nll=f, delta=d, theta=x.cpu().numpy(),

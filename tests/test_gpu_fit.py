@@ -48,8 +48,8 @@ def test_autograd_wiring(asimov):
     dev = torch.device("cuda:0")
     th = torch.tensor(synth.theta_prior(5, 77, f_range=(0.9, 1.1)),
                       dtype=torch.float64, device=dev, requires_grad=True)
-    for batched in (True, False):
-        v = nll(th, ctx, batched)
+    for form in (True, False, "templates"):
+        v = nll(th, ctx, form)
         w = torch.arange(1, 6, dtype=torch.float64, device=dev)
         (v * w).sum().backward()
         g = th.grad.cpu().numpy()
@@ -60,7 +60,8 @@ def test_autograd_wiring(asimov):
         th.grad = None
 
 
-def test_lbfgs_from_64_starts(asimov):
+@pytest.mark.parametrize("form", ["batched", "templates"])
+def test_lbfgs_from_64_starts(asimov, form):
     import torch
     from paper_2607_00488_amd.autograd import lbfgs_fit
     q, o, ctx, th_inj = asimov
@@ -68,10 +69,10 @@ def test_lbfgs_from_64_starts(asimov):
     starts = np.vstack([synth.theta_prior(1, 5000 + s, f_range=(0.8, 1.2))
                         for s in range(64)])
     x, f, gn, calls = lbfgs_fit(ctx, torch.tensor(starts, device=dev),
-                                iters=200, gtol=1e-4)
+                                iters=200, gtol=1e-4, form=form)
     x, f, gn = x.cpu().numpy(), f.cpu().numpy(), gn.cpu().numpy()
     best = int(np.argmin(f))
-    log(f"[gpu] L-BFGS: {calls} batched calls, best -2lnL {f[best]:.6f}, "
+    log(f"[gpu] L-BFGS ({form}): {calls} calls, best -2lnL {f[best]:.6f}, "
         f"median |grad| {np.median(gn):.2e}, converged(|g|<1e-2) "
         f"{np.mean(gn < 1e-2):.2f}")
     # the Asimov minimum is the injected point: -2lnL there is the floor

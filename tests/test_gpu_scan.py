@@ -48,21 +48,22 @@ def oracle_profile(o, th):
     return r.fun
 
 
+@pytest.mark.parametrize("form", ["batched", "templates"])
 @pytest.mark.parametrize("index,inj,grid", [
     (0, 0.05, np.linspace(-0.1, 0.2, 31)),     # eps_ee^L
     (4, 9.0, np.linspace(0.0, 25.0, 26)),      # m2 = (mu_nu / 1e-11 mu_B)^2
 ])
-def test_injection_recovery(index, inj, grid):
+def test_injection_recovery(index, inj, grid, form):
     from paper_2607_00488_amd.scan import interval, profile_scan
     th_inj = synth.theta_sm().copy()
     th_inj[index] = inj
     o, ctx = asimov(th_inj)
     base = synth.theta_sm()
     sc = profile_scan(ctx, index, grid, base, free=(5, 6),
-                      lower=0.0 if index == 4 else None)
+                      lower=0.0 if index == 4 else None, form=form)
     lo, hi = interval(sc["values"], sc["delta"])
     k = int(np.argmin(sc["delta"]))
-    log(f"[gpu] scan of theta[{index}]: {len(grid)} values, {sc['calls']} "
+    log(f"[gpu] {form} scan of theta[{index}]: {len(grid)} values, {sc['calls']} "
         f"batched calls, minimum at {sc['values'][k]:.4g}, 90% CL "
         f"[{lo:.4g}, {hi:.4g}], max |grad| {sc['grad_norm'].max():.2e}")
     # the grid value at the injected point is the minimum, and it reaches

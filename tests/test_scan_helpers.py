@@ -19,3 +19,12 @@ def test_scan_interval_helper():
     assert lo == pytest.approx(v[v > 0.0][0])
     from scipy import stats
     assert CHI2_1DOF_90 == pytest.approx(stats.chi2.ppf(0.9, 1), rel=1e-12)
+
+
+def test_form_names():
+    from paper_2607_00488_amd.autograd import FORMS, _form
+    assert _form(True) == "batched" and _form(False) == "plain"
+    for f in FORMS:
+        assert _form(f) == f
+    with pytest.raises(ValueError):
+        _form("surrogate")

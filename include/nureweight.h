@@ -324,11 +324,13 @@ int nr_eval_mu_batched_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
  * costs 21 products and one logarithm per reco bin.  Same results as the
  * plain and batched forms up to rounding order.
  *
- * nr_build_templates folds them now (synchronous; allocates).  Any set_*
- * call invalidates them, and the first evaluation after it folds them
- * again (synchronising and allocating, so call nr_build_templates first
- * when the evaluation is to be captured in a graph).  A multi-component
- * context returns NR_ESTATE. */
+ * nr_build_templates folds them now (synchronous; allocates).
+ * nr_set_sources, nr_set_response and nr_set_components invalidate them,
+ * and the first evaluation after such a call folds them again
+ * (synchronising and allocating); nr_set_data only has the data slots
+ * beside them rewritten (one small kernel, synchronising).  Call
+ * nr_build_templates first when the evaluation is to be captured in a
+ * graph.  A multi-component context returns NR_ESTATE. */
 int nr_build_templates(nr_ctx *ctx);
 
 /* -2lnL ([n_pts], host) and, when grad is not NULL, its gradient

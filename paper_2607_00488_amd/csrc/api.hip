@@ -188,7 +188,7 @@ struct nr_ctx {
     unsigned* d_gctr = nullptr;  // [4] tile counters (forward, adjoint)
     std::map<std::vector<const void*>, BatchPlan*> plans;
     // template form: folded basis templates and the data, per reco bin
-    bool tmpl_ok = false;
+    bool tmpl_ok = false, tmpl_data_ok = false;
     double* d_trec = nullptr;  // [n_reco][kTmplRec]
     double *d_tdp = nullptr, *d_thp = nullptr;  // evaluation partials
     double* d_tred = nullptr;                   // [1 + kTmplCols][points] slice sums
@@ -1277,7 +1277,7 @@ int nr_set_data(nr_ctx* c, const double* n, const double* b, int n_reco,
     }
     c->n_reco = n_reco;
     c->have_data = true;
-    c->tmpl_ok = false;
+    c->tmpl_data_ok = false;  // the templates themselves stay valid
     clear_graphs(c);
     return 0;
 }
@@ -2091,42 +2091,55 @@ int nr_eval_mu_batched_dev(nr_ctx* c, const double* d_theta, int n_pts,
 // Row factors F_bl = m_l I_b(T_l) / S_SM(T_l) (and m_l alone for the rows
 // with S_SM = 0, whose weight is 1) in FP64 on the host, one streaming pass
 // over R on the device, then the data of each bin beside its templates.
+// New data alone rewrite only the data slots.
 static int build_templates(nr_ctx* c) {
     const int n_t = c->n_t, n_reco = c->n_reco;
     constexpr int NC = nr::kTmplCols;
-    std::vector<double> F((size_t)n_t * NC, 0.0);
-    for (int l = 0; l < n_t; ++l) {
-        const double ssm = c->ssm[l], m = c->mrow[l];
-        if (ssm > 0.0) {
-            for (int b = 0; b < nr::kNBasis; ++b)
-                F[(size_t)l * NC + b] = m * c->basis[(size_t)b * n_t + l] / ssm;
-        } else {
-            F[(size_t)l * NC + nr::kNBasis] = m;
-        }
-    }
-    const int n_slab = (n_t + nr::kTmplSlabRows - 1) / nr::kTmplSlabRows;
-    double *d_F = nullptr, *d_part = nullptr;
     int rc;
-    if ((rc = dalloc(&d_F, F.size())) || (rc = dalloc(&d_part, (size_t)n_slab * NC * n_reco)) ||
-        (rc = dalloc(&c->d_trec, (size_t)n_reco * nr::kTmplRec))) {
+    hipError_t e = hipSuccess;
+    if (!c->tmpl_ok) {
+        std::vector<double> F((size_t)n_t * NC, 0.0);
+        for (int l = 0; l < n_t; ++l) {
+            const double ssm = c->ssm[l], m = c->mrow[l];
+            if (ssm > 0.0) {
+                for (int b = 0; b < nr::kNBasis; ++b)
+                    F[(size_t)l * NC + b] = m * c->basis[(size_t)b * n_t + l] / ssm;
+            } else {
+                F[(size_t)l * NC + nr::kNBasis] = m;
+            }
+        }
+        const int n_slab = (n_t + nr::kTmplSlabRows - 1) / nr::kTmplSlabRows;
+        double *d_F = nullptr, *d_part = nullptr;
+        c->tmpl_data_ok = false;
+        if ((rc = dalloc(&d_F, F.size())) ||
+            (rc = dalloc(&d_part, (size_t)n_slab * NC * n_reco)) ||
+            (rc = dalloc(&c->d_trec, (size_t)n_reco * nr::kTmplRec))) {
+            dfree(&d_F);
+            dfree(&d_part);
+            return rc;
+        }
+        e = hipMemcpy(d_F, F.data(), sizeof(double) * F.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            nr::TmplFoldArgs fa{c->d_R, c->ldr, n_t, n_reco, d_F, d_part};
+            e = nr::launch_tmpl_fold(fa, n_slab, c->stream);
+        }
+        if (e == hipSuccess) {
+            nr::TmplRecArgs ra{d_part, n_slab, n_reco, c->d_trec};
+            e = nr::launch_tmpl_records(ra, c->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         dfree(&d_F);
         dfree(&d_part);
-        return rc;
+        if (e != hipSuccess) return fail(NR_EHIP, "template fold: %s", hipGetErrorString(e));
+        c->tmpl_ok = true;
     }
-    hipError_t e = hipMemcpy(d_F, F.data(), sizeof(double) * F.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess) {
-        nr::TmplFoldArgs fa{c->d_R, c->ldr, n_t, n_reco, d_F, d_part};
-        e = nr::launch_tmpl_fold(fa, n_slab, c->stream);
+    if (!c->tmpl_data_ok) {
+        nr::TmplDataArgs da{c->d_n, c->d_b, n_reco, c->d_trec};
+        e = nr::launch_tmpl_data(da, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(NR_EHIP, "template data: %s", hipGetErrorString(e));
+        c->tmpl_data_ok = true;
     }
-    if (e == hipSuccess) {
-        nr::TmplRecArgs ra{d_part, n_slab, n_reco, c->d_n, c->d_b, c->d_trec};
-        e = nr::launch_tmpl_records(ra, c->stream);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    dfree(&d_F);
-    dfree(&d_part);
-    if (e != hipSuccess) return fail(NR_EHIP, "template fold: %s", hipGetErrorString(e));
-    c->tmpl_ok = true;
     return 0;
 }
 
@@ -2146,7 +2159,7 @@ static int tmpl_split(const nr_ctx* c, int n_pts, bool grad, int* cols_per) {
 
 static int ensure_tmpl(nr_ctx* c, int n_pts, bool grad) {
     int rc;
-    if (!c->tmpl_ok && (rc = build_templates(c))) return rc;
+    if ((!c->tmpl_ok || !c->tmpl_data_ok) && (rc = build_templates(c))) return rc;
     int cp;
     const size_t ns = (size_t)tmpl_split(c, n_pts, grad, &cp);
     if (ns * n_pts > c->t_cap_d) {

@@ -91,8 +91,13 @@ struct TmplFoldArgs {
 struct TmplRecArgs {
     const double* part;
     int n_slab, n_reco;
+    double* rec;       // [n_reco][kTmplRec]
+};
+
+struct TmplDataArgs {
     const double* n;   // [n_reco] data
     const double* b;   // [n_reco] background
+    int n_reco;
     double* rec;       // [n_reco][kTmplRec]
 };
 
@@ -128,6 +133,7 @@ struct TmplFinalArgs {
 
 hipError_t launch_tmpl_fold(const TmplFoldArgs& a, int n_slab, hipStream_t s);
 hipError_t launch_tmpl_records(const TmplRecArgs& a, hipStream_t s);
+hipError_t launch_tmpl_data(const TmplDataArgs& a, hipStream_t s);
 hipError_t launch_tmpl_eval(const TmplEvalArgs& a, int n_split, hipStream_t s);
 hipError_t launch_tmpl_reduce(const TmplReduceArgs& a, hipStream_t s);
 hipError_t launch_tmpl_final(const TmplFinalArgs& a, hipStream_t s);

@@ -401,16 +401,21 @@ __global__ __launch_bounds__(256) void k_tmpl_fold(TmplFoldArgs a) {
         a.part[((size_t)blockIdx.y * kTmplCols + b) * a.n_reco + j] = acc[b];
 }
 
-// Slab sums in slab order, then the data of the bin beside its templates.
+// Slab sums in slab order, one (bin, template) per thread.
 __global__ __launch_bounds__(256) void k_tmpl_records(TmplRecArgs a) {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= a.n_reco) return;
+    const int b = blockIdx.y;
+    double s = 0.0;
+    for (int q = 0; q < a.n_slab; ++q) s += a.part[((size_t)q * kTmplCols + b) * a.n_reco + j];
+    a.rec[(size_t)j * kTmplRec + b] = s;
+}
+
+// The data of each bin beside its templates (rewritten alone by set_data).
+__global__ __launch_bounds__(256) void k_tmpl_data(TmplDataArgs a) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.n_reco) return;
     double* r = a.rec + (size_t)j * kTmplRec;
-    for (int b = 0; b < kTmplCols; ++b) {
-        double s = 0.0;
-        for (int q = 0; q < a.n_slab; ++q) s += a.part[((size_t)q * kTmplCols + b) * a.n_reco + j];
-        r[b] = s;
-    }
     const double nj = a.n[j];
     r[kTmplCols] = a.b[j];
     r[kTmplCols + 1] = nj;
@@ -522,7 +527,12 @@ hipError_t launch_tmpl_fold(const TmplFoldArgs& a, int n_slab, hipStream_t s) {
 }
 
 hipError_t launch_tmpl_records(const TmplRecArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_tmpl_records, dim3((a.n_reco + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_tmpl_records, dim3((a.n_reco + 255) / 256, kTmplCols), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tmpl_data(const TmplDataArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_tmpl_data, dim3((a.n_reco + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -456,6 +456,12 @@ def main():
                            fold_alone_us=round(fold_ms * 1e3, 2),
                            fold_plus_likelihood_us=round(fold_lik_ms * 1e3, 2)))
     forms = {}
+    # the FP64 matrix-core rate the chip sustains on register operands: the
+    # practical ceiling of the batched GEMM beside the data-sheet 78.6
+    import paper_2607_00488_amd as nr
+    probe = nr.nr_probe_mfma_f64(0, 8192, 250)
+    res["detail"]["fp64_mfma_probe_tflops"] = round(probe, 2)
+    log(f"[bench] FP64 MFMA probe: {probe:.1f} TFLOP/s sustained")
     # gradient form: 1024 points at the same shapes, -2lnL + 7 derivatives
     # per point through the FP64-MFMA forward and adjoint products
     thg = synth.theta_prior(1024, p["seeds"]["theta"] + 5, f_range=(0.8, 1.2))
@@ -464,11 +470,14 @@ def main():
         evals_per_s=round(1024 / dtg, 1), points=1024, ms=round(dtg * 1e3, 3),
         flop=2 * 2.0 * 1024 * c.n_t * c.n_reco,
         tflops=round(2 * 2.0 * 1024 * c.n_t * c.n_reco / dtg / 1e12, 2),
-        peak_tflops=78.6, what="nll + gradient, forward and adjoint GEMMs")
+        peak_tflops=78.6,
+        frac_of_probe=round(2 * 2.0 * 1024 * c.n_t * c.n_reco / dtg / 1e12 / probe, 3),
+        what="nll + gradient, forward and adjoint GEMMs")
     dtb, _, _ = time_batched([ctx], [thg], reps=3, grad=False)
     forms["nll_batched_same_shapes"] = dict(
         evals_per_s=round(1024 / dtb, 1), points=1024, ms=round(dtb * 1e3, 3),
-        tflops=round(2.0 * 1024 * c.n_t * c.n_reco / dtb / 1e12, 2))
+        tflops=round(2.0 * 1024 * c.n_t * c.n_reco / dtb / 1e12, 2),
+        frac_of_probe=round(2.0 * 1024 * c.n_t * c.n_reco / dtb / 1e12 / probe, 3))
     log(f"[bench] grad batched: {1024 / dtg:.0f} evals/s; nll batched "
         f"{1024 / dtb:.0f} evals/s")
     forms["templates"] = tf = templates_form(ctx, p["seeds"]["theta"] + 7)
@@ -484,6 +493,7 @@ def main():
             evals_per_s=round(npts / dt2, 1), points=npts,
             ms=round(dt2 * 1e3, 3), flop=flops,
             tflops=round(flops / dt2 / 1e12, 2), peak_tflops=78.6,
+            frac_of_probe=round(flops / dt2 / 1e12 / probe, 3),
             what="64 datasets, N_T 2048-16384, N_reco 512-4096, one grouped "
                  "persistent FP64-MFMA launch per scan (graph replay)")
         log(f"[bench] batched scan: {npts / dt2:.0f} evals/s, "

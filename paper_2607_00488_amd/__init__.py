@@ -33,7 +33,7 @@ EXPORTS = (
     "nr_mlp_set_output_norm", "nr_mlp_targets_dev", "nr_mlp_train_step_dev",
     "nr_mlp_logmu_dev", "nr_mlp_nll_dev", "nr_eval_mu_batched_dev",
     "nr_build_templates", "nr_eval_nll_templates", "nr_eval_mu_templates",
-    "nr_eval_nll_templates_dev",
+    "nr_eval_nll_templates_dev", "nr_probe_mfma_f64",
 )
 
 
@@ -141,6 +141,7 @@ def load():
     L.nr_eval_nll_templates.argtypes = [P, pD, I, pD, pD]
     L.nr_eval_mu_templates.argtypes = [P, pD, I, pD]
     L.nr_eval_nll_templates_dev.argtypes = [P, P, I, P, P, P]
+    L.nr_probe_mfma_f64.argtypes = [I, I, I, pD]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("nr_destroy", "nr_stream", "nr_last_error",
@@ -337,6 +338,16 @@ def nr_eval_nll_templates_dev(h, d_theta_ptr, n_pts, d_nll_ptr, d_grad_ptr=None,
                                             C.c_void_p(d_nll_ptr),
                                             C.c_void_p(d_grad_ptr or 0),
                                             C.c_void_p(stream_ptr or 0)))
+
+
+def nr_probe_mfma_f64(device=0, blocks=8192, iters=2000):
+    """Sustained FP64 matrix-core TFLOP/s of the device (register-only
+    stream of independent MFMA instructions)."""
+    out = np.zeros(1)
+    rc = load().nr_probe_mfma_f64(int(device), int(blocks), int(iters), _dp(out))
+    if rc != 0:
+        raise NrError(rc, "nr_probe_mfma_f64 failed")
+    return float(out[0])
 
 
 def nr_get_reference(h, n_t):

@@ -16,6 +16,30 @@ namespace nr {
 namespace {
 
 
+// The GEMM takes its operand pointers from a problem table in memory, so
+// the compiler cannot tell that they point to global memory and emits flat
+// loads and stores, which also count against the LDS wait counter: every
+// wait for the staged tile would then wait for the next tile's global
+// loads as well.  These views make the accesses global ones.
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T* gmem(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+template <class T>
+__device__ inline __attribute__((address_space(1))) T* gmem(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+typedef double gd2 __attribute__((ext_vector_type(2)));
+typedef float gf4 __attribute__((ext_vector_type(4)));
+__device__ inline double2 ld_global(const double2* p) {
+    const gd2 v = *(const __attribute__((address_space(1))) gd2*)p;
+    return make_double2(v.x, v.y);
+}
+__device__ inline float4 ld_global(const float4* p) {
+    const gf4 v = *(const __attribute__((address_space(1))) gf4*)p;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 __device__ inline double wave_sum64(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -169,7 +193,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
                 const int kk = q / (BM / 2), c2 = q % (BM / 2);
                 const int k = k0 + kk, m = m0 + 2 * c2;
                 ra[i] = (k < K && m < pr.lda)
-                            ? *reinterpret_cast<const double2*>(pr.At + (size_t)k * pr.lda + m)
+                            ? ld_global(reinterpret_cast<const double2*>(pr.At + (size_t)k * pr.lda + m))
                             : make_double2(0.0, 0.0);
             }
 #pragma unroll
@@ -179,13 +203,13 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
                     const int kk = q / (BN / 4), c4 = q % (BN / 4);
                     const int k = k0 + kk, n = n0 + 4 * c4;
                     rb[i] = (k < K && n < pr.ldb)
-                                ? *reinterpret_cast<const float4*>(pr.B + (size_t)k * pr.ldb + n)
+                                ? ld_global(reinterpret_cast<const float4*>(pr.B + (size_t)k * pr.ldb + n))
                                 : make_float4(0.f, 0.f, 0.f, 0.f);
                 } else {  // B[k][n] = R[n][k], K contiguous
                     const int nn = q >> 2, k4 = q & 3;
                     const int n = n0 + nn, k = k0 + 4 * k4;
                     rb[i] = (n < pr.N && k < pr.ldb)
-                                ? *reinterpret_cast<const float4*>(pr.B + (size_t)n * pr.ldb + k)
+                                ? ld_global(reinterpret_cast<const float4*>(pr.B + (size_t)n * pr.ldb + k))
                                 : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
             }
@@ -247,7 +271,7 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
                         const int p = m0 + wm * WTM + bi * 16 + lk + 4 * r;
                         const int col = n0 + wn * WTN + bj * 16 + li;
                         if (p < pr.M && col < pr.N)
-                            pr.C[(size_t)p * pr.ldc + col] = acc[bi][bj][r];
+                            *gmem(pr.C + (size_t)p * pr.ldc + col) = acc[bi][bj][r];
                     }
         } else {
             // one 16-row strip of each wave at a time through LDS; four lanes
@@ -268,23 +292,23 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
                 const int p = m0 + i;
                 double dsum = 0.0, gsum = 0.0;
                 if (p < pr.M) {
-                    const double fb = pr.theta[(size_t)p * kNTheta + 6];
+                    const double fb = *gmem(pr.theta + (size_t)p * kNTheta + 6);
                     for (int q = 0; q < CQ; ++q) {
                         const int col = n0 + wn * WTN + cs * CQ + q;
                         if (col >= pr.N) break;
-                        const double bj_ = pr.b[col];
+                        const double bj_ = *gmem(pr.b + col);
                         const double mu = fb * bj_ + stage[r16 * EPI + cs * CQ + q];
-                        const double nj = pr.n[col];
+                        const double nj = *gmem(pr.n + col);
                         double d;
                         if (nj > 0.0)
                             d = mu > 0.0 ? (mu - nj + nj * log(nj / mu)) : INFINITY;
                         else
                             d = mu;
                         dsum += d;
-                        if (pr.mu) pr.mu[(size_t)p * pr.N + col] = mu;
+                        if (pr.mu) *gmem(pr.mu + (size_t)p * pr.N + col) = mu;
                         if (pr.aout) {
                             const double aj = 2.0 * (1.0 - nj / mu);
-                            pr.aout[(size_t)col * pr.lda_out + p] = aj;
+                            *gmem(pr.aout + (size_t)col * pr.lda_out + p) = aj;
                             gsum += aj * bj_;
                         }
                     }
@@ -302,9 +326,9 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
             if (tid < BM) {
                 const int p = m0 + tid;
                 if (p < pr.M) {
-                    pr.part[(size_t)p * pr.n_nt + tl.nt] = rowred[tid][0] + rowred[tid][1];
+                    *gmem(pr.part + (size_t)p * pr.n_nt + tl.nt) = rowred[tid][0] + rowred[tid][1];
                     if (pr.aout)
-                        pr.part_gb[(size_t)p * pr.n_nt + tl.nt] = rowred2[tid][0] + rowred2[tid][1];
+                        *gmem(pr.part_gb + (size_t)p * pr.n_nt + tl.nt) = rowred2[tid][0] + rowred2[tid][1];
                 }
             }
         }

@@ -44,3 +44,15 @@ def test_binding_has_the_same_names():
     import paper_2607_00488_amd as nr
     for n in declared_functions():
         assert hasattr(nr, n), n
+
+
+def test_probe_rejects_bad_arguments_without_a_device():
+    """Argument checks of the matrix-core probe return before any device
+    call (so they run here without a GPU)."""
+    import numpy as np
+    import paper_2607_00488_amd as nr
+    lib = nr.load()
+    out = np.zeros(1)
+    for blocks, iters in ((0, 1), (1, 0), (1 << 17, 1)):
+        assert lib.nr_probe_mfma_f64(0, blocks, iters, nr._dp(out)) == nr.NR_EINVAL
+    assert lib.nr_probe_mfma_f64(0, 1, 1, None) == nr.NR_EINVAL

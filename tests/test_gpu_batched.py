@@ -175,3 +175,12 @@ def test_autotuner_cache(tmp_path, monkeypatch):
     (key, cfg), = saved.items()
     assert key.startswith("nll|") and cfg in (0, 1, 2, 3)
     ctx.close()
+
+
+def test_mfma_probe_runs():
+    """The matrix-core probe the batched GEMM rate is read against returns
+    a finite, plausible rate (between 1 TFLOP/s and the data-sheet peak)."""
+    import paper_2607_00488_amd as nr
+    r = nr.nr_probe_mfma_f64(0, 1024, 50)
+    log(f"[gpu] FP64 MFMA probe (1024 work-groups, short): {r:.1f} TFLOP/s")
+    assert 1.0 < r < 80.0

@@ -461,7 +461,11 @@ def main():
     import paper_2607_00488_amd as nr
     probe = nr.nr_probe_mfma_f64(0, 8192, 250)
     res["detail"]["fp64_mfma_probe_tflops"] = round(probe, 2)
-    log(f"[bench] FP64 MFMA probe: {probe:.1f} TFLOP/s sustained")
+    # and the HBM read rate of a plain stream (2 GiB, far beyond the caches)
+    rd = nr.nr_probe_hbm_read(0, 2 << 30, 10)
+    res["detail"]["hbm_read_probe_gbs"] = round(rd, 1)
+    res["detail"]["step_frac_of_read_probe"] = round(roof["achieved"] / rd, 4)
+    log(f"[bench] probes: FP64 MFMA {probe:.1f} TFLOP/s, HBM read {rd:.0f} GB/s")
     # gradient form: 1024 points at the same shapes, -2lnL + 7 derivatives
     # per point through the FP64-MFMA forward and adjoint products
     thg = synth.theta_prior(1024, p["seeds"]["theta"] + 5, f_range=(0.8, 1.2))

@@ -358,6 +358,13 @@ int nr_eval_nll_templates_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
  * errors; it does not set the nr_last_error message. */
 int nr_probe_mfma_f64(int device, int blocks, int iters, double *tflops);
 
+/* Diagnostic: the HBM read rate the device sustains, from `reps` streaming
+ * sums (16-byte non-temporal loads) over a zero-filled buffer of `bytes`
+ * (1 MiB .. 64 GiB, a multiple of 16; allocated and freed here).  *gbs
+ * receives GB/s (1e9 B/s); the single-point fold is compared with it.
+ * Status codes as nr_probe_mfma_f64. */
+int nr_probe_hbm_read(int device, long long bytes, int reps, double *gbs);
+
 /* Message for the last non-zero status on this thread. */
 const char *nr_last_error(void);
 

@@ -33,7 +33,7 @@ EXPORTS = (
     "nr_mlp_set_output_norm", "nr_mlp_targets_dev", "nr_mlp_train_step_dev",
     "nr_mlp_logmu_dev", "nr_mlp_nll_dev", "nr_eval_mu_batched_dev",
     "nr_build_templates", "nr_eval_nll_templates", "nr_eval_mu_templates",
-    "nr_eval_nll_templates_dev", "nr_probe_mfma_f64",
+    "nr_eval_nll_templates_dev", "nr_probe_mfma_f64", "nr_probe_hbm_read",
 )
 
 
@@ -142,6 +142,7 @@ def load():
     L.nr_eval_mu_templates.argtypes = [P, pD, I, pD]
     L.nr_eval_nll_templates_dev.argtypes = [P, P, I, P, P, P]
     L.nr_probe_mfma_f64.argtypes = [I, I, I, pD]
+    L.nr_probe_hbm_read.argtypes = [I, C.c_longlong, I, pD]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("nr_destroy", "nr_stream", "nr_last_error",
@@ -347,6 +348,16 @@ def nr_probe_mfma_f64(device=0, blocks=8192, iters=2000):
     rc = load().nr_probe_mfma_f64(int(device), int(blocks), int(iters), _dp(out))
     if rc != 0:
         raise NrError(rc, "nr_probe_mfma_f64 failed")
+    return float(out[0])
+
+
+def nr_probe_hbm_read(device=0, nbytes=2 << 30, reps=10):
+    """Sustained HBM read GB/s of the device (streaming sum over a buffer
+    much larger than the caches)."""
+    out = np.zeros(1)
+    rc = load().nr_probe_hbm_read(int(device), int(nbytes), int(reps), _dp(out))
+    if rc != 0:
+        raise NrError(rc, "nr_probe_hbm_read failed")
     return float(out[0])
 
 

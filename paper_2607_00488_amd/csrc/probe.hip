@@ -1,7 +1,9 @@
-// Diagnostic: the FP64 matrix-core rate this device sustains, measured by a
-// stream of independent v_mfma_f64_16x16x4_f64 on register operands (no
-// memory traffic inside the timed loop).  The batched GEMM's TFLOP/s are
-// read against it beside the data-sheet peak.
+// Diagnostics: what this device sustains, measured rather than taken from
+// the data sheet.  The FP64 matrix-core rate from a stream of independent
+// v_mfma_f64_16x16x4_f64 on register operands (no memory traffic inside the
+// timed loop), which the batched GEMM's TFLOP/s are read against; and the
+// HBM read rate of a plain streaming sum over a buffer much larger than the
+// caches, which the single-point fold's bytes per second are read against.
 #include "../../include/nureweight.h"
 
 #include <hip/hip_runtime.h>
@@ -27,7 +29,74 @@ __global__ __launch_bounds__(256) void k_probe_mfma_f64(double* out, int iters) 
     out[(size_t)blockIdx.x * 256 + threadIdx.x] = s;  // keeps the chains live
 }
 
+// Grid-stride sum of a buffer with 16-byte non-temporal loads, eight in
+// flight per lane, 32 work-groups per compute unit (the fastest of
+// non-temporal / ordinary loads, 4 / 8 in flight and 4..32 work-groups per
+// CU measured on MI355X: 6.3 TB/s over 2 GiB).  The sum decides a store that
+// never happens for the zero-filled buffer, which keeps every load live.
+constexpr int kReadUnroll = 8;
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_probe_read(const f4v* __restrict__ p, size_t n4,
+                                                    float* out) {
+    const size_t stride = (size_t)gridDim.x * 256;
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    float s = 0.0f;
+    for (; i + (kReadUnroll - 1) * stride < n4; i += kReadUnroll * stride) {
+        f4v v[kReadUnroll];
+#pragma unroll
+        for (int q = 0; q < kReadUnroll; ++q) v[q] = __builtin_nontemporal_load(p + i + q * stride);
+#pragma unroll
+        for (int q = 0; q < kReadUnroll; ++q) s += v[q].x + v[q].y + v[q].z + v[q].w;
+    }
+    for (; i < n4; i += stride) {
+        const f4v v = __builtin_nontemporal_load(p + i);
+        s += v.x + v.y + v.z + v.w;
+    }
+    if (s == 1234.5f) out[0] = s;
+}
+
 }  // namespace
+
+extern "C" int nr_probe_hbm_read(int device, long long bytes, int reps, double* gbs) {
+    if (!gbs || bytes < (1 << 20) || bytes > (1LL << 36) || (bytes & 15) || reps <= 0)
+        return NR_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return NR_EHIP;
+    float* d = nullptr;
+    float* o = nullptr;
+    if (hipMalloc((void**)&d, (size_t)bytes) != hipSuccess) return NR_ENOMEM;
+    if (hipMalloc((void**)&o, sizeof(float)) != hipSuccess) {
+        (void)hipFree(d);
+        return NR_ENOMEM;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = NR_EHIP;
+    float ms = 0.0f;
+    const size_t n4 = (size_t)bytes / 16;
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    const int grid = (cus > 0 ? cus : 256) * 32;
+    if (hipMemset(d, 0, (size_t)bytes) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+        hipEventCreate(&e1) == hipSuccess) {
+        hipLaunchKernelGGL(k_probe_read, dim3(grid), dim3(256), 0, nullptr,
+                           reinterpret_cast<const f4v*>(d), n4, o);
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps; ++r)
+            hipLaunchKernelGGL(k_probe_read, dim3(grid), dim3(256), 0, nullptr,
+                               reinterpret_cast<const f4v*>(d), n4, o);
+        (void)hipEventRecord(e1, nullptr);
+        if (hipEventSynchronize(e1) == hipSuccess && hipGetLastError() == hipSuccess &&
+            hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f) {
+            *gbs = (double)bytes * reps / (ms * 1e-3) / 1e9;
+            rc = NR_OK;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(o);
+    (void)hipFree(d);
+    return rc;
+}
 
 extern "C" int nr_probe_mfma_f64(int device, int blocks, int iters, double* tflops) {
     if (!tflops || blocks <= 0 || blocks > (1 << 16) || iters <= 0) return NR_EINVAL;

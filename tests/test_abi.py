@@ -56,3 +56,5 @@ def test_probe_rejects_bad_arguments_without_a_device():
     for blocks, iters in ((0, 1), (1, 0), (1 << 17, 1)):
         assert lib.nr_probe_mfma_f64(0, blocks, iters, nr._dp(out)) == nr.NR_EINVAL
     assert lib.nr_probe_mfma_f64(0, 1, 1, None) == nr.NR_EINVAL
+    for nbytes, reps in ((1 << 19, 1), ((1 << 20) + 8, 1), (1 << 20, 0), (1 << 37, 1)):
+        assert lib.nr_probe_hbm_read(0, nbytes, reps, nr._dp(out)) == nr.NR_EINVAL

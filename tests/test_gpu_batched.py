@@ -184,3 +184,6 @@ def test_mfma_probe_runs():
     r = nr.nr_probe_mfma_f64(0, 1024, 50)
     log(f"[gpu] FP64 MFMA probe (1024 work-groups, short): {r:.1f} TFLOP/s")
     assert 1.0 < r < 80.0
+    g = nr.nr_probe_hbm_read(0, 256 << 20, 4)
+    log(f"[gpu] HBM read probe (256 MiB): {g:.0f} GB/s")
+    assert 100.0 < g < 20000.0

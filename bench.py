@@ -125,6 +125,38 @@ def time_batched(ctxs, ths, reps=3, grad=False):
                                                 [g.cpu().numpy() for g in gr])
 
 
+def plain_config0_form(n_pts=4096, reps=5):
+    """The plain single-point path at the parity configuration (512 recoil x
+    256 reco bins, N_E = 256, 1e6 MC events): the response is 512 KiB and
+    stays in L2, so the chain of step launches is latency-bound.  One graph
+    replay of n_pts evaluations at prior points, timed with events."""
+    import torch
+    import synth
+    p = build_plain(0)
+    ctx = p["ctx"]
+    dev = torch.device("cuda:0")
+    th = torch.tensor(synth.theta_prior(n_pts, p["seeds"]["theta"] + 11),
+                      dtype=torch.float64, device=dev)
+    out = torch.empty(n_pts, dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream(device=dev)
+    ctx.eval_nll_dev(th, out, stream=s)
+    s.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        ctx.eval_nll_dev(th, out, stream=s)
+    e1.record(s)
+    s.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ctx.close()
+    return dict(evals_per_s=round(n_pts / (ms * 1e-3), 1), points=n_pts,
+                us_per_eval=round(ms * 1e3 / n_pts, 3),
+                what="plain single-point path at 512 x 256 (N_E = 256): the "
+                     "512 KiB response stays in L2; one graph replay of "
+                     f"{n_pts} evaluations ({n_pts + 4} step launches)")
+
+
 def templates_form(ctx, seed, n_pts=65536, reps=5):
     """The template form at the paper-scale shapes: the 20 basis templates
     and the S_SM = 0 rows folded once through R (one FP64 pass), then 21
@@ -484,6 +516,9 @@ def main():
         frac_of_probe=round(2.0 * 1024 * c.n_t * c.n_reco / dtb / 1e12 / probe, 3))
     log(f"[bench] grad batched: {1024 / dtg:.0f} evals/s; nll batched "
         f"{1024 / dtb:.0f} evals/s")
+    forms["plain_config0"] = pc = plain_config0_form()
+    log(f"[bench] plain at 512 x 256: {pc['evals_per_s']:.0f} evals/s "
+        f"({pc['us_per_eval']:.2f} us/eval)")
     forms["templates"] = tf = templates_form(ctx, p["seeds"]["theta"] + 7)
     log(f"[bench] templates: {tf['evals_per_s']:.0f} evals/s "
         f"({tf['grad_evals_per_s']:.0f} with gradient), fold "

@@ -328,9 +328,12 @@ int nr_eval_mu_batched_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
  * nr_set_sources, nr_set_response and nr_set_components invalidate them,
  * and the first evaluation after such a call folds them again
  * (synchronising and allocating); nr_set_data only has the data slots
- * beside them rewritten (one small kernel, synchronising).  Call
- * nr_build_templates first when the evaluation is to be captured in a
- * graph.  A multi-component context returns NR_ESTATE. */
+ * beside them rewritten (one small kernel, synchronising).  Partial-sum
+ * buffers grow (allocating) with the point count and the gradient flag.
+ * Before capturing an evaluation in a graph, run it once eagerly with at
+ * least as many points (and the same gradient flag), so that nothing is
+ * folded or allocated inside the capture.  A multi-component context
+ * returns NR_ESTATE. */
 int nr_build_templates(nr_ctx *ctx);
 
 /* -2lnL ([n_pts], host) and, when grad is not NULL, its gradient

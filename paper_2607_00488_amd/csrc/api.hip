@@ -505,11 +505,14 @@ int run_points(nr_ctx* c, const double* th, int n_pts, double* nll,
     auto it = c->graphs.find(key);
     if (it == c->graphs.end()) {
         if (c->graphs.size() >= 16) clear_graphs(c);
-        hipGraph_t g;
+        hipGraph_t g = nullptr;
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         int rc = enqueue_points(c, th, n_pts, nll, grad, mu, w, s);
         hipError_t e = hipStreamEndCapture(s, &g);
-        if (rc) return rc;
+        if (rc) {
+            if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+            return rc;
+        }
         if (e != hipSuccess)
             return fail(NR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
         hipGraphExec_t ex;
@@ -898,17 +901,22 @@ int run_multi(const MultiCall& mc, hipStream_t s) {
         rc = build_plan(mc, grad, cfg, np);
         if (rc) { free_plan(np); owner->plans.erase(key); return rc; }
         if (owner->use_graph) {
-            hipGraph_t g;
-            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            rc = enqueue_plan(mc, grad, np, owner->d_gctr, s);
-            hipError_t e = hipStreamEndCapture(s, &g);
-            if (rc) return rc;
-            if (e != hipSuccess)
-                return fail(NR_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-            e = hipGraphInstantiate(&np->graph, g, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(g);
-            if (e != hipSuccess)
-                return fail(NR_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                rc = enqueue_plan(mc, grad, np, owner->d_gctr, s);
+                e = hipStreamEndCapture(s, &g);
+            }
+            if (!rc && e == hipSuccess) {
+                e = hipGraphInstantiate(&np->graph, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) np->graph = nullptr;
+            }
+            if (g) (void)hipGraphDestroy(g);
+            if (rc || e != hipSuccess) {  // no half-built plan stays cached
+                free_plan(np);
+                owner->plans.erase(key);
+                return rc ? rc : fail(NR_EHIP, "graph capture: %s", hipGetErrorString(e));
+            }
         }
         np->epoch = g_epoch;
         BatchPlan* use = np;

@@ -79,7 +79,8 @@ def lbfgs_fit(context: Context, theta0: torch.Tensor, iters: int = 100,
     """Independent L-BFGS minimisations of -2lnL from every row of theta0
     ([S, 7]), advanced together: one batched likelihood+gradient call per
     line-search trial for all starts.  Two-loop recursion per start and a
-    backtracking Armijo line search per start.  ``free``: the indices of the
+    backtracking Armijo line search per start, whose sufficient-decrease
+    test allows for the FP64 rounding noise of -2lnL (1e-12 |f|).  ``free``: the indices of the
     parameters that move (default all seven); the others keep the values
     theta0 gives them.  ``form``: as for ``nll``.
 
@@ -147,7 +148,12 @@ def lbfgs_fit(context: Context, theta0: torch.Tensor, iters: int = 100,
             trial = x + (step * (~accepted))[:, None] * d
             ft, gt = fg(torch.where(accepted[:, None], x_new, trial))
             calls += 1
-            ok = (ft <= f + 1e-4 * step * slope) & torch.isfinite(ft) & ~accepted
+            # sufficient decrease, up to the rounding noise of -2lnL itself
+            # (about 1e-13 |f| in FP64 over thousands of bins): near a
+            # minimum the decrease the test asks for falls below that
+            # noise, and without the allowance line searches fail by chance
+            ok = ((ft <= f + 1e-4 * step * slope + 1e-12 * f.abs().clamp_min(1.0))
+                  & torch.isfinite(ft) & ~accepted)
             x_new = torch.where(ok[:, None], trial, x_new)
             f_new = torch.where(ok, ft, f_new)
             g_new = torch.where(ok[:, None], gt, g_new)

@@ -77,7 +77,7 @@ struct ContractArgs {
 //   G_bj = sum_{l: S_SM(T_l) > 0} F_bl R_lj,  F_bl = m_l I_b(T_l) / S_SM(T_l),
 //   G0_j = sum_{l: S_SM(T_l) = 0} m_l R_lj   (rows with w := 1).
 constexpr int kTmplCols = kNBasis + 1;     // G_0..G_19, G0
-constexpr int kTmplRec = 24;               // per reco bin: G_0..G_19, G0, b, n, ln n
+constexpr int kTmplRec = 24;               // per reco bin: G_0..G_19, G0, b, n, pad
 constexpr int kTmplSlabRows = 256;         // response rows per template-fold work-group
 constexpr int kTmplWave = 64;              // points per evaluation work-group
 

@@ -443,7 +443,7 @@ __global__ __launch_bounds__(256) void k_tmpl_data(TmplDataArgs a) {
     const double nj = a.n[j];
     r[kTmplCols] = a.b[j];
     r[kTmplCols + 1] = nj;
-    r[kTmplCols + 2] = nj > 0.0 ? ln_pos(nj) : 0.0;
+    r[kTmplCols + 2] = 0.0;  // pads the record to 24 doubles
 }
 
 // One thread per point, one work-group column per slice of reco bins.  The
@@ -451,7 +451,7 @@ __global__ __launch_bounds__(256) void k_tmpl_data(TmplDataArgs a) {
 // mu_j, the deviance term of Eq. (logL) and, for the gradient, the
 // contractions h_b = sum_j a_j G_bj with a_j = 2 (1 - n_j / mu_j).  The
 // logarithm is the plain-FP64 series of lnpos.h (the library one spends
-// ~85 double-double operations per bin for accuracy the sum cannot use).
+// ~85 double-double operations per bin on accuracy the sum cannot use).
 template <bool GRAD, bool MU>
 __global__ __launch_bounds__(kTmplWave) void k_tmpl_eval(TmplEvalArgs a) {
     const int p = blockIdx.x * kTmplWave + threadIdx.x;
@@ -474,15 +474,21 @@ __global__ __launch_bounds__(kTmplWave) void k_tmpl_eval(TmplEvalArgs a) {
 #pragma unroll
         for (int b = 0; b < kNBasis; ++b) mu = fma(c[b], r[b], mu);
         const double nj = r[kTmplCols + 1];
+        // n ln(n / mu), not n (ln n - ln mu): near a fit's minimum the two
+        // logarithms agree to many digits and their separate roundings
+        // would leave ~1e-10 of noise in -2lnL, enough to stall a line
+        // search; the logarithm of the ratio is accurate relative to its
+        // own small size.
+        const double q = nj / mu;
         double d;
         if (nj > 0.0)
-            d = mu > 0.0 ? (mu - nj) + nj * (r[kTmplCols + 2] - ln_pos(mu)) : INFINITY;
+            d = mu > 0.0 ? (mu - nj) + nj * ln_pos(q) : INFINITY;
         else
             d = mu;
         dsum += d;
         if (MU && ok) a.mu[(size_t)p * a.n_reco + j] = mu;
         if (GRAD) {
-            const double aj = 2.0 * (1.0 - nj / mu);
+            const double aj = 2.0 * (1.0 - q);
 #pragma unroll
             for (int b = 0; b < kNBasis; ++b) h[b] = fma(aj, r[b], h[b]);
             h[kNBasis] = fma(aj, r[kTmplCols], h[kNBasis]);  // sum_j a_j b_j

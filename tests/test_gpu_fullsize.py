@@ -136,3 +136,42 @@ def test_templates_paper_scale(cfg1):
         scale = np.maximum(np.abs(ref), 1e-9 * np.abs(ref).max())
         assert np.max(np.abs(mu[i] - ref) / scale) <= 1e-5
     log(f"[gpu] paper scale templates: max |d(-2lnL)| {worst:.2e}")
+
+
+def test_response_beyond_2g_elements():
+    """Maximum sizes: a 65536 x 36864 response (2.4e9 elements, 9.7 GB of
+    FP32, so element offsets pass 2^31), uniform random rows scaled to sum
+    to about 1, sampled points through the plain, template and batched
+    forms against the oracle."""
+    import oracle
+    import paper_2607_00488_amd as nr
+    n_t, n_reco, n_e = 65536, 36864, 64
+    log(f"[gpu] {n_t} x {n_reco} response ({n_t * n_reco * 4 / 1e9:.1f} GB)")
+    R = synth.rng(4242).random((n_t, n_reco), dtype=np.float32)
+    R *= np.float32(2.0 / n_reco)
+    src = synth.source_nodes(n_e)
+    b = np.full(n_reco, 10.0)
+    o = oracle.Oracle()
+    o.set_sources(src, n_t)
+    o.set_response(R, n_sig=1.0e6)
+    o.set_data(np.zeros(n_reco), b)
+    n = synth.poisson_data(o.mu(oracle.THETA_SM) + b, 4243)  # signal only before set_data
+    o.set_data(n, b)
+    ctx = nr.Context(0)
+    ctx.set_sources(src, n_t)
+    ctx.set_response(R, n_sig=1.0e6)
+    del R
+    ctx.set_data(n, b)
+    th = np.vstack([synth.theta_sm()[None], synth.theta_prior(2, 4244, f_range=(0.8, 1.2))])
+    plain = ctx.eval_nll(th)
+    tmpl = ctx.eval_nll_templates(th)
+    bat = ctx.eval_nll_batched(th)
+    worst = 0.0
+    for i in range(len(th)):
+        ref = o.nll(th[i])
+        for got in (plain[i], tmpl[i], bat[i]):
+            worst = max(worst, abs(got - ref))
+            assert abs(got - ref) <= 1e-3, (i, got, ref)
+    log(f"[gpu] beyond 2^31 elements: max |d(-2lnL)| {worst:.2e} over 3 forms x {len(th)} points")
+    ctx.close()
+    o.close()

@@ -359,8 +359,38 @@ def components_form(n_pts=400):
     dt = time.perf_counter() - t1
     step_ms = ev0.elapsed_time(ev1) / n_pts
     alg = 4 * K * 16384 * 4096 + 16 * K * 16384 + 16 * 4096
+    # the template form of the same likelihood: 65 536 points per call
+    t2 = time.perf_counter()
+    ctx.build_templates()
+    t_fold = time.perf_counter() - t2
+    P = 65536
+    tht = np.concatenate([g.uniform(-0.5, 0.5, (P, 4)), g.uniform(0, 25, (P, 1)),
+                          g.uniform(0.8, 1.2, (P, n_theta - 5))], axis=1)
+    ttt = torch.tensor(tht, dtype=torch.float64, device=dev)
+    nl = torch.empty(P, dtype=torch.float64, device=dev)
+    gr = torch.empty(P, n_theta, dtype=torch.float64, device=dev)
+    tms = {}
+    for mode, gg in (("nll", None), ("grad", gr)):
+        ctx.eval_nll_templates_dev(ttt, nl, gg, stream=s)
+        s.synchronize()
+        ev0.record(s)
+        for _ in range(3):
+            ctx.eval_nll_templates_dev(ttt, nl, gg, stream=s)
+        ev1.record(s)
+        s.synchronize()
+        tms[mode] = ev0.elapsed_time(ev1) / 3
+    ctx.eval_nll_templates_dev(tt, out, None, stream=s)   # the streaming path's points
+    s.synchronize()
+    stream_nll = ctx.eval_nll(th[:16])
+    d_vs_stream = float(np.max(np.abs(out.cpu().numpy()[:16] - stream_nll)))
     ctx.close()
     return dict(evals_per_s=round(n_pts / dt, 1), points=n_pts,
+                templates=dict(evals_per_s=round(P / (tms["nll"] * 1e-3), 1),
+                               grad_evals_per_s=round(P / (tms["grad"] * 1e-3), 1),
+                               points=P, ms=round(tms["nll"], 3),
+                               grad_ms=round(tms["grad"], 3),
+                               template_fold_ms=round(t_fold * 1e3, 1),
+                               max_abs_dnll_vs_streaming=d_vs_stream),
                 us_per_eval=round(dt / n_pts * 1e6, 2), components=K,
                 backgrounds=2, n_theta=n_theta, algorithmic_bytes=alg,
                 step_kernel_us=round(step_ms * 1e3, 2),
@@ -596,7 +626,10 @@ def main():
     if not args.no_components:
         forms["multi_component"] = mc = components_form()
         log(f"[bench] multi-component: {mc['evals_per_s']:.0f} evals/s, "
-            f"{mc['achieved_gbs']:.0f} GB/s ({mc['frac_hbm']:.3f} of peak)")
+            f"{mc['achieved_gbs']:.0f} GB/s ({mc['frac_hbm']:.3f} of peak); "
+            f"templates {mc['templates']['evals_per_s']:.0f} evals/s "
+            f"({mc['templates']['grad_evals_per_s']:.0f} with gradient), "
+            f"max |d| vs streaming {mc['templates']['max_abs_dnll_vs_streaming']:.1e}")
     res["forms"] = forms
     if not args.no_cpu_baseline:
         cb, dmax = cpu_baseline(p, args.cpu_evals, ctx)

@@ -312,7 +312,7 @@ int nr_mlp_nll_dev(nr_mlp *mlp, nr_ctx *ctx, const double *d_theta, int B,
 int nr_eval_mu_batched_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
                            double *d_mu, void *stream);
 
-/* Template form (single-component contexts).  The cross section of
+/* Template form.  The cross section of
  * Eqs. (xs_nsi) and (xs_mm) is linear in the coupling products, m2 and
  * f_8B, so S_theta of Eq. (fT) is sum_b c_b(theta) I_b over 20
  * theta-independent basis spectra, and the fold of Eq. (matrix_reweight)
@@ -324,6 +324,14 @@ int nr_eval_mu_batched_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
  * costs 21 products and one logarithm per reco bin.  Same results as the
  * plain and batched forms up to rounding order.
  *
+ * On a multi-component context (nr_set_components) each component's
+ * sources give 10 basis spectra and its row block is folded with its own
+ * SM spectrum, so per bin
+ *   mu_j = M_j [sum_k r_k (G0^(k)_j + sum_b c_b G^(k)_bj) + sum_q r_q B_qj]
+ * (Eqs. (Rij), (fNp_reweight), (mu_total)), and the gradient covers every
+ * parameter of that layout, which the streaming path does not provide.
+ * Up to 8 components and 8 background templates (NR_EINVAL beyond).
+ *
  * nr_build_templates folds them now (synchronous; allocates).
  * nr_set_sources, nr_set_response and nr_set_components invalidate them,
  * and the first evaluation after such a call folds them again
@@ -332,12 +340,12 @@ int nr_eval_mu_batched_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
  * buffers grow (allocating) with the point count and the gradient flag.
  * Before capturing an evaluation in a graph, run it once eagerly with at
  * least as many points (and the same gradient flag), so that nothing is
- * folded or allocated inside the capture.  A multi-component context
- * returns NR_ESTATE. */
+ * folded or allocated inside the capture. */
 int nr_build_templates(nr_ctx *ctx);
 
 /* -2lnL ([n_pts], host) and, when grad is not NULL, its gradient
- * ([n_pts][7], host) by the template form.  Synchronous. */
+ * ([n_pts][n_theta], host; n_theta = nr_num_theta) by the template form;
+ * theta is [n_pts][n_theta].  Synchronous. */
 int nr_eval_nll_templates(nr_ctx *ctx, const double *theta, int n_pts,
                           double *nll, double *grad);
 
@@ -345,8 +353,8 @@ int nr_eval_nll_templates(nr_ctx *ctx, const double *theta, int n_pts,
 int nr_eval_mu_templates(nr_ctx *ctx, const double *theta, int n_pts,
                          double *mu);
 
-/* Device-pointer variant: d_theta [n_pts][7], d_nll [n_pts], d_grad
- * [n_pts][7] or NULL, all FP64 on the context's device; enqueued on
+/* Device-pointer variant: d_theta [n_pts][n_theta], d_nll [n_pts], d_grad
+ * [n_pts][n_theta] or NULL, all FP64 on the context's device; enqueued on
  * `stream` (NULL = the default stream), returns without waiting.  Calls
  * that overlap on one context share its partial-sum buffers and race. */
 int nr_eval_nll_templates_dev(nr_ctx *ctx, const double *d_theta, int n_pts,

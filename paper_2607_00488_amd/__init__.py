@@ -318,16 +318,17 @@ def nr_build_templates(h):
 
 
 def nr_eval_nll_templates(h, theta, grad=False):
-    th = _f64(theta, (-1, NR_NTHETA))
+    nt = nr_num_theta(h)
+    th = _f64(theta, (-1, nt))
     out = np.empty(th.shape[0])
-    g = np.empty((th.shape[0], NR_NTHETA)) if grad else None
+    g = np.empty((th.shape[0], nt)) if grad else None
     _check(load().nr_eval_nll_templates(h, _dp(th), th.shape[0], _dp(out),
                                         _dp(g) if grad else None))
     return (out, g) if grad else out
 
 
 def nr_eval_mu_templates(h, theta, n_reco):
-    th = _f64(theta, (-1, NR_NTHETA))
+    th = _f64(theta, (-1, nr_num_theta(h)))
     out = np.empty((th.shape[0], n_reco))
     _check(load().nr_eval_mu_templates(h, _dp(th), th.shape[0], _dp(out)))
     return out
@@ -602,7 +603,7 @@ class Context:
         if theta_t.dim() != 2 or theta_t.shape[1] != self.n_theta:
             raise ValueError(f"theta must be [P, {self.n_theta}]")
         if nll_t.numel() < theta_t.shape[0] or (
-                grad_t is not None and grad_t.numel() < 7 * theta_t.shape[0]):
+                grad_t is not None and grad_t.numel() < self.n_theta * theta_t.shape[0]):
             raise ValueError("output tensors are too small")
         if grad_t is not None:
             assert grad_t.dtype == nll_t.dtype and grad_t.is_contiguous()

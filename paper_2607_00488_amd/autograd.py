@@ -33,16 +33,18 @@ def _buffers(context: Context, P: int, dev, form: str):
     key = (P, str(dev), form)
     b = cache.get(key)
     if b is None:
-        b = (torch.empty(P, 7, dtype=torch.float64, device=dev),
+        D = context.n_theta
+        b = (torch.empty(P, D, dtype=torch.float64, device=dev),
              torch.empty(P, dtype=torch.float64, device=dev),
-             torch.empty(P, 7, dtype=torch.float64, device=dev))
+             torch.empty(P, D, dtype=torch.float64, device=dev))
         cache[key] = b
     return b
 
 
 class NllFunction(torch.autograd.Function):
-    """nll[p] = -2lnL(theta[p]) for theta [P, 7] float64 on the context's
-    device.  ``form``: "batched" (the GEMM form, many points at once; also
+    """nll[p] = -2lnL(theta[p]) for theta [P, n_theta] float64 on the
+    context's device (n_theta = 7, or 5 + K + B for a multi-component
+    context, which only the template form takes).  ``form``: "batched" (the GEMM form, many points at once; also
     True), "plain" (P single-point evaluations; also False) or "templates"
     (the folded-template form)."""
 

@@ -249,6 +249,30 @@ inline bool reach(double me, double E, double T) {
     return T <= 2.0 * E * E / (me + 2.0 * E);
 }
 
+// The ten theta-independent pieces of source k's recoil spectrum at bin l:
+// per flavour the sums of nu P_a, nu P_a y^2 and nu P_a x over the reachable
+// nodes (the coefficients of g_L^2, g_R^2 and -g_L g_R in Eq.
+// (sm_cross_section)), and nu (1/T - 1/E) for the magnetic term (Eq.
+// (xs_mm)); S_theta(T_l) is sum_b c_b(theta) times these.
+void source_basis(const nr_ctx* c, int k, int l, double acc[10]) {
+    const int n_t = c->n_t;
+    const double T = c->tc[l];
+    const int hi = c->src_off[k] + c->src_n[k];
+    for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+    for (int j = c->jmin[(size_t)k * n_t + l]; j < hi; ++j) {
+        const double E = c->hE[j], nu = c->hW[j], pe = c->hPe[j];
+        const double P[3] = {pe, (1 - pe) * (1 - c->ph.tau_frac),
+                             (1 - pe) * c->ph.tau_frac};
+        const double y = 1.0 - T / E, x = c->ph.me * T / (E * E);
+        for (int a = 0; a < 3; ++a) {
+            acc[3 * a + 0] += nu * P[a];
+            acc[3 * a + 1] += nu * P[a] * y * y;
+            acc[3 * a + 2] += nu * P[a] * x;
+        }
+        acc[9] += nu * (P[0] + P[1] + P[2]) * (1.0 / T - 1.0 / E);
+    }
+}
+
 void recompute_mrow(nr_ctx* c) {
     if (c->m_user || !c->have_src || c->multi) return;
     double tot = 0;
@@ -299,7 +323,7 @@ int ensure_stage(nr_ctx* c, size_t pts, size_t mu_elems, size_t w_elems) {
         size_t n = std::max(pts, (size_t)64);
         if ((rc = dalloc(&c->d_th, n * nr::kMaxTheta))) return rc;  // any form's theta
         if ((rc = dalloc(&c->d_out, n))) return rc;
-        if ((rc = dalloc(&c->d_grad, n * NR_NTHETA))) return rc;
+        if ((rc = dalloc(&c->d_grad, n * nr::kMaxTheta))) return rc;  // any form's gradient
         c->cap_pts = n;
         clear_graphs(c);
     }
@@ -1123,28 +1147,14 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
     c->n_blocks = (n_t + nr::kStepRows - 1) / nr::kStepRows;
     // theta-independent basis spectra (FP64), used by the adjoint
     c->basis.assign((size_t)nr::kNBasis * n_t, 0.0);
-    for (int l = 0; l < n_t; ++l) {
-        const double T = c->tc[l];
+    for (int l = 0; l < n_t; ++l)
         for (int k = 0; k < n_src; ++k) {
+            double acc[10];
+            source_basis(c, k, l, acc);
             const int g = c->src_group[k] ? 10 : 0;
-            const int hi = c->src_off[k] + c->src_n[k];
-            double acc[10] = {0};
-            for (int j = c->jmin[(size_t)k * n_t + l]; j < hi; ++j) {
-                const double E = c->hE[j], nu = c->hW[j], pe = c->hPe[j];
-                const double P[3] = {pe, (1 - pe) * (1 - c->ph.tau_frac),
-                                     (1 - pe) * c->ph.tau_frac};
-                const double y = 1.0 - T / E, x = c->ph.me * T / (E * E);
-                for (int a = 0; a < 3; ++a) {
-                    acc[3 * a + 0] += nu * P[a];
-                    acc[3 * a + 1] += nu * P[a] * y * y;
-                    acc[3 * a + 2] += nu * P[a] * x;
-                }
-                acc[9] += nu * (P[0] + P[1] + P[2]) * (1.0 / T - 1.0 / E);
-            }
             for (int q = 0; q < 10; ++q)
                 c->basis[(size_t)(g + q) * n_t + l] += acc[q];
         }
-    }
     // upload
     if ((rc = dalloc(&c->d_E, c->n_nodes)) || (rc = dalloc(&c->d_W, c->n_nodes)) ||
         (rc = dalloc(&c->d_Pe, c->n_nodes)) || (rc = dalloc(&c->d_tc, n_t)) ||
@@ -2099,51 +2109,113 @@ int nr_eval_mu_batched_dev(nr_ctx* c, const double* d_theta, int n_pts,
 // Row factors F_bl = m_l I_b(T_l) / S_SM(T_l) (and m_l alone for the rows
 // with S_SM = 0, whose weight is 1) in FP64 on the host, one streaming pass
 // over R on the device, then the data of each bin beside its templates.
-// New data alone rewrite only the data slots.
+// New data alone rewrite only the data slots.  In the multi-component form
+// each component's row block is folded with that component's basis and
+// SM spectrum.
+
+// Record length and gradient contractions per point of the context's form.
+static int tmpl_rl(const nr_ctx* c) {
+    return c->multi ? (nr::kTmplCompCols * c->n_comp + c->n_bkg + 2 + 1) / 2 * 2
+                    : nr::kTmplRec;
+}
+static int tmpl_nacc(const nr_ctx* c) {
+    return c->multi ? 10 + c->n_comp + c->n_bkg : nr::kTmplCols;
+}
+
+// Fold the row block [row0, row0 + n_t) of R with factors F [n_t][kTmplCols]
+// into the record columns dst (of records rl doubles long).
+static hipError_t fold_block(nr_ctx* c, const std::vector<double>& F, size_t row0,
+                             const int dst[nr::kTmplCols], int rl, double* d_F,
+                             double* d_part, int n_slab) {
+    hipError_t e = hipMemcpy(d_F, F.data(), sizeof(double) * F.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    nr::TmplFoldArgs fa{c->d_R + row0 * c->ldr, c->ldr, c->n_t, c->n_reco, d_F, d_part};
+    if ((e = nr::launch_tmpl_fold(fa, n_slab, c->stream)) != hipSuccess) return e;
+    nr::TmplRecArgs ra{};
+    ra.part = d_part;
+    ra.n_slab = n_slab;
+    ra.n_reco = c->n_reco;
+    ra.rec = c->d_trec;
+    ra.rl = rl;
+    for (int b = 0; b < nr::kTmplCols; ++b) ra.dst[b] = dst[b];
+    if ((e = nr::launch_tmpl_records(ra, c->stream)) != hipSuccess) return e;
+    return hipStreamSynchronize(c->stream);  // F and part are reused
+}
+
 static int build_templates(nr_ctx* c) {
-    const int n_t = c->n_t, n_reco = c->n_reco;
+    const int n_t = c->n_t, n_reco = c->n_reco, rl = tmpl_rl(c);
     constexpr int NC = nr::kTmplCols;
     int rc;
     hipError_t e = hipSuccess;
     if (!c->tmpl_ok) {
-        std::vector<double> F((size_t)n_t * NC, 0.0);
-        for (int l = 0; l < n_t; ++l) {
-            const double ssm = c->ssm[l], m = c->mrow[l];
-            if (ssm > 0.0) {
-                for (int b = 0; b < nr::kNBasis; ++b)
-                    F[(size_t)l * NC + b] = m * c->basis[(size_t)b * n_t + l] / ssm;
-            } else {
-                F[(size_t)l * NC + nr::kNBasis] = m;
-            }
-        }
         const int n_slab = (n_t + nr::kTmplSlabRows - 1) / nr::kTmplSlabRows;
         double *d_F = nullptr, *d_part = nullptr;
         c->tmpl_data_ok = false;
-        if ((rc = dalloc(&d_F, F.size())) ||
+        if ((rc = dalloc(&d_F, (size_t)n_t * NC)) ||
             (rc = dalloc(&d_part, (size_t)n_slab * NC * n_reco)) ||
-            (rc = dalloc(&c->d_trec, (size_t)n_reco * nr::kTmplRec))) {
+            (rc = dalloc(&c->d_trec, (size_t)n_reco * rl))) {
             dfree(&d_F);
             dfree(&d_part);
             return rc;
         }
-        e = hipMemcpy(d_F, F.data(), sizeof(double) * F.size(), hipMemcpyHostToDevice);
-        if (e == hipSuccess) {
-            nr::TmplFoldArgs fa{c->d_R, c->ldr, n_t, n_reco, d_F, d_part};
-            e = nr::launch_tmpl_fold(fa, n_slab, c->stream);
+        std::vector<double> F((size_t)n_t * NC);
+        int dst[NC];
+        if (!c->multi) {
+            for (int l = 0; l < n_t; ++l) {
+                const double ssm = c->ssm[l], m = c->mrow[l];
+                for (int b = 0; b < NC; ++b) F[(size_t)l * NC + b] = 0.0;
+                if (ssm > 0.0) {
+                    for (int b = 0; b < nr::kNBasis; ++b)
+                        F[(size_t)l * NC + b] = m * c->basis[(size_t)b * n_t + l] / ssm;
+                } else {
+                    F[(size_t)l * NC + nr::kNBasis] = m;
+                }
+            }
+            for (int b = 0; b < NC; ++b) dst[b] = b;
+            e = fold_block(c, F, 0, dst, rl, d_F, d_part, n_slab);
+        } else {
+            // per component: its sources' basis, its SM spectrum, its rows
+            const int K = c->n_comp;
+            std::vector<double> ssmc((size_t)K * n_t), mrow((size_t)K * n_t);
+            e = hipMemcpy(ssmc.data(), c->d_ssmc, sizeof(double) * ssmc.size(), hipMemcpyDeviceToHost);
+            if (e == hipSuccess)
+                e = hipMemcpy(mrow.data(), c->d_mrow, sizeof(double) * mrow.size(), hipMemcpyDeviceToHost);
+            for (int k = 0; k < K && e == hipSuccess; ++k) {
+                for (int l = 0; l < n_t; ++l) {
+                    double I[10] = {0}, acc[10];
+                    for (int q = c->comp_off[k]; q < c->comp_off[k + 1]; ++q) {
+                        source_basis(c, c->comp_src[q], l, acc);
+                        for (int b = 0; b < 10; ++b) I[b] += acc[b];
+                    }
+                    const size_t row = (size_t)k * n_t + l;
+                    double* f = &F[(size_t)l * NC];
+                    for (int b = 0; b < NC; ++b) f[b] = 0.0;
+                    if (ssmc[row] > 0.0) {
+                        for (int b = 0; b < 10; ++b) f[b] = mrow[row] * I[b] / ssmc[row];
+                    } else {
+                        f[nr::kNBasis] = mrow[row];
+                    }
+                }
+                for (int b = 0; b < NC; ++b) dst[b] = -1;
+                for (int b = 0; b < 10; ++b) dst[b] = nr::kTmplCompCols * k + b;
+                dst[nr::kNBasis] = nr::kTmplCompCols * k + 10;
+                e = fold_block(c, F, (size_t)k * n_t, dst, rl, d_F, d_part, n_slab);
+            }
         }
-        if (e == hipSuccess) {
-            nr::TmplRecArgs ra{d_part, n_slab, n_reco, c->d_trec};
-            e = nr::launch_tmpl_records(ra, c->stream);
-        }
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         dfree(&d_F);
         dfree(&d_part);
         if (e != hipSuccess) return fail(NR_EHIP, "template fold: %s", hipGetErrorString(e));
         c->tmpl_ok = true;
     }
     if (!c->tmpl_data_ok) {
-        nr::TmplDataArgs da{c->d_n, c->d_b, n_reco, c->d_trec};
-        e = nr::launch_tmpl_data(da, c->stream);
+        if (!c->multi) {
+            nr::TmplDataArgs da{c->d_n, c->d_b, n_reco, c->d_trec};
+            e = nr::launch_tmpl_data(da, c->stream);
+        } else {
+            nr::TmplMultiDataArgs da{c->d_n, c->d_bkg, c->d_mask, n_reco, c->n_comp,
+                                     c->n_bkg, rl, c->d_trec};
+            e = nr::launch_tmpl_mdata(da, c->stream);
+        }
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) return fail(NR_EHIP, "template data: %s", hipGetErrorString(e));
         c->tmpl_data_ok = true;
@@ -2165,20 +2237,30 @@ static int tmpl_split(const nr_ctx* c, int n_pts, bool grad, int* cols_per) {
     return (c->n_reco + cp - 1) / cp;
 }
 
+static int check_tmpl_form(const nr_ctx* c) {
+    if (c->multi && (c->n_comp > nr::kTmplMaxComp || c->n_bkg > nr::kTmplMaxBkg))
+        return fail(NR_EINVAL, "the template form takes up to %d components and %d "
+                    "background templates (have %d and %d)", nr::kTmplMaxComp,
+                    nr::kTmplMaxBkg, c->n_comp, c->n_bkg);
+    return 0;
+}
+
 static int ensure_tmpl(nr_ctx* c, int n_pts, bool grad) {
     int rc;
+    if ((rc = check_tmpl_form(c))) return rc;
     if ((!c->tmpl_ok || !c->tmpl_data_ok) && (rc = build_templates(c))) return rc;
     int cp;
     const size_t ns = (size_t)tmpl_split(c, n_pts, grad, &cp);
+    const size_t na = (size_t)tmpl_nacc(c);
     if (ns * n_pts > c->t_cap_d) {
         if ((rc = dalloc(&c->d_tdp, ns * n_pts))) return rc;
         c->t_cap_d = ns * n_pts;
     }
-    if (grad && ns * nr::kTmplCols * n_pts > c->t_cap_h) {
-        if ((rc = dalloc(&c->d_thp, ns * nr::kTmplCols * n_pts))) return rc;
-        c->t_cap_h = ns * nr::kTmplCols * n_pts;
+    if (grad && ns * na * n_pts > c->t_cap_h) {
+        if ((rc = dalloc(&c->d_thp, ns * na * n_pts))) return rc;
+        c->t_cap_h = ns * na * n_pts;
     }
-    const size_t nred = (size_t)(1 + nr::kTmplCols) * n_pts;
+    const size_t nred = (1 + na) * n_pts;
     if (nred > c->t_cap_r) {
         if ((rc = dalloc(&c->d_tred, nred))) return rc;
         c->t_cap_r = nred;
@@ -2190,39 +2272,77 @@ static int enqueue_tmpl(nr_ctx* c, const double* d_th, int n_pts, double* d_nll,
                         double* d_grad, double* d_mu, hipStream_t s) {
     int cp;
     const int ns = tmpl_split(c, n_pts, d_grad != nullptr, &cp);
-    nr::TmplEvalArgs e{};
-    e.rec = c->d_trec;
-    e.theta = d_th;
-    e.n_reco = c->n_reco;
-    e.n_pts = n_pts;
-    e.cols_per = cp;
-    e.ph = c->ph;
-    e.dpart = c->d_tdp;
-    e.hpart = d_grad ? c->d_thp : nullptr;
-    e.mu = d_mu;
-    HIPCHK(nr::launch_tmpl_eval(e, ns, s));
-    nr::TmplReduceArgs r{c->d_tdp, e.hpart, n_pts, ns, c->d_tred};
-    HIPCHK(nr::launch_tmpl_reduce(r, s));
-    nr::TmplFinalArgs f{};
-    f.red = c->d_tred;
-    f.theta = d_th;
-    f.n_pts = n_pts;
-    f.cdata = c->cdata;
-    for (int i = 0; i < NR_NTHETA; ++i) {
-        f.pull_mean[i] = c->pull_mean[i];
-        f.pull_sigma[i] = c->pull_sigma[i];
+    double* hpart = d_grad ? c->d_thp : nullptr;
+    if (!c->multi) {
+        nr::TmplEvalArgs e{};
+        e.rec = c->d_trec;
+        e.theta = d_th;
+        e.n_reco = c->n_reco;
+        e.n_pts = n_pts;
+        e.cols_per = cp;
+        e.ph = c->ph;
+        e.dpart = c->d_tdp;
+        e.hpart = hpart;
+        e.mu = d_mu;
+        HIPCHK(nr::launch_tmpl_eval(e, ns, s));
+    } else {
+        nr::TmplMultiEvalArgs e{};
+        e.rec = c->d_trec;
+        e.theta = d_th;
+        e.rl = tmpl_rl(c);
+        e.K = c->n_comp;
+        e.B = c->n_bkg;
+        e.n_theta = c->n_theta;
+        e.n_reco = c->n_reco;
+        e.n_pts = n_pts;
+        e.cols_per = cp;
+        e.ph = c->ph;
+        e.dpart = c->d_tdp;
+        e.hpart = hpart;
+        e.mu = d_mu;
+        HIPCHK(nr::launch_tmpl_meval(e, ns, s));
     }
-    f.ph = c->ph;
-    f.nll = d_nll;
-    f.grad = d_grad;
-    HIPCHK(nr::launch_tmpl_final(f, s));
+    nr::TmplReduceArgs r{c->d_tdp, hpart, n_pts, ns, tmpl_nacc(c), c->d_tred};
+    HIPCHK(nr::launch_tmpl_reduce(r, s));
+    if (!c->multi) {
+        nr::TmplFinalArgs f{};
+        f.red = c->d_tred;
+        f.theta = d_th;
+        f.n_pts = n_pts;
+        f.cdata = c->cdata;
+        for (int i = 0; i < NR_NTHETA; ++i) {
+            f.pull_mean[i] = c->pull_mean[i];
+            f.pull_sigma[i] = c->pull_sigma[i];
+        }
+        f.ph = c->ph;
+        f.nll = d_nll;
+        f.grad = d_grad;
+        HIPCHK(nr::launch_tmpl_final(f, s));
+    } else {
+        nr::TmplMultiFinalArgs f{};
+        f.red = c->d_tred;
+        f.theta = d_th;
+        f.n_theta = c->n_theta;
+        f.K = c->n_comp;
+        f.B = c->n_bkg;
+        f.n_pts = n_pts;
+        f.cdata = c->cdata;
+        for (int i = 0; i < nr::kMaxTheta; ++i) {
+            f.pull_mean[i] = c->pull_mean[i];
+            f.pull_sigma[i] = c->pull_sigma[i];
+        }
+        f.ph = c->ph;
+        f.nll = d_nll;
+        f.grad = d_grad;
+        HIPCHK(nr::launch_tmpl_mfinal(f, s));
+    }
     return 0;
 }
 
 int nr_build_templates(nr_ctx* c) {
     int rc;
     if ((rc = check_ready(c))) return rc;
-    if ((rc = check_single(c))) return rc;
+    if ((rc = check_tmpl_form(c))) return rc;
     if ((rc = set_device(c))) return rc;
     return build_templates(c);
 }
@@ -2231,7 +2351,6 @@ int nr_eval_nll_templates_dev(nr_ctx* c, const double* d_theta, int n_pts,
                               double* d_nll, double* d_grad, void* stream) {
     int rc;
     if ((rc = check_ready(c))) return rc;
-    if ((rc = check_single(c))) return rc;
     if (!d_theta || !d_nll || n_pts <= 0)
         return fail(NR_EINVAL, "null device pointer or n_pts <= 0");
     if ((rc = set_device(c))) return rc;
@@ -2246,12 +2365,11 @@ static int tmpl_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
                      double* grad, double* mu) {
     int rc;
     if ((rc = check_ready(c))) return rc;
-    if ((rc = check_single(c))) return rc;
-    if ((rc = check_theta(theta, n_pts))) return rc;
+    if ((rc = check_theta(theta, n_pts, c->n_theta))) return rc;
     if ((rc = set_device(c))) return rc;
     if ((rc = ensure_stage(c, n_pts, mu ? (size_t)n_pts * c->n_reco : 0, 0))) return rc;
     if ((rc = ensure_tmpl(c, n_pts, grad != nullptr))) return rc;
-    HIPCHK(hipMemcpyAsync(c->d_th, theta, sizeof(double) * n_pts * NR_NTHETA,
+    HIPCHK(hipMemcpyAsync(c->d_th, theta, sizeof(double) * n_pts * c->n_theta,
                           hipMemcpyHostToDevice, c->stream));
     if ((rc = enqueue_tmpl(c, c->d_th, n_pts, c->d_out, grad ? c->d_grad : nullptr,
                            mu ? c->d_mu : nullptr, c->stream)))
@@ -2260,7 +2378,7 @@ static int tmpl_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
         HIPCHK(hipMemcpyAsync(nll, c->d_out, sizeof(double) * n_pts,
                               hipMemcpyDeviceToHost, c->stream));
     if (grad)
-        HIPCHK(hipMemcpyAsync(grad, c->d_grad, sizeof(double) * n_pts * NR_NTHETA,
+        HIPCHK(hipMemcpyAsync(grad, c->d_grad, sizeof(double) * n_pts * c->n_theta,
                               hipMemcpyDeviceToHost, c->stream));
     if (mu)
         HIPCHK(hipMemcpyAsync(mu, c->d_mu, sizeof(double) * n_pts * c->n_reco,

@@ -91,7 +91,9 @@ struct TmplFoldArgs {
 struct TmplRecArgs {
     const double* part;
     int n_slab, n_reco;
-    double* rec;       // [n_reco][kTmplRec]
+    double* rec;       // [n_reco][rl]
+    int rl;            // record length (doubles)
+    int dst[kTmplCols];  // record column of each folded column, -1: not kept
 };
 
 struct TmplDataArgs {
@@ -111,12 +113,13 @@ struct TmplEvalArgs {
     double* mu;           // [n_pts][n_reco] or null
 };
 
-// Slice sums in slice order: red[0][p] = deviance, red[1 + b][p] = h_b.
+// Slice sums in slice order: red[0][p] = deviance, red[1 + v][p] = the
+// gradient contraction v (n_acc of them).
 struct TmplReduceArgs {
     const double* dpart;
-    const double* hpart;  // or null
-    int n_pts, n_split;
-    double* red;          // [1 + kTmplCols][n_pts] (first row only without hpart)
+    const double* hpart;  // [n_split][n_acc][n_pts] or null
+    int n_pts, n_split, n_acc;
+    double* red;          // [1 + n_acc][n_pts] (first row only without hpart)
 };
 
 struct TmplFinalArgs {
@@ -131,7 +134,50 @@ struct TmplFinalArgs {
     double* grad;         // [n_pts][7] or null
 };
 
+// Multi-component template form (Eqs. (Rij), (fNp_reweight), (mu_total)):
+// component k's sources give 10 basis spectra (no group scaling: the rate
+// parameter r_k scales the component), so per reco bin the record holds
+// G^(k)_0..9 and G0^(k) for each component, the background templates
+// MT Rate_q pdf_q(j), the common mask M_j and the data n_j:
+//   mu_j = M_j [ sum_k r_k (G0^(k)_j + sum_b c_b G^(k)_bj) + sum_q r_q B_qj ].
+constexpr int kTmplMaxComp = 8;
+constexpr int kTmplMaxBkg = 8;
+constexpr int kTmplCompCols = 11;
+
+struct TmplMultiDataArgs {
+    const double* n;     // [n_reco]
+    const double* bkg;   // [B][n_reco]
+    const double* mask;  // [n_reco] or null (1)
+    int n_reco, K, B, rl;
+    double* rec;
+};
+
+struct TmplMultiEvalArgs {
+    const double* rec;    // [n_reco][rl]
+    const double* theta;  // [n_pts][n_theta], n_theta = 5 + K + B
+    int rl, K, B, n_theta, n_reco, n_pts, cols_per;
+    Phys ph;
+    double* dpart;        // [n_split][n_pts]
+    double* hpart;        // [n_split][10 + K + B][n_pts] or null (gradient)
+    double* mu;           // [n_pts][n_reco] or null
+};
+
+struct TmplMultiFinalArgs {
+    const double* red;    // [1 + 10 + K + B][n_pts]
+    const double* theta;
+    int n_theta, K, B, n_pts;
+    double cdata;
+    double pull_mean[kMaxTheta];
+    double pull_sigma[kMaxTheta];
+    Phys ph;
+    double* nll;
+    double* grad;         // [n_pts][n_theta] or null
+};
+
 hipError_t launch_tmpl_fold(const TmplFoldArgs& a, int n_slab, hipStream_t s);
+hipError_t launch_tmpl_mdata(const TmplMultiDataArgs& a, hipStream_t s);
+hipError_t launch_tmpl_meval(const TmplMultiEvalArgs& a, int n_split, hipStream_t s);
+hipError_t launch_tmpl_mfinal(const TmplMultiFinalArgs& a, hipStream_t s);
 hipError_t launch_tmpl_records(const TmplRecArgs& a, hipStream_t s);
 hipError_t launch_tmpl_data(const TmplDataArgs& a, hipStream_t s);
 hipError_t launch_tmpl_eval(const TmplEvalArgs& a, int n_split, hipStream_t s);

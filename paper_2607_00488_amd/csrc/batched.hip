@@ -425,14 +425,15 @@ __global__ __launch_bounds__(256) void k_tmpl_fold(TmplFoldArgs a) {
         a.part[((size_t)blockIdx.y * kTmplCols + b) * a.n_reco + j] = acc[b];
 }
 
-// Slab sums in slab order, one (bin, template) per thread.
+// Slab sums in slab order, one (bin, template) per thread, into the record
+// column the caller maps each folded column to.
 __global__ __launch_bounds__(256) void k_tmpl_records(TmplRecArgs a) {
     const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= a.n_reco) return;
     const int b = blockIdx.y;
+    if (j >= a.n_reco || a.dst[b] < 0) return;
     double s = 0.0;
     for (int q = 0; q < a.n_slab; ++q) s += a.part[((size_t)q * kTmplCols + b) * a.n_reco + j];
-    a.rec[(size_t)j * kTmplRec + b] = s;
+    a.rec[(size_t)j * a.rl + a.dst[b]] = s;
 }
 
 // The data of each bin beside its templates (rewritten alone by set_data).
@@ -479,7 +480,7 @@ __global__ __launch_bounds__(kTmplWave) void k_tmpl_eval(TmplEvalArgs a) {
         // would leave ~1e-10 of noise in -2lnL, enough to stall a line
         // search; the logarithm of the ratio is accurate relative to its
         // own small size.
-        const double q = nj / mu;
+        const double q = nj > 0.0 ? nj / mu : 0.0;
         double d;
         if (nj > 0.0)
             d = mu > 0.0 ? (mu - nj) + nj * ln_pos(q) : INFINITY;
@@ -514,7 +515,7 @@ __global__ __launch_bounds__(kTmplWave) void k_tmpl_reduce(TmplReduceArgs a) {
         for (int q = 0; q < a.n_split; ++q) s += a.dpart[(size_t)q * a.n_pts + p];
     } else {
         for (int q = 0; q < a.n_split; ++q)
-            s += a.hpart[((size_t)q * kTmplCols + v - 1) * a.n_pts + p];
+            s += a.hpart[((size_t)q * a.n_acc + v - 1) * a.n_pts + p];
     }
     a.red[(size_t)v * a.n_pts + p] = s;
 }
@@ -549,7 +550,172 @@ __global__ __launch_bounds__(256) void k_tmpl_final(TmplFinalArgs a) {
     }
 }
 
+// ------------------------------------------------ multi-component templates
+// Backgrounds, mask and data of each bin after the component templates.
+__global__ __launch_bounds__(256) void k_tmpl_mdata(TmplMultiDataArgs a) {
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.n_reco) return;
+    double* r = a.rec + (size_t)j * a.rl;
+    const int ob = kTmplCompCols * a.K;
+    for (int q = 0; q < a.B; ++q) r[ob + q] = a.bkg[(size_t)q * a.n_reco + j];
+    r[ob + a.B] = a.mask ? a.mask[j] : 1.0;
+    r[ob + a.B + 1] = a.n[j];
+}
+
+// As k_tmpl_eval, for the multi-component record: per (point, bin) the
+// component sums t_k = G0^(k) + sum_b c_b G^(k)_b (11 K products), mu from
+// the rates, and for the gradient the 10 + K + B contractions
+//   H_b = sum_j a'_j sum_k r_k G^(k)_bj,  R_k = sum_j a'_j t_kj,
+//   Q_q = sum_j a'_j B_qj,  a'_j = M_j d(-2lnL)/d mu_j.
+// Loops run to the compile-time maxima with uniform predicates, so every
+// accumulator stays in registers.
+template <bool GRAD, bool MU>
+__global__ __launch_bounds__(kTmplWave) void k_tmpl_meval(TmplMultiEvalArgs a) {
+    const int p = blockIdx.x * kTmplWave + threadIdx.x;
+    const int sl = blockIdx.y;
+    const bool ok = p < a.n_pts;
+    const int pc = ok ? p : a.n_pts - 1;
+    const double* th = a.theta + (size_t)pc * a.n_theta;
+    double t7[kNTheta] = {th[0], th[1], th[2], th[3], th[4], 1.0, 1.0};
+    double c[kNBasis];
+    basis_coef(t7, a.ph, c);  // c[0..9]: the coefficients without group scaling
+    double rk[kTmplMaxComp], rb[kTmplMaxBkg];
+#pragma unroll
+    for (int k = 0; k < kTmplMaxComp; ++k) rk[k] = k < a.K ? th[5 + k] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kTmplMaxBkg; ++q) rb[q] = q < a.B ? th[5 + a.K + q] : 0.0;
+    const int ob = kTmplCompCols * a.K;
+    const int j0 = sl * a.cols_per;
+    const int j1 = min(j0 + a.cols_per, a.n_reco);
+    double dsum = 0.0;
+    double H[10], Rk[kTmplMaxComp], Qb[kTmplMaxBkg];
+#pragma unroll
+    for (int b = 0; b < 10; ++b) H[b] = 0.0;
+#pragma unroll
+    for (int k = 0; k < kTmplMaxComp; ++k) Rk[k] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kTmplMaxBkg; ++q) Qb[q] = 0.0;
+    for (int j = j0; j < j1; ++j) {
+        const double* __restrict__ r = a.rec + (size_t)j * a.rl;
+        double s = 0.0, tk[kTmplMaxComp];
+#pragma unroll
+        for (int k = 0; k < kTmplMaxComp; ++k) {
+            tk[k] = 0.0;
+            if (k < a.K) {
+                const double* g = r + kTmplCompCols * k;
+                double t = g[10];
+#pragma unroll
+                for (int b = 0; b < 10; ++b) t = fma(c[b], g[b], t);
+                tk[k] = t;
+                s = fma(rk[k], t, s);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kTmplMaxBkg; ++q)
+            if (q < a.B) s = fma(rb[q], r[ob + q], s);
+        const double mask = r[ob + a.B], nj = r[ob + a.B + 1];
+        const double mu = s * mask;
+        const double qn = nj > 0.0 ? nj / mu : 0.0;
+        double d;
+        if (nj > 0.0)
+            d = mu > 0.0 ? (mu - nj) + nj * ln_pos(qn) : INFINITY;
+        else
+            d = mu;
+        dsum += d;
+        if (MU && ok) a.mu[(size_t)p * a.n_reco + j] = mu;
+        if (GRAD) {
+            const double ap = 2.0 * (1.0 - qn) * mask;
+#pragma unroll
+            for (int k = 0; k < kTmplMaxComp; ++k)
+                if (k < a.K) Rk[k] = fma(ap, tk[k], Rk[k]);
+#pragma unroll
+            for (int b = 0; b < 10; ++b) {
+                double T = 0.0;
+#pragma unroll
+                for (int k = 0; k < kTmplMaxComp; ++k)
+                    if (k < a.K) T = fma(rk[k], r[kTmplCompCols * k + b], T);
+                H[b] = fma(ap, T, H[b]);
+            }
+#pragma unroll
+            for (int q = 0; q < kTmplMaxBkg; ++q)
+                if (q < a.B) Qb[q] = fma(ap, r[ob + q], Qb[q]);
+        }
+    }
+    if (!ok) return;
+    a.dpart[(size_t)sl * a.n_pts + p] = dsum;
+    if (GRAD) {
+        const int na = 10 + a.K + a.B;
+        double* hp = a.hpart + (size_t)sl * na * a.n_pts + p;
+#pragma unroll
+        for (int b = 0; b < 10; ++b) hp[(size_t)b * a.n_pts] = H[b];
+#pragma unroll
+        for (int k = 0; k < kTmplMaxComp; ++k)
+            if (k < a.K) hp[(size_t)(10 + k) * a.n_pts] = Rk[k];
+#pragma unroll
+        for (int q = 0; q < kTmplMaxBkg; ++q)
+            if (q < a.B) hp[(size_t)(10 + a.K + q) * a.n_pts] = Qb[q];
+    }
+}
+
+// -2lnL and gradient of the multi-component form: d/d theta_i (i < 5) =
+// sum_b dc_ib H_b, d/d r_k = R_k, d/d r_q = Q_q, plus the pulls.
+__global__ __launch_bounds__(256) void k_tmpl_mfinal(TmplMultiFinalArgs a) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= a.n_pts) return;
+    const double* th = a.theta + (size_t)p * a.n_theta;
+    double pulls = 0.0;
+    for (int i = 0; i < a.n_theta; ++i)
+        if (a.pull_sigma[i] > 0.0) {
+            const double z = (th[i] - a.pull_mean[i]) / a.pull_sigma[i];
+            pulls += z * z;
+        }
+    a.nll[p] = 2.0 * a.red[p] + 2.0 * a.cdata + pulls;
+    if (!a.grad) return;
+    const double* h = a.red + a.n_pts + p;  // contraction v at h[v * n_pts]
+    double t7[kNTheta] = {th[0], th[1], th[2], th[3], th[4], 1.0, 1.0};
+    double dc[kNTheta][kNBasis];
+    basis_dcoef(t7, a.ph, dc);
+    double* g = a.grad + (size_t)p * a.n_theta;
+    double hb[10];
+#pragma unroll
+    for (int b = 0; b < 10; ++b) hb[b] = h[(size_t)b * a.n_pts];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < 10; ++b) v += dc[i][b] * hb[b];
+        g[i] = v;
+    }
+    for (int i = 5; i < a.n_theta; ++i) g[i] = h[(size_t)(10 + i - 5) * a.n_pts];  // R_k, Q_q
+    for (int i = 0; i < a.n_theta; ++i)
+        if (a.pull_sigma[i] > 0.0)
+            g[i] += 2.0 * (th[i] - a.pull_mean[i]) / (a.pull_sigma[i] * a.pull_sigma[i]);
+}
+
 }  // namespace
+
+hipError_t launch_tmpl_mdata(const TmplMultiDataArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_tmpl_mdata, dim3((a.n_reco + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tmpl_meval(const TmplMultiEvalArgs& a, int n_split, hipStream_t s) {
+    if (a.K < 1 || a.K > kTmplMaxComp || a.B < 0 || a.B > kTmplMaxBkg || (a.hpart && a.mu))
+        return hipErrorInvalidValue;
+    const dim3 grid((a.n_pts + kTmplWave - 1) / kTmplWave, n_split);
+    if (a.hpart)
+        hipLaunchKernelGGL((k_tmpl_meval<true, false>), grid, dim3(kTmplWave), 0, s, a);
+    else if (a.mu)
+        hipLaunchKernelGGL((k_tmpl_meval<false, true>), grid, dim3(kTmplWave), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_tmpl_meval<false, false>), grid, dim3(kTmplWave), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tmpl_mfinal(const TmplMultiFinalArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_tmpl_mfinal, dim3((a.n_pts + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_tmpl_fold(const TmplFoldArgs& a, int n_slab, hipStream_t s) {
     hipLaunchKernelGGL(k_tmpl_fold, dim3((a.n_reco + 255) / 256, n_slab), dim3(256), 0, s, a);
@@ -579,7 +745,7 @@ hipError_t launch_tmpl_eval(const TmplEvalArgs& a, int n_split, hipStream_t s) {
 }
 
 hipError_t launch_tmpl_reduce(const TmplReduceArgs& a, hipStream_t s) {
-    const dim3 grid((a.n_pts + kTmplWave - 1) / kTmplWave, a.hpart ? 1 + kTmplCols : 1);
+    const dim3 grid((a.n_pts + kTmplWave - 1) / kTmplWave, a.hpart ? 1 + a.n_acc : 1);
     hipLaunchKernelGGL(k_tmpl_reduce, grid, dim3(kTmplWave), 0, s, a);
     return hipGetLastError();
 }

@@ -97,6 +97,60 @@ def test_device_path_graph_replay_and_guards(setup):
         ctx.eval_nll_batched(th[:2])
 
 
+def test_templates_multi_component(setup):
+    """The template form of the multi-component likelihood: spectra and
+    -2lnL against the multi-component oracle, agreement with the streaming
+    path, and gradients (ε, m2, every component and background rate)
+    against five-point central differences of the oracle's -2lnL."""
+    co, ctx, K, B, n_t, n_reco = setup
+    th = points(K, B, 96, 65)
+    mu = ctx.eval_mu_templates(th)
+    nll, g = ctx.eval_nll_templates(th, grad=True)
+    plain = ctx.eval_nll(th)
+    worst = 0.0
+    for i in range(len(th)):
+        ref = co.mu(th[i])
+        scale = np.maximum(np.abs(ref), 1e-9 * np.abs(ref).max())
+        assert np.max(np.abs(mu[i] - ref) / scale) <= 1e-5, i
+        v = co.nll(th[i])
+        worst = max(worst, abs(nll[i] - v))
+        assert abs(nll[i] - v) <= 1e-3, (i, nll[i], v)
+    assert np.max(np.abs(nll - plain)) <= 1e-3
+    h = 1e-4
+    for i in (0, 7, 50):
+        fd = np.empty(len(th[i]))
+        for k in range(len(th[i])):
+            def f(sg):
+                t = th[i].copy()
+                t[k] += sg * h
+                return co.nll(t)
+            fd[k] = (8 * (f(1) - f(-1)) - (f(2) - f(-2))) / (12 * h)
+        sc = np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+        assert np.all(np.abs(g[i] - fd) <= 1e-4 * sc + 1e-6), (i, g[i], fd)
+    log(f"[gpu] multi-component templates {n_t}x{n_reco}: max |dnll| {worst:.2e}")
+
+
+def test_templates_multi_component_limits():
+    """More background templates than the template form takes: a status
+    code, while the streaming path still evaluates."""
+    import paper_2607_00488_amd as nr
+    n_t, n_reco = 64, 32
+    src = synth.source_nodes(16)
+    d = synth.component_inputs(n_t, n_reco, 20_000, 83)
+    ctx = nr.Context(0)
+    ctx.set_sources(src, n_t)
+    ctx.set_components(d["comp_of_source"], d["hist"], d["scale"], d["rate_sm"],
+                       bkg_pdf=np.full((9, n_reco), 1.0 / n_reco), bkg_rate=np.ones(9))
+    ctx.set_data(np.ones(n_reco), None)
+    th = np.concatenate([np.zeros(5), np.ones(5 + 9)])[None]
+    for call in (lambda: ctx.build_templates(), lambda: ctx.eval_nll_templates(th)):
+        with pytest.raises(nr.NrError) as e:
+            call()
+        assert e.value.code == nr.NR_EINVAL
+    assert np.isfinite(ctx.eval_nll(th)).all()
+    ctx.close()
+
+
 def test_back_to_single_component():
     """nr_set_response after the multi-component form restores the
     single-component path exactly."""

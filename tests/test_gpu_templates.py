@@ -1,8 +1,9 @@
 """Parity of the template form (basis templates folded once through R, then
 21 products and a logarithm per bin and point) with the FP64 oracle: spectra,
 -2lnL and gradients at the parity sizes, ragged shapes and point counts,
-empty bins and mu <= 0, invalidation by set_data / set_response, graph
-replay, and the multi-component refusal."""
+empty bins and mu <= 0, invalidation by set_data / set_response and graph
+replay (the multi-component form is tested with the other multi-component
+paths)."""
 import math
 import sys
 
@@ -174,24 +175,3 @@ def test_templates_device_path_and_graph_replay(cfg0):
         assert np.array_equal(gr.cpu().numpy(), gref), rep
         x = torch.randn(1 << 20, device=dev)
         (x * 2).sum().item()
-
-
-def test_templates_refuse_multi_component():
-    import paper_2607_00488_amd as nr
-    n_t, n_reco = 64, 16
-    src = synth.source_nodes(8)
-    d = synth.component_inputs(n_t, n_reco, 20_000, 9)
-    ctx = nr.Context(0)
-    ctx.set_sources(src, n_t, 0.0, 16.0)
-    ctx.set_components(d["comp_of_source"], d["hist"], d["scale"], d["rate_sm"],
-                       bkg_pdf=d["bkg_pdf"], bkg_rate=d["bkg_rate"],
-                       comp_mask=d["comp_mask"], mask=d["mask"],
-                       exposure=d["exposure"])
-    ctx.set_data(np.full(n_reco, 5.0), None)
-    with pytest.raises(nr.NrError) as e:
-        ctx.build_templates()
-    assert e.value.code == nr.NR_ESTATE
-    with pytest.raises(nr.NrError) as e:
-        ctx.eval_nll_templates(synth.theta_sm())
-    assert e.value.code == nr.NR_ESTATE
-    ctx.close()

@@ -142,6 +142,8 @@ struct TmplFinalArgs {
 //   mu_j = M_j [ sum_k r_k (G0^(k)_j + sum_b c_b G^(k)_bj) + sum_q r_q B_qj ].
 constexpr int kTmplMaxComp = 8;
 constexpr int kTmplMaxBkg = 8;
+constexpr int kTmplSmallComp = 5;  // a smaller register class of the kernel
+constexpr int kTmplSmallBkg = 4;
 constexpr int kTmplCompCols = 11;
 
 struct TmplMultiDataArgs {

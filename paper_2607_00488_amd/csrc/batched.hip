@@ -567,9 +567,11 @@ __global__ __launch_bounds__(256) void k_tmpl_mdata(TmplMultiDataArgs a) {
 // the rates, and for the gradient the 10 + K + B contractions
 //   H_b = sum_j a'_j sum_k r_k G^(k)_bj,  R_k = sum_j a'_j t_kj,
 //   Q_q = sum_j a'_j B_qj,  a'_j = M_j d(-2lnL)/d mu_j.
-// Loops run to the compile-time maxima with uniform predicates, so every
-// accumulator stays in registers.
-template <bool GRAD, bool MU>
+// Loops run to compile-time maxima KM, BM with uniform predicates, so every
+// accumulator stays in registers; the smaller size class (five components,
+// four backgrounds: the solar species) needs fewer registers and keeps more
+// waves resident.
+template <bool GRAD, bool MU, int KM, int BM>
 __global__ __launch_bounds__(kTmplWave) void k_tmpl_meval(TmplMultiEvalArgs a) {
     const int p = blockIdx.x * kTmplWave + threadIdx.x;
     const int sl = blockIdx.y;
@@ -579,39 +581,45 @@ __global__ __launch_bounds__(kTmplWave) void k_tmpl_meval(TmplMultiEvalArgs a) {
     double t7[kNTheta] = {th[0], th[1], th[2], th[3], th[4], 1.0, 1.0};
     double c[kNBasis];
     basis_coef(t7, a.ph, c);  // c[0..9]: the coefficients without group scaling
-    double rk[kTmplMaxComp], rb[kTmplMaxBkg];
+    double rk[KM], rb[BM];
 #pragma unroll
-    for (int k = 0; k < kTmplMaxComp; ++k) rk[k] = k < a.K ? th[5 + k] : 0.0;
+    for (int k = 0; k < KM; ++k) rk[k] = k < a.K ? th[5 + k] : 0.0;
 #pragma unroll
-    for (int q = 0; q < kTmplMaxBkg; ++q) rb[q] = q < a.B ? th[5 + a.K + q] : 0.0;
+    for (int q = 0; q < BM; ++q) rb[q] = q < a.B ? th[5 + a.K + q] : 0.0;
     const int ob = kTmplCompCols * a.K;
     const int j0 = sl * a.cols_per;
     const int j1 = min(j0 + a.cols_per, a.n_reco);
     double dsum = 0.0;
-    double H[10], Rk[kTmplMaxComp], Qb[kTmplMaxBkg];
+    double H[10], Rk[KM], Qb[BM];
 #pragma unroll
     for (int b = 0; b < 10; ++b) H[b] = 0.0;
 #pragma unroll
-    for (int k = 0; k < kTmplMaxComp; ++k) Rk[k] = 0.0;
+    for (int k = 0; k < KM; ++k) Rk[k] = 0.0;
 #pragma unroll
-    for (int q = 0; q < kTmplMaxBkg; ++q) Qb[q] = 0.0;
+    for (int q = 0; q < BM; ++q) Qb[q] = 0.0;
     for (int j = j0; j < j1; ++j) {
         const double* __restrict__ r = a.rec + (size_t)j * a.rl;
-        double s = 0.0, tk[kTmplMaxComp];
+        double s = 0.0, tk[KM], T[10];
 #pragma unroll
-        for (int k = 0; k < kTmplMaxComp; ++k) {
+        for (int b = 0; b < 10; ++b) T[b] = 0.0;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
             tk[k] = 0.0;
             if (k < a.K) {
                 const double* g = r + kTmplCompCols * k;
                 double t = g[10];
 #pragma unroll
                 for (int b = 0; b < 10; ++b) t = fma(c[b], g[b], t);
+                if (GRAD) {  // T_b = sum_k r_k G^(k)_bj, for H_b
+#pragma unroll
+                    for (int b = 0; b < 10; ++b) T[b] = fma(rk[k], g[b], T[b]);
+                }
                 tk[k] = t;
                 s = fma(rk[k], t, s);
             }
         }
 #pragma unroll
-        for (int q = 0; q < kTmplMaxBkg; ++q)
+        for (int q = 0; q < BM; ++q)
             if (q < a.B) s = fma(rb[q], r[ob + q], s);
         const double mask = r[ob + a.B], nj = r[ob + a.B + 1];
         const double mu = s * mask;
@@ -626,18 +634,12 @@ __global__ __launch_bounds__(kTmplWave) void k_tmpl_meval(TmplMultiEvalArgs a) {
         if (GRAD) {
             const double ap = 2.0 * (1.0 - qn) * mask;
 #pragma unroll
-            for (int k = 0; k < kTmplMaxComp; ++k)
+            for (int k = 0; k < KM; ++k)
                 if (k < a.K) Rk[k] = fma(ap, tk[k], Rk[k]);
 #pragma unroll
-            for (int b = 0; b < 10; ++b) {
-                double T = 0.0;
+            for (int b = 0; b < 10; ++b) H[b] = fma(ap, T[b], H[b]);
 #pragma unroll
-                for (int k = 0; k < kTmplMaxComp; ++k)
-                    if (k < a.K) T = fma(rk[k], r[kTmplCompCols * k + b], T);
-                H[b] = fma(ap, T, H[b]);
-            }
-#pragma unroll
-            for (int q = 0; q < kTmplMaxBkg; ++q)
+            for (int q = 0; q < BM; ++q)
                 if (q < a.B) Qb[q] = fma(ap, r[ob + q], Qb[q]);
         }
     }
@@ -649,10 +651,10 @@ __global__ __launch_bounds__(kTmplWave) void k_tmpl_meval(TmplMultiEvalArgs a) {
 #pragma unroll
         for (int b = 0; b < 10; ++b) hp[(size_t)b * a.n_pts] = H[b];
 #pragma unroll
-        for (int k = 0; k < kTmplMaxComp; ++k)
+        for (int k = 0; k < KM; ++k)
             if (k < a.K) hp[(size_t)(10 + k) * a.n_pts] = Rk[k];
 #pragma unroll
-        for (int q = 0; q < kTmplMaxBkg; ++q)
+        for (int q = 0; q < BM; ++q)
             if (q < a.B) hp[(size_t)(10 + a.K + q) * a.n_pts] = Qb[q];
     }
 }
@@ -703,12 +705,17 @@ hipError_t launch_tmpl_meval(const TmplMultiEvalArgs& a, int n_split, hipStream_
     if (a.K < 1 || a.K > kTmplMaxComp || a.B < 0 || a.B > kTmplMaxBkg || (a.hpart && a.mu))
         return hipErrorInvalidValue;
     const dim3 grid((a.n_pts + kTmplWave - 1) / kTmplWave, n_split);
-    if (a.hpart)
-        hipLaunchKernelGGL((k_tmpl_meval<true, false>), grid, dim3(kTmplWave), 0, s, a);
-    else if (a.mu)
-        hipLaunchKernelGGL((k_tmpl_meval<false, true>), grid, dim3(kTmplWave), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_tmpl_meval<false, false>), grid, dim3(kTmplWave), 0, s, a);
+    const bool small = a.K <= kTmplSmallComp && a.B <= kTmplSmallBkg;
+    constexpr int KS = kTmplSmallComp, BS = kTmplSmallBkg, KL = kTmplMaxComp, BL = kTmplMaxBkg;
+    if (a.hpart) {
+        if (small) hipLaunchKernelGGL((k_tmpl_meval<true, false, KS, BS>), grid, dim3(kTmplWave), 0, s, a);
+        else hipLaunchKernelGGL((k_tmpl_meval<true, false, KL, BL>), grid, dim3(kTmplWave), 0, s, a);
+    } else if (a.mu) {
+        hipLaunchKernelGGL((k_tmpl_meval<false, true, KL, BL>), grid, dim3(kTmplWave), 0, s, a);
+    } else {
+        if (small) hipLaunchKernelGGL((k_tmpl_meval<false, false, KS, BS>), grid, dim3(kTmplWave), 0, s, a);
+        else hipLaunchKernelGGL((k_tmpl_meval<false, false, KL, BL>), grid, dim3(kTmplWave), 0, s, a);
+    }
     return hipGetLastError();
 }
 

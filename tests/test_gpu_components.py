@@ -130,6 +130,54 @@ def test_templates_multi_component(setup):
     log(f"[gpu] multi-component templates {n_t}x{n_reco}: max |dnll| {worst:.2e}")
 
 
+def test_templates_multi_component_general_class():
+    """Six background templates take the kernel's general register class
+    (up to 8 components and 8 backgrounds): spectra, -2lnL and one gradient
+    against the multi-component oracle."""
+    import paper_2607_00488_amd as nr
+    n_t, n_reco, n_e = 160, 48, 24
+    src = synth.source_nodes(n_e)
+    d = synth.component_inputs(n_t, n_reco, 100_000, 85)
+    g = synth.rng(86)
+    B = 6
+    pdf = g.uniform(0.2, 1.0, (B, n_reco))
+    pdf /= pdf.sum(axis=1, keepdims=True)
+    rate = g.uniform(50.0, 500.0, B)
+    co = ComponentOracle(src, d["comp_of_source"], n_t, d["hist"], d["scale"],
+                         d["rate_sm"], pdf, rate, d["comp_mask"], d["mask"],
+                         d["exposure"])
+    K = len(d["scale"])
+    th_sm = np.concatenate([np.zeros(5), np.ones(K + B)])
+    n = synth.poisson_data(co.mu(th_sm), 87)
+    co.set_data(n)
+    ctx = nr.Context(0)
+    ctx.set_sources(src, n_t, 0.0, 16.0)
+    ctx.set_components(d["comp_of_source"], d["hist"], d["scale"], d["rate_sm"],
+                       bkg_pdf=pdf, bkg_rate=rate, comp_mask=d["comp_mask"],
+                       mask=d["mask"], exposure=d["exposure"])
+    ctx.set_data(n, None)
+    th = points(K, B, 24, 88)
+    mu = ctx.eval_mu_templates(th)
+    nll, gr = ctx.eval_nll_templates(th, grad=True)
+    for i in range(len(th)):
+        ref = co.mu(th[i])
+        scale = np.maximum(np.abs(ref), 1e-9 * np.abs(ref).max())
+        assert np.max(np.abs(mu[i] - ref) / scale) <= 1e-5, i
+        assert abs(nll[i] - co.nll(th[i])) <= 1e-3, i
+    h = 1e-4
+    fd = np.empty(th.shape[1])
+    for k in range(th.shape[1]):
+        def f(sg):
+            t = th[3].copy()
+            t[k] += sg * h
+            return co.nll(t)
+        fd[k] = (8 * (f(1) - f(-1)) - (f(2) - f(-2))) / (12 * h)
+    sc = np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+    assert np.all(np.abs(gr[3] - fd) <= 1e-4 * sc + 1e-6), (gr[3], fd)
+    ctx.close()
+    co.close()
+
+
 def test_templates_multi_component_limits():
     """More background templates than the template form takes: a status
     code, while the streaming path still evaluates."""

@@ -35,5 +35,26 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+ASAN_LIB = os.path.join(HERE, "libnureweight_asan.so")
+
+
+def build_asan() -> str:
+    """The same library with AddressSanitizer on its host code only (the
+    device code is not instrumented), for the host-side sanitizer test: a C
+    program linked against it with clang's shared ASan runtime."""
+    hipcc = os.path.join(ROCM, "bin", "hipcc")
+    flags = [f for f in HIPCC_FLAGS if f != "-O3"] + [
+        "-O1", "-g", "-Xarch_host", "-fsanitize=address",
+        "-Xarch_host", "-fno-omit-frame-pointer", "-shared-libasan"]
+    tmp = ASAN_LIB + ".tmp"
+    res = subprocess.run([hipcc] + flags + sources() + ["-o", tmp],
+                         capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("hipcc (host ASan) failed:\n" + res.stdout + res.stderr)
+    os.replace(tmp, ASAN_LIB)
+    return ASAN_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_asan())

@@ -562,7 +562,7 @@ def main():
     # the FP64 matrix-core rate the chip sustains on register operands: the
     # practical ceiling of the batched GEMM beside the data-sheet 78.6
     import paper_2607_00488_amd as nr
-    probe = nr.nr_probe_mfma_f64(0, 8192, 250)
+    probe = nr.nr_probe_mfma_f64(0, 8192, 16)
     res["detail"]["fp64_mfma_probe_tflops"] = round(probe, 2)
     # and the HBM read rate of a plain stream (2 GiB, far beyond the caches)
     rd = nr.nr_probe_hbm_read(0, 2 << 30, 10)

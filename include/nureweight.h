@@ -362,8 +362,8 @@ int nr_eval_nll_templates_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
 
 /* Diagnostic: the FP64 matrix-core rate the device sustains, from a stream
  * of independent v_mfma_f64_16x16x4_f64 on register operands (8 chains per
- * wave, `blocks` work-groups of 4 waves, `iters` rounds; no memory traffic
- * while timed).  *tflops receives the rate; the batched GEMM (Sec. III.D's
+ * wave, `blocks` work-groups of 4 waves, `iters` trips of 16 rounds over
+ * the chains; no memory traffic while timed).  *tflops receives the rate; the batched GEMM (Sec. III.D's
  * fold as a matrix product) is compared with it.  Returns NR_EINVAL for
  * bad arguments (blocks in 1..65536), NR_EHIP / NR_ENOMEM on device
  * errors; it does not set the nr_last_error message. */

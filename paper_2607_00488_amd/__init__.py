@@ -342,7 +342,7 @@ def nr_eval_nll_templates_dev(h, d_theta_ptr, n_pts, d_nll_ptr, d_grad_ptr=None,
                                             C.c_void_p(stream_ptr or 0)))
 
 
-def nr_probe_mfma_f64(device=0, blocks=8192, iters=2000):
+def nr_probe_mfma_f64(device=0, blocks=8192, iters=16):
     """Sustained FP64 matrix-core TFLOP/s of the device (register-only
     stream of independent MFMA instructions)."""
     out = np.zeros(1)

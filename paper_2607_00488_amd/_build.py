@@ -13,6 +13,11 @@ HIPCC_FLAGS = [
     "-mcode-object-version=5",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix instructions accumulate in ordinary vector registers: with the
+    # accumulation registers the compiler carried the accumulators across
+    # the GEMM's K loop in vector registers and copied them over and back
+    # every step (96 moves per 32 MFMAs in the 64 x 128 tile)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-Wno-unused-command-line-argument",
 ]
 

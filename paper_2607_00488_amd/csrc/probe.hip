@@ -11,17 +11,23 @@
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
-constexpr int kChains = 8;  // independent accumulators per wave
+constexpr int kChains = 8;   // independent accumulators per wave
+constexpr int kRounds = 16;  // rounds over the chains per loop trip
 
 __global__ __launch_bounds__(256) void k_probe_mfma_f64(double* out, int iters) {
     v4d acc[kChains];
 #pragma unroll
     for (int c = 0; c < kChains; ++c) acc[c] = (v4d){0.0, 0.0, 0.0, 0.0};
     const double a = threadIdx.x * 1e-3, b = 1.0 + blockIdx.x * 1e-6;
+    // kRounds rounds per trip: the compiler moves the loop-carried
+    // accumulators between register files once per trip, which a short
+    // body would make the bottleneck instead of the matrix cores
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
-        for (int c = 0; c < kChains; ++c)
-            acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+        for (int r = 0; r < kRounds; ++r)
+#pragma unroll
+            for (int c = 0; c < kChains; ++c)
+                acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
     }
     double s = 0.0;
 #pragma unroll
@@ -114,7 +120,7 @@ extern "C" int nr_probe_mfma_f64(int device, int blocks, int iters, double* tflo
         if (hipEventSynchronize(e1) == hipSuccess && hipGetLastError() == hipSuccess &&
             hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms > 0.0f) {
             // 4 waves per work-group, 16 x 16 x 4 multiply-adds per instruction
-            *tflops = (double)blocks * 4 * iters * kChains * 2048.0 / (ms * 1e-3) / 1e12;
+            *tflops = (double)blocks * 4 * iters * kRounds * kChains * 2048.0 / (ms * 1e-3) / 1e12;
             rc = NR_OK;
         }
     }

@@ -1738,6 +1738,8 @@ struct nr_mlp {
     nr::bf16 *dy = nullptr, *dz[2] = {nullptr, nullptr};
     double* tile_loss = nullptr;
     double* part = nullptr;
+    float* gpart = nullptr;     // K-split weight-gradient slabs
+    size_t gpart_cap = 0;
     int* outside = nullptr;
     float *mean = nullptr, *stdv = nullptr;
     double lo[NR_NTHETA] = {-0.5, -0.5, -0.5, -0.5, 0.0, 0.8, 0.8};
@@ -1785,6 +1787,58 @@ nr::MlpGemm mg(const nr::bf16* A, long sam, long sak, const nr::bf16* B,
     g.B = B; g.sbk = sbk; g.sbn = sbn;
     g.M = M; g.N = N; g.K = K;
     return g;
+}
+
+// A GEMM with a long reduction and few output tiles — the weight gradients
+// G^T = dZ^T H (K = batch; 256 x 264 for a hidden layer: 6 tiles) and the
+// first backward product dY W (K = the 4096 outputs) — is split along K
+// over enough work-groups to fill the chip (about two per compute unit,
+// chunks of at least 256), each split writing its own FP32 slab; the slabs
+// are then summed in order and the GEMM's epilogue applied (FP32 store into
+// C32, or SiLU' into g.C16).  No float atomics: a training step stays
+// bitwise reproducible.
+int mlp_split_gemm(nr_mlp* q, nr::MlpGemm g, int mode, float* C32, long ldc, hipStream_t s) {
+    constexpr int kTK = 32, kTile = 128, kMinChunk = 256;
+    const int tiles = ((g.M + kTile - 1) / kTile) * ((g.N + kTile - 1) / kTile);
+    int n_split = std::max(1, std::min((512 + tiles - 1) / tiles, g.K / kMinChunk));
+    if (n_split <= 1) {
+        g.C32 = C32;
+        g.ldc = ldc;
+        HIPCHK(nr::launch_mlp_gemm(mode, g, s));
+        return 0;
+    }
+    const int chunk = ((g.K + n_split - 1) / n_split + kTK - 1) / kTK * kTK;
+    n_split = (g.K + chunk - 1) / chunk;
+    const long ldp = g.N;                 // slab rows
+    const long slab = (long)g.M * ldp;
+    const size_t need = (size_t)n_split * slab;
+    if (need > q->gpart_cap) {
+        int rc;
+        if ((rc = dalloc(&q->gpart, need))) return rc;
+        q->gpart_cap = need;
+    }
+    nr::MlpGemm gp = g;
+    gp.C32 = q->gpart;
+    gp.ldc = ldp;
+    gp.k_chunk = chunk;
+    gp.c_split = slab;
+    HIPCHK(nr::launch_mlp_gemm(nr::kMlpStore32, gp, s));
+    nr::KSumArgs ks{};
+    ks.part = q->gpart;
+    ks.c_split = slab;
+    ks.ldc = ldp;
+    ks.n_split = n_split;
+    ks.M = g.M;
+    ks.N = g.N;
+    ks.out = C32;
+    ks.ldo = ldc;
+    ks.dsilu = mode == nr::kMlpDSilu;
+    ks.aux = g.aux;
+    ks.ldaux = g.ldaux;
+    ks.C16 = g.C16;
+    ks.ldc16 = g.ldc16;
+    HIPCHK(nr::launch_mlp_ksum(ks, s));
+    return 0;
 }
 
 // Forward through the three hidden layers: Z_l = H_{l-1} W_l (bias in the
@@ -1870,7 +1924,7 @@ void nr_mlp_destroy(nr_mlp* q) {
     dfree(&q->x); dfree(&q->dy); dfree(&q->dz[0]); dfree(&q->dz[1]);
     for (int l = 0; l < 3; ++l) { dfree(&q->h[l]); dfree(&q->z[l]); }
     dfree(&q->tile_loss); dfree(&q->part); dfree(&q->outside);
-    dfree(&q->mean); dfree(&q->stdv);
+    dfree(&q->mean); dfree(&q->stdv); dfree(&q->gpart);
     if (q->ev_in) (void)hipEventDestroy(q->ev_in);
     if (q->ev_out) (void)hipEventDestroy(q->ev_out);
     (void)hipStreamDestroy(q->stream);
@@ -1966,12 +2020,9 @@ int nr_mlp_train_step_dev(nr_mlp* q, const double* d_theta, const float* d_t,
     go.tile_loss = q->tile_loss;
     HIPCHK(nr::launch_mlp_gemm(nr::kMlpMse, go, s));
     // output layer weight gradient: G3^T = dY^T H2
-    {
-        nr::MlpGemm g = mg(q->dy, 1, N, q->h[2], ldh, 1, N, ldh, B);
-        g.C32 = q->g + q->off[3];
-        g.ldc = ldh;
-        HIPCHK(nr::launch_mlp_gemm(nr::kMlpStore32, g, s));
-    }
+    if ((rc = mlp_split_gemm(q, mg(q->dy, 1, N, q->h[2], ldh, 1, N, ldh, B),
+                             nr::kMlpStore32, q->g + q->off[3], ldh, s)))
+        return rc;
     // back through the hidden layers
     const nr::bf16* up = q->dy;   // gradient w.r.t. the next layer's output
     int upw = N;                  // its width
@@ -1983,14 +2034,13 @@ int nr_mlp_train_step_dev(nr_mlp* q, const double* d_theta, const float* d_t,
         gd.ldaux = H;
         gd.C16 = dzl;
         gd.ldc16 = H;
-        HIPCHK(nr::launch_mlp_gemm(nr::kMlpDSilu, gd, s));
+        if ((rc = mlp_split_gemm(q, gd, nr::kMlpDSilu, nullptr, 0, s))) return rc;
         // G_l^T = dZ_l^T H_{l-1}  (H_{-1} = x)
         const nr::bf16* in = l == 0 ? q->x : q->h[l - 1];
         const int kin = l == 0 ? 32 : ldh;
-        nr::MlpGemm gw = mg(dzl, 1, H, in, kin, 1, H, q->kp[l], B);
-        gw.C32 = q->g + q->off[l];
-        gw.ldc = q->kp[l];
-        HIPCHK(nr::launch_mlp_gemm(nr::kMlpStore32, gw, s));
+        if ((rc = mlp_split_gemm(q, mg(dzl, 1, H, in, kin, 1, H, q->kp[l], B),
+                                 nr::kMlpStore32, q->g + q->off[l], q->kp[l], s)))
+            return rc;
         up = dzl;
         upw = H;
     }

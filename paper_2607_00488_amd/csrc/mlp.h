@@ -38,6 +38,26 @@ struct MlpGemm {
     const double* nobs; // [N] data (Nll)
     double* part;       // [M][n_nt] deviance partials (Nll)
     int n_nt;
+    // K split (Store32 only): work-group z sums k in [z k_chunk, (z+1)
+    // k_chunk) into the slab C32 + z c_split; 0 = one pass over all of K
+    int k_chunk;
+    long c_split;
+};
+
+// v[m][n] = sum_s part[s][m][n] over n_split slabs of stride c_split
+// (rows of ldc floats), in slab order; then out[m][n] = v (FP32), or with
+// dsilu C16[m][n] = v SiLU'(aux[m][n]) as the GEMM's kMlpDSilu epilogue.
+struct KSumArgs {
+    const float* part;
+    long c_split, ldc;
+    int n_split, M, N;
+    float* out;
+    long ldo;
+    int dsilu;
+    const float* aux;
+    long ldaux;
+    bf16* C16;
+    long ldc16;
 };
 
 struct MlpInput {
@@ -67,6 +87,7 @@ struct TargetArgs {
 };
 
 hipError_t launch_mlp_gemm(int mode, const MlpGemm& g, hipStream_t s);
+hipError_t launch_mlp_ksum(const KSumArgs& a, hipStream_t s);
 hipError_t launch_mlp_input(const MlpInput& a, hipStream_t s);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
 hipError_t launch_targets(const TargetArgs& a, hipStream_t s);

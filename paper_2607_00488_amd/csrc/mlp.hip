@@ -82,17 +82,20 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_gemm(MlpGemm g) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
+    // this work-group's range of k (all of it unless K is split)
+    const int kb = g.k_chunk ? (int)blockIdx.z * g.k_chunk : 0;
+    const int ke = g.k_chunk ? min(g.K, kb + g.k_chunk) : g.K;
     uint4 ra[2], rb[2];
-    load_tile(g.A, a_row, a_k, g.M, g.K, m0, 0, ra);
-    load_tile(g.B, b_row, b_k, g.N, g.K, n0, 0, rb);
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    load_tile(g.A, a_row, a_k, g.M, ke, m0, kb, ra);
+    load_tile(g.B, b_row, b_k, g.N, ke, n0, kb, rb);
+    for (int k0 = kb; k0 < ke; k0 += TK) {
         __syncthreads();
         store_tile(As, a_k, ra);
         store_tile(Bs, b_k, rb);
         __syncthreads();
-        if (k0 + TK < g.K) {
-            load_tile(g.A, a_row, a_k, g.M, g.K, m0, k0 + TK, ra);
-            load_tile(g.B, b_row, b_k, g.N, g.K, n0, k0 + TK, rb);
+        if (k0 + TK < ke) {
+            load_tile(g.A, a_row, a_k, g.M, ke, m0, k0 + TK, ra);
+            load_tile(g.B, b_row, b_k, g.N, ke, n0, k0 + TK, rb);
         }
 #pragma unroll
         for (int ks = 0; ks < TK; ks += 16) {
@@ -143,7 +146,7 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_gemm(MlpGemm g) {
                 if (m >= g.M || n >= g.N) continue;
                 const float v = acc[bi][bj][r];
                 if (MODE == kMlpStore32) {
-                    g.C32[(long)m * g.ldc + n] = v;
+                    g.C32[(long)blockIdx.z * g.c_split + (long)m * g.ldc + n] = v;
                 } else if (MODE == kMlpSilu) {
                     g.C32[(long)m * g.ldc + n] = v;
                     g.C16[(long)m * g.ldc16 + n] = (bf16)silu(v);
@@ -231,13 +234,40 @@ __global__ void k_ones_col(bf16* h, int B, int ld, int col) {
     for (int c = col + 1; c < ld; ++c) h[(long)p * ld + c] = (bf16)0.f;
 }
 
+// Sum of the K-split slabs of a GEMM, one element per thread, with the
+// epilogue of the split GEMM (plain FP32 store, or SiLU').
+__global__ __launch_bounds__(256) void k_mlp_ksum(KSumArgs a) {
+    const long e = (long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long)a.M * a.N) return;
+    const long m = e / a.N, n = e % a.N;
+    const long o = m * a.ldc + n;
+    float v = 0.f;
+    for (int q = 0; q < a.n_split; ++q) v += a.part[(long)q * a.c_split + o];
+    if (a.dsilu) {
+        const float z = a.aux[m * a.ldaux + n];
+        const float sg = 1.f / (1.f + __expf(-z));
+        a.C16[m * a.ldc16 + n] = (bf16)(v * sg * (1.f + z * (1.f - sg)));
+    } else {
+        a.out[m * a.ldo + n] = v;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_mlp_ksum(const KSumArgs& a, hipStream_t s) {
+    const long n = (long)a.M * a.N;
+    hipLaunchKernelGGL(k_mlp_ksum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_mlp_gemm(int mode, const MlpGemm& g, hipStream_t s) {
     if (g.M % 8 || g.N % 8 || g.K % 8 || (g.sak != 1 && g.sam != 1) ||
         (g.sbk != 1 && g.sbn != 1))
         return hipErrorInvalidValue;
-    dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
+    if (g.k_chunk && (mode != kMlpStore32 || g.k_chunk % TK || g.k_chunk <= 0))
+        return hipErrorInvalidValue;
+    const int n_split = g.k_chunk ? (g.K + g.k_chunk - 1) / g.k_chunk : 1;
+    dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, n_split);
     switch (mode) {
         case kMlpStore32: hipLaunchKernelGGL(k_mlp_gemm<kMlpStore32>, grid, dim3(kMlpThreads), 0, s, g); break;
         case kMlpSilu: hipLaunchKernelGGL(k_mlp_gemm<kMlpSilu>, grid, dim3(kMlpThreads), 0, s, g); break;

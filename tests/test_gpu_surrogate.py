@@ -25,11 +25,16 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def test_backward_kernels_match_reference(torch_dev):
+@pytest.mark.parametrize("B,N", [(128, 256), (2048, 256), (1024, 1024)])
+def test_backward_kernels_match_reference(torch_dev, B, N):
+    """Long reductions are split over work-groups (slabs summed in order):
+    at B = 2048 and 1024 the weight gradients' batch sums, at N = 1024 the
+    first backward product's sum over the outputs (with its SiLU'
+    epilogue in the summing kernel); at B = 128, N = 256 nothing is."""
     torch, dev = torch_dev
     from paper_2607_00488_amd.surrogate import Surrogate, init_params
     lo, hi = synth.theta_box()
-    H, N, B = 256, 256, 128
+    H = 256
     s = Surrogate(N, lo, hi, hidden=H, seed=11)
     params = init_params(H, N, 12, out_scale=1.0)
     s.set_params(params)
@@ -104,7 +109,17 @@ def test_surrogate_accuracy_and_fallback(trained, torch_dev):
     dvs = np.sum(mu_h - nobs + np.where(nobs > 0, nobs * (np.log(np.where(nobs > 0, nobs, 1)) - lm), 0.0), axis=1)
     ref = 2.0 * (dvs + cdata)
     fused = nll_s[:256].cpu().numpy()
-    assert np.all(np.abs(fused - ref) <= 1e-2 + 1e-6 * np.abs(ref)), np.max(np.abs(fused - ref))
+    # the two sides see ln mu and mu differently: the host's ln mu comes
+    # from the log-mu output, formed as mean + std * y in FP32 (2^-24 |ln mu|),
+    # while the fused epilogue forms ln mu in FP64 and mu = 2^(ln mu log2 e)
+    # in FP32 from ln mu rounded to FP32 (2^-24 |ln mu| each for that
+    # rounding and the scaled argument, ~2^-22 for the exponential and the
+    # result).  The deviance moves by (mu_j - n_j) per unit of relative
+    # change in mu_j or of change in ln mu_j, so the two -2lnL may differ by
+    # 2 sum_j |mu_j - n_j| (2^-22 |ln mu_j| + 2^-21), with margin
+    bound = 2.0 * np.sum(np.abs(mu_h - nobs) * (np.abs(lm) * 2.0 ** -22 + 2.0 ** -21), axis=1)
+    assert np.all(np.abs(fused - ref) <= bound + 1e-9 * np.abs(ref) + 1e-6), \
+        np.max(np.abs(fused - ref) - bound)
     # the exact reference itself against the oracle on a few points
     ev = exact.cpu().numpy()
     tv = th_val.cpu().numpy()

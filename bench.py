@@ -402,6 +402,34 @@ def components_form(n_pts=400):
                      "evaluation through the step kernel")
 
 
+def gemm_counter_pass():
+    """The batched likelihood GEMM alone, for hardware counters: 1024 points
+    on a 4096 x 4096 dataset (one of the 64-dataset scan's shapes; 256
+    tiles of 128 x 128, one per compute unit), eight calls after the tuner
+    has picked its tile."""
+    import torch
+    import synth
+    import paper_2607_00488_amd as nr
+    dev = torch.device("cuda:0")
+    src = synth.source_nodes(256)
+    rsp = synth.response_mc(4096, 4096, 1_000_000, seed=2001, keep_counts=False)
+    ctx = nr.Context(0)
+    ctx.set_sources(src, 4096)
+    ctx.set_response(rsp.R, n_sig=1.0e4)
+    b = np.full(4096, 10.0)
+    ctx.set_data(b, b)
+    th = synth.theta_prior(1024, 2002)
+    tt = torch.tensor(th, dtype=torch.float64, device=dev)
+    nl = torch.empty(1024, dtype=torch.float64, device=dev)
+    nr.eval_nll_multi_dev([ctx], [tt], [nl])       # tunes and captures
+    torch.cuda.synchronize()
+    for _ in range(8):
+        nr.eval_nll_multi_dev([ctx], [tt], [nl])
+    torch.cuda.synchronize()
+    ctx.close()
+    log("[bench] GEMM counter pass done: 8 calls of 2 x 1024 x 4096 x 4096 flop")
+
+
 def cpu_baseline(p, n_eval, gpu_ctx):
     """The FP64 oracle on the host cores for a bounded sample of points, and
     the GPU's -2lnL on the same inputs for the |Delta| column."""
@@ -441,6 +469,10 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-components", action="store_true")
     ap.add_argument("--surrogate-seconds", type=float, default=20.0)
+    ap.add_argument("--gemm-counter-pass", action="store_true",
+                    help="short run for matrix-core counters: the batched "
+                         "likelihood GEMM of 1024 points on a 4096 x 4096 "
+                         "dataset (a shape of the 64-dataset scan), 8 calls")
     ap.add_argument("--counter-pass", action="store_true",
                     help="short run for hardware-counter collection: 20 "
                          "single-point evaluations, then 20 plain 256 MiB "
@@ -454,6 +486,9 @@ def main():
     import torch
     import synth
     dev = torch.device("cuda:0")
+    if args.gemm_counter_pass:
+        gemm_counter_pass()
+        return
     p = build_plain(1)
     ctx, c = p["ctx"], p["cfg"]
     if args.counter_pass:

@@ -621,7 +621,15 @@ def main():
     rd = nr.nr_probe_hbm_read(0, 2 << 30, 10)
     res["detail"]["hbm_read_probe_gbs"] = round(rd, 1)
     res["detail"]["step_frac_of_read_probe"] = round(roof["achieved"] / rd, 4)
-    log(f"[bench] probes: FP64 MFMA {probe:.1f} TFLOP/s, HBM read {rd:.0f} GB/s")
+    # the same stream over a buffer of R's size with ordinary loads and
+    # passes alternating in direction, as consecutive fold passes read R:
+    # HBM plus what L2 and the Infinity Cache keep between passes
+    r_bytes = 4 * c.n_t * ((c.n_reco + 3) // 4 * 4)
+    rc_ = nr.nr_probe_read(0, r_bytes, 40, nr.NR_PROBE_CACHED | nr.NR_PROBE_ALTERNATE)
+    res["detail"]["cache_read_probe_gbs"] = round(rc_, 1)
+    res["detail"]["step_frac_of_cache_read_probe"] = round(roof["achieved"] / rc_, 4)
+    log(f"[bench] probes: FP64 MFMA {probe:.1f} TFLOP/s, HBM read {rd:.0f} GB/s, "
+        f"R-sized alternating cached read {rc_:.0f} GB/s")
     # gradient form: 1024 points at the same shapes, -2lnL + 7 derivatives
     # per point through the FP64-MFMA forward and adjoint products
     thg = synth.theta_prior(1024, p["seeds"]["theta"] + 5, f_range=(0.8, 1.2))

@@ -376,6 +376,21 @@ int nr_probe_mfma_f64(int device, int blocks, int iters, double *tflops);
  * Status codes as nr_probe_mfma_f64. */
 int nr_probe_hbm_read(int device, long long bytes, int reps, double *gbs);
 
+/* Flags of nr_probe_read. */
+#define NR_PROBE_CACHED 1    /* ordinary loads, which allocate in L2 and the
+                                Infinity Cache, instead of non-temporal ones */
+#define NR_PROBE_ALTERNATE 2 /* odd passes walk the buffer last to first */
+
+/* Diagnostic: the read rate of the same streaming sum with a choice of load
+ * kind and pass order (`flags`, a combination of the NR_PROBE_ bits above;
+ * 0 is nr_probe_hbm_read).  With both flags over a buffer of the response's
+ * size it reads memory the way consecutive points of the single-point fold
+ * do (a forward pass, then a backward one, each starting on what the last
+ * left in the caches), the rate the fold's bytes per second are compared
+ * with besides the HBM rate.  Arguments, units and status codes as
+ * nr_probe_hbm_read; NR_EINVAL for unknown flag bits. */
+int nr_probe_read(int device, long long bytes, int reps, int flags, double *gbs);
+
 /* Message for the last non-zero status on this thread. */
 const char *nr_last_error(void);
 

@@ -18,6 +18,7 @@ from ._build import LIB as _LIB_PATH
 
 NR_NTHETA = 7
 NR_OK, NR_EINVAL, NR_ESTATE, NR_EHIP, NR_ENOMEM = 0, -1, -2, -3, -4
+NR_PROBE_CACHED, NR_PROBE_ALTERNATE = 1, 2
 
 # Exported symbols of include/nureweight.h.
 EXPORTS = (
@@ -34,6 +35,7 @@ EXPORTS = (
     "nr_mlp_logmu_dev", "nr_mlp_nll_dev", "nr_eval_mu_batched_dev",
     "nr_build_templates", "nr_eval_nll_templates", "nr_eval_mu_templates",
     "nr_eval_nll_templates_dev", "nr_probe_mfma_f64", "nr_probe_hbm_read",
+    "nr_probe_read",
 )
 
 
@@ -143,6 +145,7 @@ def load():
     L.nr_eval_nll_templates_dev.argtypes = [P, P, I, P, P, P]
     L.nr_probe_mfma_f64.argtypes = [I, I, I, pD]
     L.nr_probe_hbm_read.argtypes = [I, C.c_longlong, I, pD]
+    L.nr_probe_read.argtypes = [I, C.c_longlong, I, I, pD]
     for name in EXPORTS:
         fn = getattr(L, name)
         if name not in ("nr_destroy", "nr_stream", "nr_last_error",
@@ -359,6 +362,17 @@ def nr_probe_hbm_read(device=0, nbytes=2 << 30, reps=10):
     rc = load().nr_probe_hbm_read(int(device), int(nbytes), int(reps), _dp(out))
     if rc != 0:
         raise NrError(rc, "nr_probe_hbm_read failed")
+    return float(out[0])
+
+
+def nr_probe_read(device=0, nbytes=2 << 30, reps=10, flags=0):
+    """Read GB/s of the same streaming sum with ordinary loads
+    (NR_PROBE_CACHED) and/or passes alternating in direction
+    (NR_PROBE_ALTERNATE); flags=0 is nr_probe_hbm_read."""
+    out = np.zeros(1)
+    rc = load().nr_probe_read(int(device), int(nbytes), int(reps), int(flags), _dp(out))
+    if rc != 0:
+        raise NrError(rc, "nr_probe_read failed")
     return float(out[0])
 
 

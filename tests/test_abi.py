@@ -47,8 +47,8 @@ def test_binding_has_the_same_names():
 
 
 def test_probe_rejects_bad_arguments_without_a_device():
-    """Argument checks of the matrix-core probe return before any device
-    call (so they run here without a GPU)."""
+    """Argument checks of the matrix-core and read probes return before any
+    device call (so they run here without a GPU)."""
     import numpy as np
     import paper_2607_00488_amd as nr
     lib = nr.load()
@@ -58,3 +58,7 @@ def test_probe_rejects_bad_arguments_without_a_device():
     assert lib.nr_probe_mfma_f64(0, 1, 1, None) == nr.NR_EINVAL
     for nbytes, reps in ((1 << 19, 1), ((1 << 20) + 8, 1), (1 << 20, 0), (1 << 37, 1)):
         assert lib.nr_probe_hbm_read(0, nbytes, reps, nr._dp(out)) == nr.NR_EINVAL
+        assert lib.nr_probe_read(0, nbytes, reps, 3, nr._dp(out)) == nr.NR_EINVAL
+    for flags in (-1, 4, 7):
+        assert lib.nr_probe_read(0, 1 << 20, 1, flags, nr._dp(out)) == nr.NR_EINVAL
+    assert lib.nr_probe_read(0, 1 << 20, 1, 0, None) == nr.NR_EINVAL

@@ -187,3 +187,7 @@ def test_mfma_probe_runs():
     g = nr.nr_probe_hbm_read(0, 256 << 20, 4)
     log(f"[gpu] HBM read probe (256 MiB): {g:.0f} GB/s")
     assert 100.0 < g < 20000.0
+    for flags in (nr.NR_PROBE_CACHED, nr.NR_PROBE_ALTERNATE,
+                  nr.NR_PROBE_CACHED | nr.NR_PROBE_ALTERNATE):
+        g = nr.nr_probe_read(0, (1 << 20) + 16 * 1001, 3, flags)  # ragged tail
+        assert 1.0 < g < 50000.0, flags

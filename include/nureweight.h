@@ -45,7 +45,10 @@
  * results).  A context is not thread-safe, and the evaluations of one
  * context share its device work buffers: work enqueued on different streams
  * must not overlap in time (the synchronous entry points use the context
- * stream and wait for it).
+ * stream and wait for it).  Distinct contexts may be used from different
+ * threads at the same time (not inside one grouped call); the library's
+ * own process-wide state, the grouped GEMM's tuning table and its cache
+ * file, is locked.
  */
 #ifndef NUREWEIGHT_H
 #define NUREWEIGHT_H

@@ -7,11 +7,13 @@
 #include "../../include/nureweight.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -103,8 +105,9 @@ bool finite_all(const double* p, size_t n) {
 using GraphKey = std::tuple<const void*, int, void*, void*, void*, void*>;
 
 // Incremented whenever a context's device buffers may have moved; cached
-// grouped-launch plans built under an older epoch are rebuilt.
-unsigned long g_epoch = 1;
+// grouped-launch plans built under an older epoch are rebuilt.  Atomic:
+// distinct contexts may be driven from different threads.
+std::atomic<unsigned long> g_epoch{1};
 
 // One grouped launch over several analyses: GEMM problem tables, tile lists
 // and the captured graph of the whole batched evaluation.
@@ -704,7 +707,7 @@ int build_plan(const MultiCall& mc, bool grad, int cfg, BatchPlan* pl) {
         pl->n_tiles_a = (int)ta.size();
         pl->grid_a = nr::gemm_grid(nr::kModeAdj, cfg, pl->n_tiles_a);
     }
-    pl->epoch = g_epoch;
+    pl->epoch = g_epoch.load();
     return 0;
 }
 
@@ -763,13 +766,17 @@ int enqueue_plan(const MultiCall& mc, bool grad, BatchPlan* pl, unsigned* ctr,
 // problem (one warm-up and two timed runs each) and keeps the fastest, in
 // memory and in a small JSON file (NR_AUTOTUNE_CACHE, default
 // $HOME/.cache/nureweight/autotune.json).  NR_AUTOTUNE=0 skips tuning; a
-// missing, unreadable or corrupt cache file only means tuning again.
+// missing, unreadable or corrupt cache file only means tuning again.  The
+// table is shared by every context of the process: g_tune_mu guards it and
+// the file (held for lookups and updates, not while a class is timed, so
+// two threads may time the same class once each).
 struct TuneCache {
     bool loaded = false;
     std::map<std::string, int> best;
     std::string path;
 };
 TuneCache g_tune;
+std::mutex g_tune_mu;
 
 std::string tune_path() {
     const char* p = getenv("NR_AUTOTUNE_CACHE");
@@ -853,40 +860,58 @@ int tuned_config(const MultiCall& mc, bool grad, hipStream_t s, int* cfg_out) {
     }
     const char* e = getenv("NR_AUTOTUNE");
     if (e && e[0] == '0') { *cfg_out = 0; return 0; }
-    tune_load();
     const std::string key = shape_class(mc, grad);
-    auto it = g_tune.best.find(key);
-    if (it != g_tune.best.end()) { *cfg_out = it->second; return 0; }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load();
+        auto it = g_tune.best.find(key);
+        if (it != g_tune.best.end()) { *cfg_out = it->second; return 0; }
+    }
     nr_ctx* owner = mc.ctx[0];
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    // events and the trial plan's tables are released on every return
+    struct Trial {
+        hipStream_t st;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        BatchPlan pl;
+        void drop_plan() {
+            if (pl.d_probs_f) (void)hipFree(pl.d_probs_f);
+            if (pl.d_tiles_f) (void)hipFree(pl.d_tiles_f);
+            if (pl.d_probs_a) (void)hipFree(pl.d_probs_a);
+            if (pl.d_tiles_a) (void)hipFree(pl.d_tiles_a);
+            pl = BatchPlan{};
+        }
+        ~Trial() {
+            (void)hipStreamSynchronize(st);  // nothing in flight reads the tables
+            drop_plan();
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+        }
+    } t{s};
+    HIPCHK(hipEventCreate(&t.e0));
+    HIPCHK(hipEventCreate(&t.e1));
     float best_ms = 1e30f;
     int best = 0;
     for (int cfg = 0; cfg < nr::kGemmConfigs; ++cfg) {
-        BatchPlan pl;
-        int rc = build_plan(mc, grad, cfg, &pl);
+        int rc = build_plan(mc, grad, cfg, &t.pl);
         if (rc) return rc;
-        rc = enqueue_plan(mc, grad, &pl, owner->d_gctr, s);  // warm-up
-        if (!rc) {
-            HIPCHK(hipEventRecord(e0, s));
-            for (int r = 0; r < 2 && !rc; ++r) rc = enqueue_plan(mc, grad, &pl, owner->d_gctr, s);
-            HIPCHK(hipEventRecord(e1, s));
-            HIPCHK(hipEventSynchronize(e1));
-        }
+        rc = enqueue_plan(mc, grad, &t.pl, owner->d_gctr, s);  // warm-up
+        if (rc) return rc;
+        HIPCHK(hipEventRecord(t.e0, s));
+        for (int r = 0; r < 2 && !rc; ++r) rc = enqueue_plan(mc, grad, &t.pl, owner->d_gctr, s);
+        HIPCHK(hipEventRecord(t.e1, s));
+        HIPCHK(hipEventSynchronize(t.e1));
+        if (rc) return rc;
         float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (pl.d_probs_f) (void)hipFree(pl.d_probs_f);
-        if (pl.d_tiles_f) (void)hipFree(pl.d_tiles_f);
-        if (pl.d_probs_a) (void)hipFree(pl.d_probs_a);
-        if (pl.d_tiles_a) (void)hipFree(pl.d_tiles_a);
-        if (rc) return rc;
+        HIPCHK(hipEventElapsedTime(&ms, t.e0, t.e1));
+        t.drop_plan();
         if (ms < best_ms) { best_ms = ms; best = cfg; }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    g_tune.best[key] = best;
-    tune_save();
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load();  // the cache path may have changed meanwhile
+        g_tune.best[key] = best;
+        tune_save();
+    }
     *cfg_out = best;
     return 0;
 }

@@ -430,6 +430,41 @@ def gemm_counter_pass():
     log("[bench] GEMM counter pass done: 8 calls of 2 x 1024 x 4096 x 4096 flop")
 
 
+def tmpl_counter_pass():
+    """The template form's evaluation kernels alone, for instruction
+    counters: 65536 points over 4096 observed bins (the per-point cost does
+    not depend on N_T, so a 4096-row response keeps the set-up short), one
+    untimed call of each variant, then 8 likelihood calls and 8 calls with
+    the gradient."""
+    import torch
+    import synth
+    import paper_2607_00488_amd as nr
+    dev = torch.device("cuda:0")
+    src = synth.source_nodes(256)
+    rsp = synth.response_mc(4096, 4096, 1_000_000, seed=2101, keep_counts=False)
+    ctx = nr.Context(0)
+    ctx.set_sources(src, 4096)
+    ctx.set_response(rsp.R, n_sig=1.0e4)
+    b = np.full(4096, 10.0)
+    ctx.set_data(synth.poisson_data(b + 30.0, 2102), b)
+    P = 65536
+    tt = torch.tensor(synth.theta_prior(P, 2103, f_range=(0.8, 1.2)),
+                      dtype=torch.float64, device=dev)
+    nl = torch.empty(P, dtype=torch.float64, device=dev)
+    gr = torch.empty(P, 7, dtype=torch.float64, device=dev)
+    ctx.build_templates()
+    ctx.eval_nll_templates_dev(tt, nl)
+    ctx.eval_nll_templates_dev(tt, nl, gr)
+    torch.cuda.synchronize()
+    for _ in range(8):
+        ctx.eval_nll_templates_dev(tt, nl)
+    for _ in range(8):
+        ctx.eval_nll_templates_dev(tt, nl, gr)
+    torch.cuda.synchronize()
+    ctx.close()
+    log("[bench] template counter pass done: 8 + 8 calls of 65536 points x 4096 bins")
+
+
 def cpu_baseline(p, n_eval, gpu_ctx):
     """The FP64 oracle on the host cores for a bounded sample of points, and
     the GPU's -2lnL on the same inputs for the |Delta| column."""
@@ -491,6 +526,10 @@ def main():
                     help="short run for matrix-core counters: the batched "
                          "likelihood GEMM of 1024 points on a 4096 x 4096 "
                          "dataset (a shape of the 64-dataset scan), 8 calls")
+    ap.add_argument("--tmpl-counter-pass", action="store_true",
+                    help="short run for instruction counters: the template "
+                         "form's evaluation on 65536 points x 4096 bins, "
+                         "8 calls without and 8 with the gradient")
     ap.add_argument("--counter-pass", action="store_true",
                     help="short run for hardware-counter collection: 20 "
                          "single-point evaluations, then 20 plain 256 MiB "
@@ -506,6 +545,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.gemm_counter_pass:
         gemm_counter_pass()
+        return
+    if args.tmpl_counter_pass:
+        tmpl_counter_pass()
         return
     p = build_plain(1)
     ctx, c = p["ctx"], p["cfg"]

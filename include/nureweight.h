@@ -46,9 +46,13 @@
  * context share its device work buffers: work enqueued on different streams
  * must not overlap in time (the synchronous entry points use the context
  * stream and wait for it).  Distinct contexts may be used from different
- * threads at the same time (not inside one grouped call); the library's
- * own process-wide state, the grouped GEMM's tuning table and its cache
- * file, is locked.
+ * threads: every entry point holds one process-wide lock while it does its
+ * host-side work (for a synchronous entry point, until its results are
+ * back), so calls from different threads run one at a time on the host
+ * while their device work may overlap.  The lock exists because a call may
+ * capture a HIP graph on its stream, and the HIP runtime fails an open
+ * capture when another thread issues a default-stream operation; the
+ * caller's own default-stream work in other threads can do the same.
  */
 #ifndef NUREWEIGHT_H
 #define NUREWEIGHT_H

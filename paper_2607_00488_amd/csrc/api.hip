@@ -104,9 +104,29 @@ bool finite_all(const double* p, size_t n) {
 
 using GraphKey = std::tuple<const void*, int, void*, void*, void*, void*>;
 
+}  // namespace
+
+// One process-wide lock around the host side of every entry point (taken
+// again, recursively, when an entry point calls another).  Calls from
+// different threads then run their host work one at a time: a call may open
+// a graph capture on its stream, and the HIP runtime fails a capture when
+// another thread issues a default-stream operation (a synchronous copy, a
+// set) while it is open.  Device work of different calls still overlaps.
+namespace nr {
+std::recursive_mutex& api_mutex() {
+    static std::recursive_mutex m;
+    return m;
+}
+}  // namespace nr
+
+namespace {
+
+struct ApiLock {
+    std::lock_guard<std::recursive_mutex> g{nr::api_mutex()};
+};
+
 // Incremented whenever a context's device buffers may have moved; cached
-// grouped-launch plans built under an older epoch are rebuilt.  Atomic:
-// distinct contexts may be driven from different threads.
+// grouped-launch plans built under an older epoch are rebuilt.
 std::atomic<unsigned long> g_epoch{1};
 
 // One grouped launch over several analyses: GEMM problem tables, tile lists
@@ -1028,6 +1048,7 @@ extern "C" {
 const char* nr_last_error(void) { return g_err.c_str(); }
 
 int nr_create(int device, nr_ctx** out) {
+    const ApiLock api_lock;
     if (!out) return fail(NR_EINVAL, "out is null");
     *out = nullptr;
     int ndev = 0;
@@ -1060,6 +1081,7 @@ int nr_create(int device, nr_ctx** out) {
 }
 
 void nr_destroy(nr_ctx* c) {
+    const ApiLock api_lock;
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
@@ -1090,6 +1112,7 @@ void* nr_stream(nr_ctx* c) { return c ? (void*)c->stream : nullptr; }
 
 int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
                    double t_lo, double t_hi, const nr_physics* phys) {
+    const ApiLock api_lock;
     if (!c || !src || n_src <= 0 || n_t <= 0)
         return fail(NR_EINVAL, "null argument or non-positive size");
     if (!(std::isfinite(t_lo) && std::isfinite(t_hi) && t_hi > t_lo && t_lo >= 0))
@@ -1234,6 +1257,7 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
 
 int nr_set_response(nr_ctx* c, const float* R, int n_t, int n_reco,
                     const double* m, double n_sig) {
+    const ApiLock api_lock;
     if (!c || !R || n_t <= 0 || n_reco <= 0)
         return fail(NR_EINVAL, "null argument or non-positive size");
     if (c->have_src && n_t != c->n_t)
@@ -1290,6 +1314,7 @@ int nr_set_response(nr_ctx* c, const float* R, int n_t, int n_reco,
 
 int nr_set_data(nr_ctx* c, const double* n, const double* b, int n_reco,
                 const double* pull_mean, const double* pull_sigma) {
+    const ApiLock api_lock;
     if (!c || !n || n_reco <= 0) return fail(NR_EINVAL, "null argument or n_reco <= 0");
     if (!b && !c->multi) return fail(NR_EINVAL, "b is null");
     if (c->have_rsp && n_reco != c->n_reco)
@@ -1327,6 +1352,7 @@ int nr_set_data(nr_ctx* c, const double* n, const double* b, int n_reco,
 
 int nr_eval_nll_dev(nr_ctx* c, const double* d_theta, int n_pts, double* d_nll,
                     double* d_grad, void* stream) {
+    const ApiLock api_lock;
     int rc;
     if ((rc = check_ready(c))) return rc;
     if (!d_theta || !d_nll || n_pts <= 0)
@@ -1372,22 +1398,26 @@ static int eval_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
 }
 
 int nr_eval_nll(nr_ctx* c, const double* theta, int n_pts, double* nll) {
+    const ApiLock api_lock;
     if (!nll) return fail(NR_EINVAL, "nll is null");
     return eval_sync(c, theta, n_pts, nll, nullptr, nullptr, nullptr);
 }
 
 int nr_eval_nll_grad(nr_ctx* c, const double* theta, int n_pts, double* nll,
                      double* grad) {
+    const ApiLock api_lock;
     if (!nll || !grad) return fail(NR_EINVAL, "nll or grad is null");
     return eval_sync(c, theta, n_pts, nll, grad, nullptr, nullptr);
 }
 
 int nr_eval_mu(nr_ctx* c, const double* theta, int n_pts, double* mu) {
+    const ApiLock api_lock;
     if (!mu) return fail(NR_EINVAL, "mu is null");
     return eval_sync(c, theta, n_pts, nullptr, nullptr, mu, nullptr);
 }
 
 int nr_set_mc_events(nr_ctx* c, const double* n_events, int n_t) {
+    const ApiLock api_lock;
     if (!c || !n_events || n_t <= 0) return fail(NR_EINVAL, "null argument or n_t <= 0");
     if (int rc = check_single(c)) return rc;
     if (!c->have_rsp) return fail(NR_ESTATE, "nr_set_mc_events needs nr_set_response first");
@@ -1404,6 +1434,7 @@ int nr_set_mc_events(nr_ctx* c, const double* n_events, int n_t) {
 }
 
 int nr_eval_ess(nr_ctx* c, const double* theta, int n_pts, double* ess) {
+    const ApiLock api_lock;
     int rc;
     if (!ess) return fail(NR_EINVAL, "ess is null");
     if ((rc = check_ready(c))) return rc;
@@ -1443,6 +1474,7 @@ int nr_eval_ess(nr_ctx* c, const double* theta, int n_pts, double* ess) {
 int nr_num_theta(nr_ctx* c) { return c ? c->n_theta : NR_EINVAL; }
 
 int nr_set_components(nr_ctx* c, const nr_components* k, int n_reco) {
+    const ApiLock api_lock;
     if (!c || !k || n_reco <= 0) return fail(NR_EINVAL, "null argument or n_reco <= 0");
     if (!c->have_src) return fail(NR_ESTATE, "nr_set_components needs nr_set_sources first");
     const int K = k->n_comp, B = k->n_bkg, n_t = c->n_t, n_src = c->n_src;
@@ -1573,11 +1605,13 @@ int nr_set_components(nr_ctx* c, const nr_components* k, int n_reco) {
 }
 
 int nr_eval_weights(nr_ctx* c, const double* theta, int n_pts, double* w) {
+    const ApiLock api_lock;
     if (!w) return fail(NR_EINVAL, "w is null");
     return eval_sync(c, theta, n_pts, nullptr, nullptr, nullptr, w);
 }
 
 int nr_get_reference(nr_ctx* c, double* s_sm, double* m) {
+    const ApiLock api_lock;
     if (!c) return fail(NR_EINVAL, "null context");
     if (int rc = check_single(c)) return rc;
     if (s_sm) {
@@ -1592,6 +1626,7 @@ int nr_get_reference(nr_ctx* c, double* s_sm, double* m) {
 }
 
 int nr_set_fold_tiling(nr_ctx* c, int rows_per_wg, int use_graph) {
+    const ApiLock api_lock;
     if (!c) return fail(NR_EINVAL, "null context");
     if (use_graph >= 0) c->use_graph = use_graph != 0;
     clear_graphs(c);
@@ -1608,6 +1643,7 @@ int nr_set_fold_tiling(nr_ctx* c, int rows_per_wg, int use_graph) {
 }
 
 int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
+    const ApiLock api_lock;
     if (!c || !avg_ms || iters <= 0) return fail(NR_EINVAL, "bad argument");
     if (stage < 1 || stage > 5) return fail(NR_EINVAL, "stage must be 1 to 5");
     int rc;
@@ -1676,17 +1712,20 @@ int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
 }
 
 int nr_eval_nll_batched(nr_ctx* c, const double* theta, int n_pts, double* nll) {
+    const ApiLock api_lock;
     if (!nll) return fail(NR_EINVAL, "nll is null");
     return batched_sync(c, theta, n_pts, nll, nullptr, nullptr);
 }
 
 int nr_eval_nll_grad_batched(nr_ctx* c, const double* theta, int n_pts,
                              double* nll, double* grad) {
+    const ApiLock api_lock;
     if (!nll || !grad) return fail(NR_EINVAL, "nll or grad is null");
     return batched_sync(c, theta, n_pts, nll, grad, nullptr);
 }
 
 int nr_eval_mu_batched(nr_ctx* c, const double* theta, int n_pts, double* mu) {
+    const ApiLock api_lock;
     if (!mu) return fail(NR_EINVAL, "mu is null");
     return batched_sync(c, theta, n_pts, nullptr, nullptr, mu);
 }
@@ -1695,6 +1734,7 @@ int nr_eval_nll_multi_dev(nr_ctx* const* ctx, int n_ctx,
                           const double* const* d_theta, const int* n_pts,
                           double* const* d_nll, double* const* d_grad,
                           void* stream) {
+    const ApiLock api_lock;
     int rc;
     if ((rc = check_multi(ctx, n_ctx, n_pts))) return rc;
     if (!d_theta || !d_nll) return fail(NR_EINVAL, "null theta or nll array");
@@ -1715,6 +1755,7 @@ int nr_eval_nll_multi_dev(nr_ctx* const* ctx, int n_ctx,
 
 int nr_eval_nll_multi(nr_ctx* const* ctx, int n_ctx, const double* const* theta,
                       const int* n_pts, double* const* nll) {
+    const ApiLock api_lock;
     int rc;
     if ((rc = check_multi(ctx, n_ctx, n_pts))) return rc;
     if (!theta || !nll) return fail(NR_EINVAL, "null theta or nll array");
@@ -1902,6 +1943,7 @@ int mlp_input(nr_mlp* q, const double* th, int B, hipStream_t s) {
 extern "C" {
 
 int nr_mlp_create(int device, int hidden, int n_out, nr_mlp** out) {
+    const ApiLock api_lock;
     if (!out || hidden <= 0 || hidden % 8 || n_out <= 0 || n_out % 8)
         return fail(NR_EINVAL, "hidden and n_out must be positive multiples of 8");
     *out = nullptr;
@@ -1942,6 +1984,7 @@ int nr_mlp_create(int device, int hidden, int n_out, nr_mlp** out) {
 }
 
 void nr_mlp_destroy(nr_mlp* q) {
+    const ApiLock api_lock;
     if (!q) return;
     (void)hipSetDevice(q->device);
     (void)hipStreamSynchronize(q->stream);
@@ -1959,6 +2002,7 @@ void nr_mlp_destroy(nr_mlp* q) {
 long nr_mlp_num_params(nr_mlp* q) { return q ? q->n_params : -1; }
 
 int nr_mlp_set_params(nr_mlp* q, const float* params, long n) {
+    const ApiLock api_lock;
     if (!q || !params || n != q->n_params) return fail(NR_EINVAL, "expected %ld parameters", q ? q->n_params : -1L);
     int rc;
     if ((rc = dalloc(&q->g, q->n_params))) return rc;
@@ -1974,6 +2018,7 @@ int nr_mlp_set_params(nr_mlp* q, const float* params, long n) {
 }
 
 int nr_mlp_get_params(nr_mlp* q, float* params, long n) {
+    const ApiLock api_lock;
     if (!q || !params || n != q->n_params) return fail(NR_EINVAL, "expected %ld parameters", q ? q->n_params : -1L);
     HIPCHK(hipSetDevice(q->device));
     HIPCHK(hipStreamSynchronize(q->stream));
@@ -1982,6 +2027,7 @@ int nr_mlp_get_params(nr_mlp* q, float* params, long n) {
 }
 
 int nr_mlp_get_grads(nr_mlp* q, float* grads, long n) {
+    const ApiLock api_lock;
     if (!q || !grads || n != q->n_params) return fail(NR_EINVAL, "expected %ld values", q ? q->n_params : -1L);
     HIPCHK(hipSetDevice(q->device));
     HIPCHK(hipDeviceSynchronize());
@@ -1990,6 +2036,7 @@ int nr_mlp_get_grads(nr_mlp* q, float* grads, long n) {
 }
 
 int nr_mlp_set_box(nr_mlp* q, const double* lo, const double* hi) {
+    const ApiLock api_lock;
     if (!q || !lo || !hi) return fail(NR_EINVAL, "null argument");
     for (int i = 0; i < NR_NTHETA; ++i)
         if (!(std::isfinite(lo[i]) && std::isfinite(hi[i]) && hi[i] > lo[i]))
@@ -2002,6 +2049,7 @@ int nr_mlp_set_box(nr_mlp* q, const double* lo, const double* hi) {
 }
 
 int nr_mlp_set_output_norm(nr_mlp* q, const float* mean, const float* stdv) {
+    const ApiLock api_lock;
     if (!q || !mean || !stdv) return fail(NR_EINVAL, "null argument");
     for (int j = 0; j < q->n_out; ++j)
         if (!(std::isfinite(mean[j]) && stdv[j] > 0)) return fail(NR_EINVAL, "bad output norm at %d", j);
@@ -2012,6 +2060,7 @@ int nr_mlp_set_output_norm(nr_mlp* q, const float* mean, const float* stdv) {
 }
 
 int nr_mlp_targets_dev(nr_mlp* q, const double* d_mu, int P, float* d_t, void* stream) {
+    const ApiLock api_lock;
     if (!q || !d_mu || !d_t || P <= 0) return fail(NR_EINVAL, "bad argument");
     HIPCHK(hipSetDevice(q->device));
     nr::TargetArgs a{d_mu, P, q->n_out, q->mean, q->stdv, d_t};
@@ -2024,6 +2073,7 @@ int nr_mlp_targets_dev(nr_mlp* q, const double* d_mu, int P, float* d_t, void* s
 
 int nr_mlp_train_step_dev(nr_mlp* q, const double* d_theta, const float* d_t,
                           int B, float lr, double* loss, void* stream) {
+    const ApiLock api_lock;
     if (!q || !d_theta || !d_t || B <= 0 || B % 8)
         return fail(NR_EINVAL, "batch must be a positive multiple of 8");
     HIPCHK(hipSetDevice(q->device));
@@ -2100,6 +2150,7 @@ int nr_mlp_train_step_dev(nr_mlp* q, const double* d_theta, const float* d_t,
 
 int nr_mlp_logmu_dev(nr_mlp* q, const double* d_theta, int B, float* d_logmu,
                      void* stream) {
+    const ApiLock api_lock;
     if (!q || !d_theta || !d_logmu || B <= 0 || B % 8)
         return fail(NR_EINVAL, "batch must be a positive multiple of 8");
     HIPCHK(hipSetDevice(q->device));
@@ -2122,6 +2173,7 @@ int nr_mlp_logmu_dev(nr_mlp* q, const double* d_theta, int B, float* d_logmu,
 
 int nr_mlp_nll_dev(nr_mlp* q, nr_ctx* c, const double* d_theta, int B,
                    double* d_nll, int* d_outside, void* stream) {
+    const ApiLock api_lock;
     int rc;
     if (!q || !d_theta || !d_nll || B <= 0 || B % 8)
         return fail(NR_EINVAL, "batch must be a positive multiple of 8");
@@ -2163,6 +2215,7 @@ int nr_mlp_nll_dev(nr_mlp* q, nr_ctx* c, const double* d_theta, int B,
 
 int nr_eval_mu_batched_dev(nr_ctx* c, const double* d_theta, int n_pts,
                            double* d_mu, void* stream) {
+    const ApiLock api_lock;
     int rc;
     if ((rc = check_ready(c))) return rc;
     if ((rc = check_single(c))) return rc;
@@ -2415,6 +2468,7 @@ static int enqueue_tmpl(nr_ctx* c, const double* d_th, int n_pts, double* d_nll,
 }
 
 int nr_build_templates(nr_ctx* c) {
+    const ApiLock api_lock;
     int rc;
     if ((rc = check_ready(c))) return rc;
     if ((rc = check_tmpl_form(c))) return rc;
@@ -2424,6 +2478,7 @@ int nr_build_templates(nr_ctx* c) {
 
 int nr_eval_nll_templates_dev(nr_ctx* c, const double* d_theta, int n_pts,
                               double* d_nll, double* d_grad, void* stream) {
+    const ApiLock api_lock;
     int rc;
     if ((rc = check_ready(c))) return rc;
     if (!d_theta || !d_nll || n_pts <= 0)
@@ -2464,11 +2519,13 @@ static int tmpl_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
 
 int nr_eval_nll_templates(nr_ctx* c, const double* theta, int n_pts, double* nll,
                           double* grad) {
+    const ApiLock api_lock;
     if (!nll) return fail(NR_EINVAL, "nll is null");
     return tmpl_sync(c, theta, n_pts, nll, grad, nullptr);
 }
 
 int nr_eval_mu_templates(nr_ctx* c, const double* theta, int n_pts, double* mu) {
+    const ApiLock api_lock;
     if (!mu) return fail(NR_EINVAL, "mu is null");
     return tmpl_sync(c, theta, n_pts, nullptr, nullptr, mu);
 }

@@ -11,6 +11,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
+namespace nr {
+std::recursive_mutex& api_mutex();  // the library's entry-point lock
+}
+
 namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -125,12 +131,14 @@ int read_rate(int device, long long bytes, int reps, bool nt, bool alternate, do
 }  // namespace
 
 extern "C" int nr_probe_hbm_read(int device, long long bytes, int reps, double* gbs) {
+    const std::lock_guard<std::recursive_mutex> lk(nr::api_mutex());
     if (!gbs || bytes < (1 << 20) || bytes > (1LL << 36) || (bytes & 15) || reps <= 0)
         return NR_EINVAL;
     return read_rate(device, bytes, reps, true, false, gbs);
 }
 
 extern "C" int nr_probe_read(int device, long long bytes, int reps, int flags, double* gbs) {
+    const std::lock_guard<std::recursive_mutex> lk(nr::api_mutex());
     if (!gbs || bytes < (1 << 20) || bytes > (1LL << 36) || (bytes & 15) || reps <= 0 ||
         (flags & ~(NR_PROBE_CACHED | NR_PROBE_ALTERNATE)))
         return NR_EINVAL;
@@ -139,6 +147,7 @@ extern "C" int nr_probe_read(int device, long long bytes, int reps, int flags, d
 }
 
 extern "C" int nr_probe_mfma_f64(int device, int blocks, int iters, double* tflops) {
+    const std::lock_guard<std::recursive_mutex> lk(nr::api_mutex());
     if (!tflops || blocks <= 0 || blocks > (1 << 16) || iters <= 0) return NR_EINVAL;
     if (hipSetDevice(device) != hipSuccess) return NR_EHIP;
     double* d = nullptr;

@@ -62,3 +62,15 @@ def test_probe_rejects_bad_arguments_without_a_device():
     for flags in (-1, 4, 7):
         assert lib.nr_probe_read(0, 1 << 20, 1, flags, nr._dp(out)) == nr.NR_EINVAL
     assert lib.nr_probe_read(0, 1 << 20, 1, 0, None) == nr.NR_EINVAL
+
+
+def test_header_constants_match_the_binding():
+    """Every integer #define of the header (status codes, parameter counts,
+    probe flags) has the same value in the Python binding."""
+    import paper_2607_00488_amd as nr
+    text = open(os.path.join(ROOT, "include", "nureweight.h")).read()
+    found = dict(re.findall(r"#define\s+(NR_[A-Z0-9_]+)\s+\(?(-?\d+)\)?", text))
+    assert {"NR_OK", "NR_EINVAL", "NR_PROBE_CACHED", "NR_PROBE_ALTERNATE"} <= set(found)
+    for name, value in found.items():
+        assert hasattr(nr, name), name
+        assert getattr(nr, name) == int(value), (name, getattr(nr, name), value)

@@ -706,17 +706,27 @@ def main():
         f"interval {sc['templates']['interval_90']}")
     if not args.no_batched:
         ctxs, ths, flops = build_batched()
-        dt2, _, _ = time_batched(ctxs, ths, reps=2)
+        dt2, nls, _ = time_batched(ctxs, ths, reps=2)
         npts = sum(len(t) for t in ths)
+        # agreement with the single-point path: the first and last point of
+        # each of the 16 shape classes (datasets 0-15)
+        dscan = 0.0
+        for d in range(min(16, len(ctxs))):
+            k = [0, len(ths[d]) - 1]
+            pl = ctxs[d].eval_nll(ths[d][k])
+            dscan = max(dscan, float(np.max(np.abs(pl - nls[d][k]))))
         forms["batched_scan_64_datasets"] = dict(
             evals_per_s=round(npts / dt2, 1), points=npts,
             ms=round(dt2 * 1e3, 3), flop=flops,
             tflops=round(flops / dt2 / 1e12, 2), peak_tflops=78.6,
             frac_of_probe=round(flops / dt2 / 1e12 / probe, 3),
+            max_abs_dnll_vs_plain=dscan,
+            checked="first and last point of each of the 16 shape classes "
+                    "against the single-point path",
             what="64 datasets, N_T 2048-16384, N_reco 512-4096, one grouped "
                  "persistent FP64-MFMA launch per scan (graph replay)")
         log(f"[bench] batched scan: {npts / dt2:.0f} evals/s, "
-            f"{flops / dt2 / 1e12:.1f} TFLOP/s")
+            f"{flops / dt2 / 1e12:.1f} TFLOP/s, max |d| vs plain {dscan:.2e}")
         for cx in ctxs:
             cx.close()
     if not args.no_surrogate:

@@ -341,6 +341,14 @@ double or_nll(const or_ctx *c, const double *th)
     return r;
 }
 
+/* d(-2lnL)/d mu_j from Eq. (logL): the bin term is 2 (mu_j - n_j ln mu_j), so
+ * the derivative is 2 (1 - n_j / mu_j); an empty bin (n_j = 0) contributes
+ * 2 mu_j, whose derivative is 2 whatever mu_j is (also at mu_j = 0). */
+static double dnll_dmu(double n, double mu)
+{
+    return n > 0.0 ? 2.0 * (1.0 - n / mu) : 2.0;
+}
+
 /* Analytic gradient of Eq. (logL): chain rule through mu_j (Eq. mu_total),
  * the fold, the weights and the spectrum derivatives. */
 double or_nll_grad(const or_ctx *c, const double *th, double *grad)
@@ -374,12 +382,12 @@ double or_nll_grad(const or_ctx *c, const double *th, double *grad)
         for (int l = 0; l < nt; ++l) col[l] = dw[(size_t)i * nt + l];
         fold(c, m, col, dmu);
         double g = 0.0;
-        for (int j = 0; j < nr; ++j) g += 2.0 * (1.0 - c->n[j] / mu[j]) * dmu[j];
+        for (int j = 0; j < nr; ++j) g += dnll_dmu(c->n[j], mu[j]) * dmu[j];
         grad[i] = g;
     }
     {
         double g = 0.0;
-        for (int j = 0; j < nr; ++j) g += 2.0 * (1.0 - c->n[j] / mu[j]) * c->b[j];
+        for (int j = 0; j < nr; ++j) g += dnll_dmu(c->n[j], mu[j]) * c->b[j];
         grad[6] = g;
     }
     for (int i = 0; i < OR_NTH; ++i)

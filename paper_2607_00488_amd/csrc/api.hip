@@ -1373,9 +1373,18 @@ static int eval_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
     if ((grad || w) && (rc = check_single(c))) return rc;
     if ((rc = check_theta(theta, n_pts, c->n_theta))) return rc;
     if ((rc = set_device(c))) return rc;
-    if ((rc = ensure_stage(c, n_pts, mu ? (size_t)n_pts * c->n_reco : 0,
-                           w ? (size_t)n_pts * c->n_t : 0)))
-        return rc;
+    const size_t mu_elems = mu ? (size_t)n_pts * c->n_reco : 0;
+    const size_t w_elems = w ? (size_t)n_pts * c->n_rows : 0;
+    if ((rc = ensure_stage(c, n_pts, mu_elems, w_elems))) return rc;
+    // every staged copy and every per-point offset the launches form
+    // (theta, -2lnL, gradient, spectra, weights) lies inside the buffer
+    // ensure_stage sized for it
+    if ((size_t)n_pts > c->cap_pts || c->n_theta > nr::kMaxTheta ||
+        mu_elems > c->cap_mu || w_elems > c->cap_w ||
+        (mu && !c->d_mu) || (w && !c->d_w))
+        return fail(NR_EHIP, "staging buffers too small for %d points "
+                    "(capacity %zu points, %zu spectrum and %zu weight values)",
+                    n_pts, c->cap_pts, c->cap_mu, c->cap_w);
     HIPCHK(hipMemcpyAsync(c->d_th, theta, sizeof(double) * n_pts * c->n_theta,
                           hipMemcpyHostToDevice, c->stream));
     rc = run_points(c, c->d_th, n_pts, c->d_out, grad ? c->d_grad : nullptr,

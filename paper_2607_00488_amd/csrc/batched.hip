@@ -307,7 +307,8 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
                         dsum += d;
                         if (pr.mu) *gmem(pr.mu + (size_t)p * pr.N + col) = mu;
                         if (pr.aout) {
-                            const double aj = 2.0 * (1.0 - nj / mu);
+                            // an empty bin's term is 2 mu_j: derivative 2
+                            const double aj = nj > 0.0 ? 2.0 * (1.0 - nj / mu) : 2.0;
                             *gmem(pr.aout + (size_t)col * pr.lda_out + p) = aj;
                             gsum += aj * bj_;
                         }

@@ -322,7 +322,8 @@ __device__ void finish_role(const FoldArgs& a, int cc, double* smem) {
             dev = mu > 0.0 ? (mu - nj + nj * log(nj / mu)) : INFINITY;
         else
             dev = mu;
-        const double aj = 2.0 * (1.0 - nj / mu);
+        // an empty bin's term is 2 mu_j: its derivative is 2 at any mu_j
+        const double aj = nj > 0.0 ? 2.0 * (1.0 - nj / mu) : 2.0;
         if (a.out_a) a.out_a[col] = aj;
         gb = aj * bj;
     } else if (col < a.ldr && a.out_a) {

@@ -1,6 +1,7 @@
-"""Parity of the batched (FP32-MFMA GEMM) path with the FP64 oracle and with
+"""Parity of the batched (FP64-MFMA GEMM) path with the FP64 oracle and with
 the single-point path: one analysis, several analyses of uneven binning in
-one grouped launch, the batched gradient, and graph replays."""
+one grouped launch (also at the largest shapes of the 64-dataset scan), the
+batched gradient, and graph replays."""
 import sys
 
 import numpy as np
@@ -126,6 +127,65 @@ def test_grouped_graph_replay_and_grad(multi):
             assert abs(ref[d][i] - v) <= 1e-3
             scale = np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())
             assert np.all(np.abs(g[i] - rg) <= 1e-4 * scale + 1e-6), (d, i)
+
+
+# Shapes of the 64-dataset scan (N_T in {2048..16384}, N_reco in
+# {512..4096}, 1e6 MC events, N_E = 256, up to 4096 points per dataset) in
+# one grouped launch beside small ragged analyses: n_t, n_reco, n_pts, grid
+SCAN_SHAPES = [(16384, 4096, 1024, True), (2048, 4096, 512, True),
+               (8192, 1024, 4096, True), (300, 77, 131, False),
+               (64, 1, 3, False)]
+
+
+def test_grouped_scan_shapes():
+    import torch
+    import paper_2607_00488_amd as nr
+    probs, ctxs, ths = [], [], []
+    for d, (n_t, n_reco, P, grid) in enumerate(SCAN_SHAPES):
+        log(f"[gpu] scan-shape dataset {d}: {n_t} x {n_reco}, {P} points")
+        p = inputs(n_t, n_reco, 256 if grid else 32, 10 ** 6, 2000 + d, 4000 + d)
+        probs.append(p)
+        ctxs.append(gpu_context(p))
+        ths.append(synth.theta_grid_scan(P, 6000 + d) if grid
+                   else synth.theta_prior(P, 6000 + d))
+    dev = torch.device("cuda:0")
+    tt = [torch.tensor(t, dtype=torch.float64, device=dev) for t in ths]
+    nl = [torch.empty(len(t), dtype=torch.float64, device=dev) for t in ths]
+    gr = [torch.empty(len(t), 7, dtype=torch.float64, device=dev) for t in ths]
+    s = torch.cuda.Stream(device=dev)
+    log("[gpu] grouped launch over the scan shapes (likelihood and gradient)")
+    nr.eval_nll_multi_dev(ctxs, tt, nl, gr, stream=s)
+    s.synchronize()
+    outs = nr.eval_nll_multi(ctxs, ths)
+    worst = worst_g = worst_mu = 0.0
+    for d, p in enumerate(probs):
+        o = p["oracle"]
+        th, nll_d, g_d = ths[d], nl[d].cpu().numpy(), gr[d].cpu().numpy()
+        assert np.array_equal(nll_d, outs[d]), d
+        P = len(th)
+        for i in sorted({0, P // 3, P - 1}):
+            v, rg = o.nll_grad(th[i])
+            assert abs(nll_d[i] - v) <= 1e-3, (d, i, nll_d[i], v)
+            scale = np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())
+            assert np.all(np.abs(g_d[i] - rg) <= 1e-4 * scale + 1e-6), (d, i)
+            worst = max(worst, abs(nll_d[i] - v))
+            worst_g = max(worst_g, float(np.max(np.abs(g_d[i] - rg) / scale)))
+        # the same points through the single-dataset launch, and spectra
+        k = [0, P - 1]
+        single = ctxs[d].eval_nll_batched(th[k])
+        assert np.max(np.abs(single - nll_d[k])) <= 1e-9 * np.abs(single).max()
+        mu = ctxs[d].eval_mu_batched(th[k])
+        for r, i in enumerate(k):
+            ref = o.mu(th[i])
+            tol = 1e-5 * np.abs(ref) + 1e-9 * np.abs(ref).max()
+            ok = np.abs(mu[r] - ref) <= tol
+            assert ok.all(), (d, i, int(np.argmin(ok)))
+            worst_mu = max(worst_mu, float(np.max(np.abs(mu[r] - ref) /
+                                                  np.maximum(np.abs(ref), 1e-300))))
+    for c in ctxs:
+        c.close()
+    log(f"[gpu] scan shapes: max |d(-2lnL)| {worst:.2e}, max rel d grad "
+        f"{worst_g:.2e}, max rel d mu {worst_mu:.2e}")
 
 
 @pytest.mark.parametrize("cfg", [str(c) for c in range(4)])

@@ -97,6 +97,34 @@ def test_plain_nll_paper_scale_sampled(cfg1):
         f"{len(range(0, len(th), 4))} sampled points")
 
 
+def test_plain_mu_paper_scale(cfg1):
+    """Expected spectra of the single-point path at the paper-scale shapes,
+    bin by bin against the oracle (Sec. III.B-C, Eqs. (fNp_reweight),
+    (mu_total)).  On a context of its own whose first evaluation is the
+    spectrum of one point, then one point per call (the graph captured by
+    the first call is replayed): the call pattern the benchmark's set-up
+    runs on every 16384 x 4096 context."""
+    p, _ = cfg1
+    o = p["oracle"]
+    ctx = gpu_context(p)
+    th = np.vstack([synth.theta_sm()[None], synth.theta_corners()[[0, 31]],
+                    synth.theta_prior(3, 3008, f_range=(0.8, 1.2))])
+    worst = 0.0
+    try:
+        for i in range(len(th)):
+            log(f"[gpu] paper scale plain mu, point {i}")
+            mu = ctx.eval_mu(th[i])[0]
+            ref = o.mu(th[i])
+            tol = 1e-5 * np.abs(ref) + 1e-9 * np.abs(ref).max()
+            ok = np.abs(mu - ref) <= tol
+            assert ok.all(), (i, int(np.argmin(ok)), mu[~ok][:4], ref[~ok][:4])
+            worst = max(worst, float(np.max(np.abs(mu - ref) /
+                                            np.maximum(np.abs(ref), 1e-300))))
+    finally:
+        ctx.close()
+    log(f"[gpu] paper scale plain mu: max rel diff {worst:.2e} over {len(th)} points")
+
+
 def test_batched_mu_paper_scale(cfg1):
     """Expected spectra at the paper-scale shapes through the batched
     method, bin by bin against the oracle."""

@@ -35,7 +35,7 @@ def test_host_code_under_asan(tmp_path):
                     f"-Wl,-rpath,{os.path.dirname(rt[0])}", "-lm", "-o", exe], check=True)
     fin = str(tmp_path / "in.bin")
     write_problem(fin, inputs(333, 77, 37, 200_000, 91, 92), parity_thetas(0, 48))
-    print("[gpu] host ASan stress run (333 x 77, 81 points)", flush=True)
+    print("[gpu] host ASan stress run (333 x 77, 81 points, no single-point spectra)", flush=True)
     # the HIP runtime's own allocations outlive the process, so no leak check
     env = dict(os.environ, ASAN_OPTIONS="verify_asan_link_order=0:detect_leaks=0")
     r = subprocess.run([exe, fin], capture_output=True, text=True, timeout=240, env=env)

@@ -279,6 +279,46 @@ def test_nll_brute_force():
     assert o.nll(th(fb=-1.0)) == math.inf
 
 
+def test_gradient_with_empty_bin():
+    """Eq. (logL) at a bin with n_j = 0 is the term 2 mu_j, whose derivative
+    is 2 also where mu_j = 0 (an empty response column with no background):
+    the analytic gradient stays finite there and equals central differences
+    of -2lnL, on the 4x3 problem above widened by such a column."""
+    o = oracle.Oracle()
+    o.set_sources([dict(kind=0, E=[0.862], weight=[1.0], p_ee=[0.5],
+                        group=0),
+                   dict(kind=0, E=[1.44], weight=[0.3], p_ee=[0.45],
+                        group=1)], 4, 0.0, 1.6)
+    R = np.array([[0.5, 0.25, 0.125, 0.0], [0.0, 0.75, 0.25, 0.0],
+                  [0.25, 0.25, 0.5, 0.0], [1.0, 0.0, 0.0, 0.0]],
+                 dtype=np.float32)
+    m = np.array([3.0, 5.0, 7.0, 11.0])
+    o.set_response(R, m=m)
+    n = np.array([0.0, 7.0, 3.5, 0.0])
+    b = np.array([1.0, 2.0, 0.5, 0.0])
+    o.set_data(n, b, pull_mean=[0, 0, 0, 0, 0, 1, 1],
+               pull_sigma=[0, 0, 0, 0, 0, 0.1, 0.2])
+    t = th(eLL=0.1, eRR=-0.2, tLL=0.3, tRR=0.05, m2=3.0, f8=1.1, fb=0.9)
+    assert o.mu(t)[3] == 0.0
+    v, g = o.nll_grad(t)
+    assert np.all(np.isfinite(g)) and v == pytest.approx(o.nll(t), rel=1e-14)
+    h = 1e-3
+    for i in range(7):
+        def f(s):
+            tt = t.copy()
+            tt[i] += s * h
+            return o.nll(tt)
+        fd = (8 * (f(1) - f(-1)) - (f(2) - f(-2))) / (12 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-8, abs=1e-9), i
+    # the empty bin's term is 2 mu_3 = 0 whatever theta is, so f_bkg's
+    # derivative is the sum over the other bins of 2 (1 - n_j/mu_j) b_j plus
+    # the pull, written out by hand
+    mu = o.mu(t)
+    ref = sum((2.0 if n[j] == 0 else 2 * (1 - n[j] / mu[j])) * b[j]
+              for j in range(3)) + 2 * (t[6] - 1) / 0.2 ** 2
+    assert g[6] == pytest.approx(ref, rel=1e-13)
+
+
 def test_polynomial_structure(small):
     """S_theta is exactly quadratic in each eps, linear in m2 and f_8B;
     mu is linear in f_bkg."""

@@ -97,7 +97,7 @@ int nr_create(int device, nr_ctx **out);
 void nr_destroy(nr_ctx *ctx);
 
 /* Sources and the recoil grid: n_t bins on [t_lo, t_hi], bin l represented
- * by its centre (Sec. V.A, the single representative energy per bin).
+ * by its centre (Sec. VI.A, the single representative energy per bin).
  * Computes the SM reference S_SM(T_l) on the device (Eq. (fT) at theta_SM,
  * Sec. III.A last paragraph) and every theta-independent table. */
 int nr_set_sources(nr_ctx *ctx, const nr_source *src, int n_src, int n_t,
@@ -240,7 +240,7 @@ int nr_set_mc_events(nr_ctx *ctx, const double *n_events, int n_t);
  * bin, ESS_j = (sum_l N_lj w_l)^2 / sum_l N_lj w_l^2 (0 where no weighted
  * event lands), with the weights w_l of the single-point path: how many
  * unweighted events the reweighted prediction of bin j is worth (the
- * reweighting's statistical support, Sec. V.A).  ESS_j = sum_l N_lj at
+ * reweighting's statistical support, Sec. VI.A).  ESS_j = sum_l N_lj at
  * theta_SM.  ess: [n_pts][n_reco] host.  NR_ESTATE before
  * nr_set_mc_events.  Synchronous. */
 int nr_eval_ess(nr_ctx *ctx, const double *theta, int n_pts, double *ess);
@@ -370,7 +370,7 @@ int nr_eval_nll_templates_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
 /* Diagnostic: the FP64 matrix-core rate the device sustains, from a stream
  * of independent v_mfma_f64_16x16x4_f64 on register operands (8 chains per
  * wave, `blocks` work-groups of 4 waves, `iters` trips of 16 rounds over
- * the chains; no memory traffic while timed).  *tflops receives the rate; the batched GEMM (Sec. III.D's
+ * the chains; no memory traffic while timed).  *tflops receives the rate; the batched GEMM (Sec. III.B's
  * fold as a matrix product) is compared with it.  Returns NR_EINVAL for
  * bad arguments (blocks in 1..65536), NR_EHIP / NR_ENOMEM on device
  * errors; it does not set the nr_last_error message. */

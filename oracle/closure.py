@@ -1,5 +1,5 @@
 """Closure of the bin-level reweighting against a direct continuum fold
-(Sec. V.A of the paper; test infrastructure only).
+(Sec. VI.A of the paper; test infrastructure only).
 
 A single 7Be line, an analytic scintillator response (light yield Y
 photoelectrons per MeV, a quenching non-linearity that lowers the yield at

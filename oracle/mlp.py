@@ -63,8 +63,12 @@ def forward(params, theta, lo, hi, hidden, n_out, bf16=True):
     return y, acts, zs
 
 
-def mse_grad(params, theta, targets, lo, hi, hidden, n_out, bf16=True):
-    """Loss mean((y - t)^2) and its gradient w.r.t. the flat parameters."""
+def mse_grad(params, theta, targets, lo, hi, hidden, n_out, bf16=True,
+             magnitude=False):
+    """Loss mean((y - t)^2) and its gradient w.r.t. the flat parameters.
+    With ``magnitude`` also the sum of the absolute values of the terms
+    that make up each gradient element, sum_b |dL/dz_b| |a_b|, the scale
+    against which a device's rounding of those terms is bounded."""
     r = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     layers = unpack(params, hidden, n_out)
     y, acts, zs = forward(params, theta, lo, hi, hidden, n_out, bf16)
@@ -72,14 +76,20 @@ def mse_grad(params, theta, targets, lo, hi, hidden, n_out, bf16=True):
     res = y - targets
     loss = float(np.mean(res ** 2))
     delta = r(2.0 * res / (B * n_out))   # dL/dy, stored in bfloat16
-    grads = [None] * 4
+    grads, mags = [None] * 4, [None] * 4
     for li in range(3, -1, -1):
         w, kin = layers[li]
         g = np.zeros_like(w)
         g[:, :kin + 1] = delta.T @ acts[li]
         grads[li] = g
+        if magnitude:
+            a = np.zeros_like(w)
+            a[:, :kin + 1] = np.abs(delta).T @ np.abs(acts[li])
+            mags[li] = a
         if li > 0:
             W = r(w[:, :kin])
             delta = r((delta @ W) * dsilu(zs[li - 1]))
     flat = np.concatenate([g.ravel() for g in grads])
+    if magnitude:
+        return loss, flat, np.concatenate([a.ravel() for a in mags])
     return loss, flat

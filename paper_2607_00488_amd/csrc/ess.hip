@@ -1,7 +1,7 @@
 // Effective sample size of the reweighted Monte Carlo per observed bin,
 // ESS_j = (sum_l N_lj w_l)^2 / sum_l N_lj w_l^2 with N_lj = R_lj n_l the MC
 // events of true recoil bin l seen in bin j (n_l events generated in row l).
-// A diagnostic of where reweighting runs short of MC support (Sec. V.A:
+// A diagnostic of where reweighting runs short of MC support (Sec. VI.A:
 // large weights where the SM spectrum is small, at low recoil energy for a
 // magnetic moment).  One streaming pass over R accumulates both sums.
 #include "common.h"

@@ -1,5 +1,5 @@
 """Profile-likelihood scans with injected signals (the paper's Asimov
-demonstration, Sec. V.B): a parameter of interest is stepped over a grid,
+demonstration, Sec. VI.B): a parameter of interest is stepped over a grid,
 the nuisance parameters are minimised at every grid value by the batched
 L-BFGS driver (all grid values advance together, one batched likelihood and
 gradient call per line-search trial), and the profile Delta(-2lnL) is read

@@ -8,7 +8,7 @@ Everything here is an *input* to the method:
 * the detector response R_cond[T, E_reco], histogrammed from a seeded
   Monte Carlo of mono-energetic recoil electrons whose true kinetic energy
   is drawn flat in T (the "flatter recoil spectrum" sampling the paper
-  recommends for low-recoil support, Sec. V.A last paragraph), with a
+  recommends for low-recoil support, Sec. VI.A last paragraph), with a
   Birks-like quench and Gaussian photo-statistics smearing;
 * Poisson data drawn from an expectation the *caller* provides;
 * parameter-point lists.

@@ -1,4 +1,4 @@
-"""The paper's closure test of the bin-level reweighting (Sec. V.A): the
+"""The paper's closure test of the bin-level reweighting (Sec. VI.A): the
 oracle's cross sections and the reweighting rule against a direct
 continuum fold, pinned to the values the paper prints."""
 import json

@@ -1,4 +1,4 @@
-"""The HIP single-point path on the paper's closure problem (Sec. V.A):
+"""The HIP single-point path on the paper's closure problem (Sec. VI.A):
 fed the binned SM response of a 7Be line, it must reproduce the oracle's
 reweighted prediction, and therefore close against the direct continuum
 fold as the paper reports."""

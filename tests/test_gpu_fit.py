@@ -25,7 +25,7 @@ def log(msg):
 @pytest.fixture(scope="module")
 def asimov():
     """Config-0 analysis with Asimov data injected at eps_eL = 0.05,
-    mu_nu = 3e-11 mu_B (the paper's demonstration values, Sec. V.B)."""
+    mu_nu = 3e-11 mu_B (the paper's demonstration values, Sec. VI.B)."""
     p = config_inputs(0)
     th_inj = synth.theta_sm().copy()
     th_inj[0] = 0.05

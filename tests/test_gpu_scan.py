@@ -1,4 +1,4 @@
-"""Injection-recovery scans (the paper's Asimov demonstration, Sec. V.B):
+"""Injection-recovery scans (the paper's Asimov demonstration, Sec. VI.B):
 Asimov data with eps_eL = 0.05, or mu_nu = 3e-11 mu_B (m2 = 9), injected;
 the parameter is scanned with the 8B and background normalisations
 profiled by the batched L-BFGS driver, and the profile is checked against an

@@ -47,22 +47,40 @@ def test_backward_kernels_match_reference(torch_dev, B, N):
     tgt = torch.tensor(tg, device=dev)
     loss = nr_mlp_train_step_dev(s.h, tt.data_ptr(), tgt.data_ptr(), B, 0.0, True)
     got = s.grads().astype(np.float64)
-    rl, rg = ref.mse_grad(params.astype(np.float64), th, tg.astype(np.float64),
-                          lo, hi, H, N, bf16=True)
-    assert loss == pytest.approx(rl, rel=2e-3)
-    err = np.linalg.norm(got - rg) / np.linalg.norm(rg)
-    log(f"[gpu] mlp gradient rel L2 error vs reference {err:.2e}")
-    assert err < 5e-3
-    # layer by layer
-    o = 0
-    for rows, kp, _ in [(H, 32, 7), (H, H + 8, H), (H, H + 8, H), (N, H + 8, H)]:
-        a, b = got[o:o + rows * kp], rg[o:o + rows * kp]
-        assert np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)) > 0.9999
-        o += rows * kp
+    rl, rg, mag = ref.mse_grad(params.astype(np.float64), th,
+                               tg.astype(np.float64), lo, hi, H, N, bf16=True,
+                               magnitude=True)
+    # Element by element.  Both sides round the same quantities to bfloat16
+    # (8 significant bits, neighbours 2^-7 apart relative); the values being
+    # rounded differ only by the order of FP32 accumulation (relative to
+    # their sum of absolute terms about K 2^-24), so a quantity near a
+    # rounding boundary can land on neighbouring values.  A gradient element
+    # is a sum of products of one back-propagated error and one activation,
+    # each possibly one neighbour away: the difference of an element is then
+    # within 2^-6 of its terms' absolute sum (the magnitude from the
+    # reference), plus K 2^-24 of it for the accumulation.  Elements with no
+    # terms (the parameter layout's padding) are exactly zero on both sides.
+    live = mag > 0
+    assert np.all(got[~live] == 0.0)
+    ratio = np.abs(got - rg)[live] / mag[live]
+    bound = 2.0 ** -6 + max(B, N) * 2.0 ** -24
+    log(f"[gpu] mlp gradient B={B} N={N}: max |diff|/magnitude "
+        f"{ratio.max():.2e} (bound {bound:.2e}), loss rel diff "
+        f"{abs(loss - rl) / rl:.2e}")
+    assert ratio.max() <= bound, int(np.argmax(ratio))
+    # the loss: FP64 sum of FP32 squared residuals; a residual differs by
+    # the FP32 accumulation of its output (K 2^-24 of its terms)
+    assert loss == pytest.approx(rl, rel=1e-4)
     # forward (log mu with mean 0, std 1 is the raw output)
     y = s.logmu(tt).cpu().numpy()
-    ry, _, _ = ref.forward(params.astype(np.float64), th, lo, hi, H, N, bf16=True)
-    assert np.max(np.abs(y - ry)) <= 2e-3 * np.max(np.abs(ry)) + 1e-4
+    ry, acts, _ = ref.forward(params.astype(np.float64), th, lo, hi, H, N,
+                              bf16=True)
+    w_out = np.abs(params.astype(np.float64)[-N * (H + 8):].reshape(N, H + 8)
+                   [:, :H + 1])
+    ymag = np.abs(acts[3]) @ ref.bf16_round(w_out).T
+    yr = np.abs(y - ry) / ymag
+    log(f"[gpu] mlp forward: max |diff|/magnitude {yr.max():.2e}")
+    assert yr.max() <= 2.0 ** -6
     s.close()
 
 

@@ -145,6 +145,30 @@ int nr_eval_mu(nr_ctx *ctx, const double *theta, int n_pts, double *mu);
 int nr_eval_nll_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
                     double *d_nll, double *d_grad, void *stream);
 
+/* Size in bytes of the static workspace of nr_eval_nll_dev_noalloc, one per
+ * device. */
+#define NR_NOALLOC_WORKSPACE_BYTES 16777216
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * computation, arguments and results of nr_eval_nll_dev, through the same
+ * kernels, with nothing allocated.  The pipeline's node tables, fold vectors,
+ * partial sums and adjoint buffers live in a static workspace of the library
+ * (NR_NOALLOC_WORKSPACE_BYTES per device, held from the first nr_create on
+ * that device until the process ends) instead of the context's buffers, and
+ * the launches go directly onto `stream` with no graph of the library's own,
+ * so that the caller may capture them in a graph of its own.  Every call on
+ * one device shares that workspace: calls that overlap on one device, from
+ * any context or thread, race, and the caller must order them (one stream,
+ * or events).  No part of the workspace needs to start at zero: each call
+ * writes every value it reads.  Returns NR_EINVAL when the context's shapes
+ * need more workspace than that (about 2 KiB per reco bin at the default
+ * tiling, plus 64 bytes per energy node and 16 per recoil row: a
+ * 16384 x 4096 response takes 9.3 MB), besides the status codes of
+ * nr_eval_nll_dev. */
+int nr_eval_nll_dev_noalloc(nr_ctx *ctx, const double *d_theta, int n_pts,
+                            double *d_nll, double *d_grad, void *stream);
+
 /* Batched form: n_pts points of one analysis at once.  The weights of all
  * points (from the theta-independent recoil basis, exact for Eq. (fT)) form
  * a matrix W[p][l] = m_l w_l(theta_p), and the fold of Eq. (mu_total)

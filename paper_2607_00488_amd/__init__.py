@@ -19,12 +19,13 @@ from ._build import LIB as _LIB_PATH
 NR_NTHETA = 7
 NR_OK, NR_EINVAL, NR_ESTATE, NR_EHIP, NR_ENOMEM = 0, -1, -2, -3, -4
 NR_PROBE_CACHED, NR_PROBE_ALTERNATE = 1, 2
+NR_NOALLOC_WORKSPACE_BYTES = 16 << 20
 
 # Exported symbols of include/nureweight.h.
 EXPORTS = (
     "nr_create", "nr_destroy", "nr_set_sources", "nr_set_response",
     "nr_set_data", "nr_eval_nll", "nr_eval_nll_grad", "nr_eval_mu",
-    "nr_eval_nll_dev", "nr_eval_weights", "nr_get_reference", "nr_stream",
+    "nr_eval_nll_dev", "nr_eval_nll_dev_noalloc", "nr_eval_weights", "nr_get_reference", "nr_stream",
     "nr_set_mc_events", "nr_eval_ess", "nr_set_components", "nr_num_theta",
     "nr_time_stage", "nr_set_fold_tiling", "nr_last_error",
     "nr_eval_nll_batched", "nr_eval_nll_grad_batched", "nr_eval_mu_batched",
@@ -109,6 +110,7 @@ def load():
     L.nr_num_theta.argtypes = [P]
     L.nr_eval_ess.argtypes = [P, pD, I, pD]
     L.nr_eval_nll_dev.argtypes = [P, P, I, P, P, P]
+    L.nr_eval_nll_dev_noalloc.argtypes = [P, P, I, P, P, P]
     L.nr_get_reference.argtypes = [P, pD, pD]
     L.nr_stream.argtypes = [P]
     L.nr_stream.restype = P
@@ -314,6 +316,14 @@ def nr_eval_nll_dev(h, d_theta_ptr, n_pts, d_nll_ptr, d_grad_ptr=None,
                                   C.c_void_p(d_nll_ptr),
                                   C.c_void_p(d_grad_ptr or 0),
                                   C.c_void_p(stream_ptr or 0)))
+
+
+def nr_eval_nll_dev_noalloc(h, d_theta_ptr, n_pts, d_nll_ptr, d_grad_ptr=None,
+                            stream_ptr=None):
+    _check(load().nr_eval_nll_dev_noalloc(h, C.c_void_p(d_theta_ptr), int(n_pts),
+                                          C.c_void_p(d_nll_ptr),
+                                          C.c_void_p(d_grad_ptr or 0),
+                                          C.c_void_p(stream_ptr or 0)))
 
 
 def nr_build_templates(h):
@@ -631,6 +641,15 @@ class Context:
         nr_eval_nll_dev(self.h, theta_t.data_ptr(), theta_t.shape[0],
                         nll_t.data_ptr(),
                         None if grad_t is None else grad_t.data_ptr(), sp)
+
+    def eval_nll_dev_noalloc(self, theta_t, nll_t, grad_t=None, stream=None):
+        """As eval_nll_dev, through the entry point that allocates nothing
+        (the library's static per-device workspace)."""
+        self._dev_args(theta_t, nll_t, grad_t)
+        sp = None if stream is None else stream.cuda_stream
+        nr_eval_nll_dev_noalloc(self.h, theta_t.data_ptr(), theta_t.shape[0],
+                                nll_t.data_ptr(),
+                                None if grad_t is None else grad_t.data_ptr(), sp)
 
     def build_templates(self):
         nr_build_templates(self.h)

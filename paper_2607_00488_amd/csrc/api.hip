@@ -19,6 +19,14 @@
 #include <vector>
 #include <sys/stat.h>
 
+// Workspace of the allocation-free entry point nr_eval_nll_dev_noalloc: the
+// single-point pipeline's node tables, fold vectors, partial sums and
+// adjoint buffers for any context on the device, in place of the context's
+// own.  One copy per device, resident until the process ends.  Host code
+// never passes this name to a kernel or a copy: it uses the device address
+// hipGetSymbolAddress returns on each device (g_scratch_dev).
+static __device__ __align__(256) double scratch[NR_NOALLOC_WORKSPACE_BYTES / sizeof(double)];
+
 namespace {
 
 thread_local std::string g_err;
@@ -129,6 +137,22 @@ struct ApiLock {
 // grouped-launch plans built under an older epoch are rebuilt.
 std::atomic<unsigned long> g_epoch{1};
 
+// Device address of the static workspace on each device, looked up once per
+// device by the first nr_create on it (under the API lock).
+std::vector<double*> g_scratch_dev;
+
+int lookup_scratch(int device, int ndev) {
+    if ((int)g_scratch_dev.size() < ndev) g_scratch_dev.resize(ndev, nullptr);
+    if (g_scratch_dev[device]) return 0;
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        return fail(NR_EHIP, "hipGetSymbolAddress(static workspace) on device %d: %s",
+                    device, hipGetErrorString(e));
+    g_scratch_dev[device] = static_cast<double*>(p);
+    return 0;
+}
+
 // One grouped launch over several analyses: GEMM problem tables, tile lists
 // and the captured graph of the whole batched evaluation.
 struct BatchPlan {
@@ -184,7 +208,6 @@ struct nr_ctx {
     int rows_per_wg = 0, n_rb = 0, n_fc = 0, n_cc = 0, adj_grid = 0;
     double *d_colpart = nullptr;  // [2][n_rb][ldr]
     double *d_chunk_dev = nullptr, *d_chunk_gb = nullptr;
-    unsigned* d_ctr = nullptr;  // [n_cc + 1] fold, [1] adjoint after that
     double* d_a = nullptr;
     double *d_gb = nullptr, *d_jpart = nullptr;
     // staging for the synchronous entry points
@@ -332,8 +355,6 @@ int choose_tiling(nr_ctx* c, int rows_req) {
     if ((rc = dalloc(&c->d_colpart, (size_t)2 * c->n_rb * c->ldr))) return rc;
     if ((rc = dalloc(&c->d_chunk_dev, (size_t)2 * c->n_cc))) return rc;
     if ((rc = dalloc(&c->d_chunk_gb, (size_t)2 * c->n_cc))) return rc;
-    if ((rc = dalloc(&c->d_ctr, (size_t)c->n_cc + 2))) return rc;
-    HIPCHK(hipMemset(c->d_ctr, 0, sizeof(unsigned) * (c->n_cc + 2)));
     c->adj_grid = nr::adjoint_grid(c->n_t);
     if ((rc = dalloc(&c->d_jpart, (size_t)c->adj_grid * nr::kNBasis))) return rc;
     clear_graphs(c);
@@ -362,7 +383,47 @@ int ensure_stage(nr_ctx* c, size_t pts, size_t mu_elems, size_t w_elems) {
     return 0;
 }
 
-nr::ScanArgs scan_args(nr_ctx* c, const double* d_theta, int par) {
+// Device buffers of the single-point pipeline: node tables, fold vectors,
+// fold partial rows and likelihood group sums (each by point parity), and
+// the adjoint's a_j, sum_j a_j b_j and basis contractions.  A context owns
+// one set; the allocation-free entry point carves another out of the
+// library's static workspace (NULL = the context's).
+struct Work {
+    double* table[2];   // [4 (n_nodes + n_src)] each
+    double* v[2];       // [n_rows] each
+    double* colpart;    // [2][n_rb][ldr]
+    double* chunk_dev;  // [2][n_cc]
+    double* chunk_gb;   // [2][n_cc]
+    double* a;          // [ldr]
+    double* gb;         // [1]
+    double* jpart;      // [adj_grid][kNBasis]
+};
+
+// Lays the buffers of Work out from base (256-byte pieces) and returns the
+// bytes they take; with base NULL only the size is formed.
+size_t carve_work(const nr_ctx* c, double* base, Work* w) {
+    size_t off = 0;
+    auto take = [&](size_t n) {
+        double* p = base ? base + off : nullptr;
+        off += (n + 31) / 32 * 32;
+        return p;
+    };
+    const size_t nt = (size_t)4 * (c->n_nodes + c->n_src);
+    w->table[0] = take(nt);
+    w->table[1] = take(nt);
+    w->v[0] = take(c->n_rows);
+    w->v[1] = take(c->n_rows);
+    w->colpart = take((size_t)2 * c->n_rb * c->ldr);
+    w->chunk_dev = take((size_t)2 * c->n_cc);
+    w->chunk_gb = take((size_t)2 * c->n_cc);
+    w->a = take(c->ldr);
+    w->gb = take(1);
+    w->jpart = take((size_t)c->adj_grid * nr::kNBasis);
+    return off * sizeof(double);
+}
+
+nr::ScanArgs scan_args(nr_ctx* c, const double* d_theta, int par,
+                       const Work* wk = nullptr) {
     nr::ScanArgs a{};
     a.nodeIE = c->d_E;
     a.nodeW = c->d_W;
@@ -372,14 +433,15 @@ nr::ScanArgs scan_args(nr_ctx* c, const double* d_theta, int par) {
     a.srcGroup = c->multi ? c->d_group0 : c->d_group;
     a.theta = d_theta;
     a.ph = c->ph;
-    a.table = reinterpret_cast<double4*>(c->d_table[par]);
+    a.table = reinterpret_cast<double4*>(wk ? wk->table[par] : c->d_table[par]);
     return a;
 }
 
 nr::RowArgs row_args(nr_ctx* c, int par, double* v, double* out_w,
-                     double* out_s, const double* d_theta) {
+                     double* out_s, const double* d_theta,
+                     const Work* wk = nullptr) {
     nr::RowArgs a{};
-    a.table = reinterpret_cast<const double4*>(c->d_table[par]);
+    a.table = reinterpret_cast<const double4*>(wk ? wk->table[par] : c->d_table[par]);
     a.jmin = c->d_jmin;
     a.tc = c->d_tc;
     a.n_t = c->n_t;
@@ -399,7 +461,7 @@ nr::RowArgs row_args(nr_ctx* c, int par, double* v, double* out_w,
 
 nr::FoldArgs fold_args(nr_ctx* c, const double* thp, const double* v,
                        double* colpart, double* nll, double* mu, bool grad,
-                       int cpar = 0) {
+                       int cpar = 0, const Work* wk = nullptr) {
     nr::FoldArgs fa{};
     fa.R = c->d_R;
     fa.ldr = c->ldr;
@@ -414,12 +476,13 @@ nr::FoldArgs fold_args(nr_ctx* c, const double* thp, const double* v,
     fa.n_theta = c->n_theta;
     fa.theta = thp;
     fa.colpart = colpart;
-    fa.chunk_dev = c->d_chunk_dev + (size_t)cpar * c->n_cc;  // group sums, by parity
-    fa.chunk_gb = c->d_chunk_gb + (size_t)cpar * c->n_cc;
+    // group sums, by parity
+    fa.chunk_dev = (wk ? wk->chunk_dev : c->d_chunk_dev) + (size_t)cpar * c->n_cc;
+    fa.chunk_gb = (wk ? wk->chunk_gb : c->d_chunk_gb) + (size_t)cpar * c->n_cc;
     fa.out_nll = nll;
     fa.out_mu = mu;
-    fa.out_a = grad ? c->d_a : nullptr;
-    fa.out_gb = grad ? c->d_gb : nullptr;
+    fa.out_a = grad ? (wk ? wk->a : c->d_a) : nullptr;
+    fa.out_gb = grad ? (wk ? wk->gb : c->d_gb) : nullptr;
     fa.cdata = c->cdata;
     for (int i = 0; i < c->n_theta; ++i) {
         fa.pull_mean[i] = c->pull_mean[i];
@@ -472,19 +535,24 @@ int step(nr_ctx* c, const nr::FoldArgs* fold, const nr::RowArgs* rows,
 // only synchronisation.  With a gradient each point runs its stages in
 // turn, the adjoint pass (which needs the finished a_j) last.
 int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
-                   double* grad, double* mu, double* w, hipStream_t s) {
+                   double* grad, double* mu, double* w, hipStream_t s,
+                   const Work* wk = nullptr) {
+    const Work own{{c->d_table[0], c->d_table[1]}, {c->d_v[0], c->d_v[1]},
+                   c->d_colpart, c->d_chunk_dev, c->d_chunk_gb, c->d_a, c->d_gb,
+                   c->d_jpart};
+    if (!wk) wk = &own;
     const size_t cp = (size_t)c->n_rb * c->ldr;
     auto thp = [&](int p) { return th + (size_t)p * c->n_theta; };
-    auto sa = [&](int p) { return scan_args(c, thp(p), p & 1); };
+    auto sa = [&](int p) { return scan_args(c, thp(p), p & 1, wk); };
     auto ra = [&](int p) {
-        return row_args(c, p & 1, c->d_v[p & 1],
-                        w ? w + (size_t)p * c->n_rows : nullptr, nullptr, thp(p));
+        return row_args(c, p & 1, wk->v[p & 1],
+                        w ? w + (size_t)p * c->n_rows : nullptr, nullptr, thp(p), wk);
     };
     auto fa = [&](int p) {
-        nr::FoldArgs f = fold_args(c, thp(p), c->d_v[p & 1],
-                                   c->d_colpart + (p & 1) * cp, nll + p,
+        nr::FoldArgs f = fold_args(c, thp(p), wk->v[p & 1],
+                                   wk->colpart + (p & 1) * cp, nll + p,
                                    mu ? mu + (size_t)p * c->n_reco : nullptr,
-                                   grad != nullptr, p & 1);
+                                   grad != nullptr, p & 1, wk);
         // a scan walks R forwards and backwards in turn, so each point starts
         // on the rows the previous one left in the Infinity Cache
         f.reverse = (grad || f.stream_nt) ? 0 : (p & 1);
@@ -523,14 +591,13 @@ int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
         aa.ldr = c->ldr;
         aa.n_t = c->n_t;
         aa.n_reco = c->n_reco;
-        aa.a = c->d_a;
+        aa.a = wk->a;
         aa.ssm = c->d_ssm;
         aa.mrow = c->d_mrow;
         aa.basis = c->d_basis;
         aa.theta = thp(p);
-        aa.gb = c->d_gb;
-        aa.jpart = c->d_jpart;
-        aa.ctr = c->d_ctr + c->n_cc + 1;
+        aa.gb = wk->gb;
+        aa.jpart = wk->jpart;
         aa.out_grad = grad + (size_t)p * NR_NTHETA;
         for (int i = 0; i < NR_NTHETA; ++i) {
             aa.pull_mean[i] = c->pull_mean[i];
@@ -1066,6 +1133,10 @@ int nr_create(int device, nr_ctx** out) {
         delete c;
         return fail(NR_EHIP, "stream creation: %s", hipGetErrorString(e));
     }
+    if (int rc = lookup_scratch(device, ndev)) {
+        nr_destroy(c);
+        return rc;
+    }
     if (dalloc(&c->d_a, 1) || dalloc(&c->d_gb, 1) || dalloc(&c->d_thsm, nr::kMaxTheta) ||
         dalloc(&c->d_gctr, 4) || dalloc(&c->d_tnll, 1 + NR_NTHETA)) {
         delete c;
@@ -1093,7 +1164,7 @@ void nr_destroy(nr_ctx* c) {
     dfree(&c->d_group); dfree(&c->d_jmin); dfree(&c->d_srcoff);
     dfree(&c->d_table[0]); dfree(&c->d_table[1]); dfree(&c->d_R); dfree(&c->d_mrow);
     dfree(&c->d_n); dfree(&c->d_b); dfree(&c->d_colpart);
-    dfree(&c->d_chunk_dev); dfree(&c->d_chunk_gb); dfree(&c->d_ctr);
+    dfree(&c->d_chunk_dev); dfree(&c->d_chunk_gb);
     dfree(&c->d_a); dfree(&c->d_gb); dfree(&c->d_jpart);
     dfree(&c->d_th); dfree(&c->d_out); dfree(&c->d_grad);
     dfree(&c->d_mu); dfree(&c->d_w); dfree(&c->d_thsm);
@@ -1362,6 +1433,34 @@ int nr_eval_nll_dev(nr_ctx* c, const double* d_theta, int n_pts, double* d_nll,
     Bridge br;
     if ((rc = bridge_begin(br, stream, c->stream, c->ev_in, c->ev_out))) return rc;
     if ((rc = run_points(c, d_theta, n_pts, d_nll, d_grad, nullptr, nullptr, br.work)))
+        return rc;
+    return bridge_end(br);
+}
+
+int nr_eval_nll_dev_noalloc(nr_ctx* c, const double* d_theta, int n_pts,
+                            double* d_nll, double* d_grad, void* stream) {
+    const ApiLock api_lock;
+    int rc;
+    if ((rc = check_ready(c))) return rc;
+    if (!d_theta || !d_nll || n_pts <= 0)
+        return fail(NR_EINVAL, "null device pointer or n_pts <= 0");
+    if (d_grad && (rc = check_single(c))) return rc;
+    if ((rc = set_device(c))) return rc;
+    double* base = c->device < (int)g_scratch_dev.size() ? g_scratch_dev[c->device] : nullptr;
+    if (!base) return fail(NR_ESTATE, "no static workspace on device %d", c->device);
+    Work w;
+    const size_t need = carve_work(c, nullptr, &w);
+    if (need > (size_t)NR_NOALLOC_WORKSPACE_BYTES)
+        return fail(NR_EINVAL, "this context's shapes need %zu bytes of workspace; "
+                    "the static workspace holds %zu", need,
+                    (size_t)NR_NOALLOC_WORKSPACE_BYTES);
+    carve_work(c, base, &w);
+    // launched directly on the caller's stream (no graph of our own), so
+    // that a caller may capture them in its own graph
+    Bridge br;
+    if ((rc = bridge_begin(br, stream, c->stream, c->ev_in, c->ev_out))) return rc;
+    if ((rc = enqueue_points(c, d_theta, n_pts, d_nll, d_grad, nullptr, nullptr,
+                             br.work, &w)))
         return rc;
     return bridge_end(br);
 }
@@ -1687,7 +1786,6 @@ int nr_time_stage(nr_ctx* c, int stage, int iters, double* avg_ms) {
         aa.theta = th;
         aa.gb = c->d_gb;
         aa.jpart = c->d_jpart;
-        aa.ctr = c->d_ctr + c->n_cc + 1;
         aa.out_grad = c->d_tnll + 1;
         aa.ph = c->ph;
     }

@@ -113,7 +113,6 @@ struct AdjArgs {
     const double* theta;
     const double* gb;     // [1]
     double* jpart;        // [grid][kNBasis]
-    unsigned* ctr;        // [1]
     double* out_grad;     // [7]
     double pull_mean[kNTheta];
     double pull_sigma[kNTheta];

@@ -1,9 +1,11 @@
 """Benchmark: likelihood evaluations per second on one MI355X.
 
-A step is one plain single-point evaluation of the whole path (device
-E-integral, weights, HBM-streaming fold of the 16384 x 4096 FP32 response,
-Poisson -2lnL) at a fresh parameter point, with every input resident in HBM.
-The K timed steps are one HIP-graph replay of K evaluations.
+A step is one batch of parameter points (100 by default, a row of a
+likelihood scan), each put through the whole plain single-point path
+(device E-integral, weights, HBM-streaming fold of the 16384 x 4096 FP32
+response, Poisson -2lnL), with every input resident in HBM.  The K timed
+steps are one HIP-graph replay of K x 100 evaluations; the value is
+evaluations per second.
 
 Prints one JSON line: the plain rate as `value`, the roofline of the step
 kernel, the batched and gradient forms and the CPU oracle timed beside it.
@@ -245,7 +247,70 @@ def asimov_scan_form(p):
     return out
 
 
-def surrogate_form(ctx, train_seconds=20.0):
+def surrogate_ceiling(ctx, sur, n_data, th_val, ks=(16, 32, 64)):
+    """How far the trained network's -2lnL is from the exact one, and how
+    far first-order corrections from exact linear functionals of mu would
+    take it (measurement only, FP64 torch on the device).  Writing
+    d_j = ln mu^_j - ln mu_j, the error is 2 sum_j (mu^_j - mu_j) - 2 sum_j
+    n_j d_j.  The first sum is a linear functional of mu, exact for any
+    point from the 21 folded templates; the second is to first order
+    2 sum_j (n_j / mu^_j)(mu_j - mu^_j), which exact functionals
+    L_k = sum_j V_kj mu_j remove along the span of V (the leading K right
+    singular vectors of n / mu over 8192 other points of the box)."""
+    import torch
+    import paper_2607_00488_amd as nr
+    dev = th_val.device
+    s = torch.cuda.current_stream(dev)
+
+    def exact_mu(th):
+        mu = torch.empty(th.shape[0], ctx.n_reco, dtype=torch.float64, device=dev)
+        for c0 in range(0, th.shape[0], 4096):
+            k = min(4096, th.shape[0] - c0)
+            nr.nr_eval_mu_batched_dev(ctx.h, th[c0:c0 + k].contiguous().data_ptr(),
+                                      k, mu[c0:c0 + k].data_ptr(), s.cuda_stream)
+        return mu
+
+    nt = torch.tensor(n_data, dtype=torch.float64, device=dev)
+
+    def dev2(m):
+        return 2.0 * torch.where(nt > 0, m - nt + nt * torch.log(nt / m), m).sum(1)
+
+    r = nt / exact_mu(sur.sample_box(8192, 4006))
+    V = torch.linalg.svd(r, full_matrices=False)[2]
+    del r
+    mu = exact_mu(th_val)
+    lmh = sur.logmu(th_val).double()
+    muh = torch.exp(lmh)
+    d_ex = dev2(mu)
+    raw = dev2(muh) - d_ex
+    summ = raw - 2.0 * (muh.sum(1) - mu.sum(1))
+    rh = nt / muh
+    far = d_ex - d_ex.min()
+
+    def q(x):
+        a = x.abs()
+        return dict(median=float(a.median()), q90=float(a.quantile(0.9)),
+                    max=float(a.max()), frac_le_0p1=float((a <= 0.1).double().mean()))
+
+    out = dict(dln_mu_rms=float((lmh - torch.log(mu)).pow(2).mean().sqrt()),
+               raw=q(raw), exact_sum_mu=q(summ))
+    for k in ks:
+        Vk = V[:k]
+        corr = 2.0 * ((rh @ Vk.T) * (mu @ Vk.T - muh @ Vk.T)).sum(1)
+        dk = summ - corr
+        out[f"functionals_{k}"] = q(dk)
+        for lim in (100.0, 1.0e3, 1.0e4):
+            m = far <= lim
+            if int(m.sum()) >= 8:
+                out[f"functionals_{k}_within_dchi2_{int(lim)}"] = dict(
+                    q(dk[m]), fraction_of_box=float(m.double().mean()))
+    out["what"] = ("validation points: |d(-2lnL)| of the network as is, with "
+                   "the exact sum of mu, and with first-order corrections "
+                   "from K exact linear functionals of mu")
+    return out
+
+
+def surrogate_form(ctx, train_seconds=20.0, n_data=None):
     """The learned surrogate at the paper-scale binning: 7 -> 256 -> 256 ->
     256 -> 4096 SiLU MLP trained on 2^18 spectra from the batched method
     (prior box), validated on 2^14 held-out points against the exact
@@ -270,6 +335,8 @@ def surrogate_form(ctx, train_seconds=20.0):
     nr.eval_nll_multi_dev([ctx], [th_val], [ex_val])
     nl_val, _ = sur.nll(ctx, th_val)
     d = (nl_val - ex_val).abs().cpu().numpy()
+    ceiling = (surrogate_ceiling(ctx, sur, n_data, th_val)
+               if n_data is not None else None)
     B = 1 << 16
     th = sur.sample_box(B, 4005)
     ex = torch.empty(B, dtype=torch.float64, device=dev)
@@ -312,6 +379,7 @@ def surrogate_form(ctx, train_seconds=20.0):
                    seconds=round(info["seconds"], 2),
                    data_seconds=round(t_data, 2),
                    final_loss=info["losses"][-1][1] if info["losses"] else None),
+        ceiling=ceiling,
         what="MLP 7-256-256-256-4096 SiLU on BF16 matrix cores; -2lnL "
              "with 1% exact spot checks, fallback to the exact batched "
              "method when a check misses by more than 0.1")
@@ -513,8 +581,10 @@ def cpu_baseline(p, n_eval, gpu_ctx):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--points-per-step", type=int, default=100,
+                    help="parameter points per step (one scan row)")
     ap.add_argument("--cpu-evals", type=int, default=96,
                     help="oracle evaluations timed for cpu_baseline (~10 s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -566,15 +636,16 @@ def main():
         torch.cuda.synchronize()
         log("[bench] counter pass done")
         return
-    K, W = args.steps, args.warmup
-    th = synth.theta_prior(K, p["seeds"]["theta"])
+    K, W, PPS = args.steps, args.warmup, args.points_per_step
+    NE = K * PPS                      # evaluations in the timed region
+    th = synth.theta_prior(NE, p["seeds"]["theta"])
     tt = torch.tensor(th, dtype=torch.float64, device=dev)
-    out = torch.empty(K, dtype=torch.float64, device=dev)
-    thw = torch.tensor(synth.theta_prior(max(W, 1), p["seeds"]["theta"] + 1),
+    out = torch.empty(NE, dtype=torch.float64, device=dev)
+    thw = torch.tensor(synth.theta_prior(max(W, 1) * PPS, p["seeds"]["theta"] + 1),
                        dtype=torch.float64, device=dev)
-    outw = torch.empty(max(W, 1), dtype=torch.float64, device=dev)
+    outw = torch.empty(max(W, 1) * PPS, dtype=torch.float64, device=dev)
     stream = torch.cuda.Stream(device=dev)
-    # warm-up: captures the K-point and W-point graphs and runs them once
+    # warm-up: captures the timed and the warm-up graphs and runs them once
     ctx.eval_nll_dev(thw, outw, stream=stream)
     ctx.eval_nll_dev(tt, out, stream=stream)
     stream.synchronize()
@@ -589,10 +660,10 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # device time of the timed region on the stream the step kernels run
-    # on: K + 4 launches, K - 4 of them the steady-state k_step
+    # on: NE + 4 launches, NE - 4 of them the steady-state k_step
     dev_ms = ev0.elapsed_time(ev1)
     ms_step = dt * 1e3 / K
-    evals_s = K / dt
+    evals_s = NE / dt
     log(f"[bench] plain: {ms_step * 1e3:.2f} us/eval, {evals_s:.0f} evals/s")
 
     # host-visible synchronous latency (paper protocol: 10 calls, drop 1st)
@@ -606,10 +677,10 @@ def main():
     # roofline of the dominant kernel, the step kernel as the pipeline runs
     # it: device time of the timed region (HIP events on its stream) per
     # evaluation, which charges the 8 shorter fill/drain launches to the
-    # K - 4 steady-state ones (a conservative average); the steady-state
+    # NE - 4 steady-state ones (a conservative average); the steady-state
     # launch alone back to back, the fold role alone and the other stages
     # for the breakdown
-    step_ms = dev_ms / K
+    step_ms = dev_ms / NE
     step_bb_ms = ctx.time_stage(5, 200)
     # the same launch after 512 MiB of other data have been read through the
     # device's caches (the 256 MB Infinity Cache included): the cold-cache
@@ -634,9 +705,16 @@ def main():
                 unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=measured_traffic(), kernel="k_step",
                 avg_kernel_us=round(step_ms * 1e3, 2),
-                algorithmic_bytes=alg_bytes)
+                algorithmic_bytes=alg_bytes,
+                note="effective rate: the algorithmic bytes of a launch over "
+                     "its time, whether HBM or the Infinity Cache served "
+                     "them (consecutive points walk R in opposite "
+                     "directions and reuse what the last one left cached); "
+                     "one launch after a 512 MiB cache flush: "
+                     "detail.step_after_cache_flush_us")
     res = dict(metric=METRIC, value=round(evals_s, 1), unit="evals/s",
                n_gpus=1, steps=K, warmup=W, ms_per_step=round(ms_step, 5),
+               points_per_step=PPS,
                higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="f64", data="synthetic",
                config=dict(workload="plain single-point eval: N_T=16384 "
@@ -730,7 +808,8 @@ def main():
         for cx in ctxs:
             cx.close()
     if not args.no_surrogate:
-        forms["surrogate"] = sf = surrogate_form(ctx, args.surrogate_seconds)
+        forms["surrogate"] = sf = surrogate_form(ctx, args.surrogate_seconds,
+                                                 n_data=p["n"])
         log(f"[bench] surrogate: {sf['evals_per_s']:.0f} evals/s with "
             f"fallback {sf['fallback']} ({sf['fallback_fraction']:.2f}); "
             f"network alone {sf['network_only_evals_per_s']:.0f} evals/s; "

@@ -196,6 +196,7 @@ struct nr_ctx {
     // data
     double *d_n = nullptr, *d_b = nullptr;
     double cdata = 0;
+    double lgsum = 0;  // sum_j lnGamma(n_j + 1)
     double pull_mean[nr::kMaxTheta] = {0}, pull_sigma[nr::kMaxTheta] = {0};
     // multi-component form (Eqs. (Rij), (fNp_reweight), (mu_total)): the
     // component responses are stacked row-wise in d_R, n_rows = n_comp * n_t
@@ -1406,10 +1407,14 @@ int nr_set_data(nr_ctx* c, const double* n, const double* b, int n_reco,
     else HIPCHK(hipMemset(c->d_b, 0, sizeof(double) * n_reco));
     // data-only constant of Eq. (logL): the device reduces the deviance
     // mu - n + n ln(n/mu); -2lnL = 2 (deviance + C_data) + pulls.
-    double cd = 0;
-    for (int j = 0; j < n_reco; ++j)
-        cd += n[j] - (n[j] > 0 ? n[j] * std::log(n[j]) : 0.0) + std::lgamma(n[j] + 1.0);
+    double cd = 0, lg = 0;
+    for (int j = 0; j < n_reco; ++j) {
+        const double l = std::lgamma(n[j] + 1.0);
+        cd += n[j] - (n[j] > 0 ? n[j] * std::log(n[j]) : 0.0) + l;
+        lg += l;
+    }
     c->cdata = cd;
+    c->lgsum = lg;
     for (int i = 0; i < nr::kMaxTheta; ++i) {
         c->pull_mean[i] = pull_mean && i < c->n_theta ? pull_mean[i] : 0.0;
         c->pull_sigma[i] = pull_sigma && i < c->n_theta ? pull_sigma[i] : 0.0;
@@ -1906,6 +1911,9 @@ struct nr_mlp {
     long n_params = 0;
     float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
     nr::bf16* w16 = nullptr;
+    // per layer the BF16 weights transposed, [kp_l][nn_l] (input-major): the
+    // operand of the backward product dY W, read along its reduction index
+    nr::bf16* w16t = nullptr;
     nr::bf16 *x = nullptr, *h[3] = {nullptr, nullptr, nullptr};
     float* z[3] = {nullptr, nullptr, nullptr};
     nr::bf16 *dy = nullptr, *dz[2] = {nullptr, nullptr};
@@ -1953,6 +1961,14 @@ int mlp_alloc_batch(nr_mlp* q, int B, bool train) {
     return 0;
 }
 
+// Refreshes the transposed BF16 copies of the weights of layers 1 to 3.
+int mlp_transpose(nr_mlp* q, hipStream_t s) {
+    for (int l = 1; l < 4; ++l)
+        HIPCHK(nr::launch_transpose_bf16(q->w16 + q->off[l], q->w16t + q->off[l],
+                                         q->nn[l], q->kp[l], s));
+    return 0;
+}
+
 nr::MlpGemm mg(const nr::bf16* A, long sam, long sak, const nr::bf16* B,
                long sbk, long sbn, int M, int N, int K) {
     nr::MlpGemm g{};
@@ -1966,12 +1982,12 @@ nr::MlpGemm mg(const nr::bf16* A, long sam, long sak, const nr::bf16* B,
 // G^T = dZ^T H (K = batch; 256 x 264 for a hidden layer: 6 tiles) and the
 // first backward product dY W (K = the 4096 outputs) — is split along K
 // over enough work-groups to fill the chip (about two per compute unit,
-// chunks of at least 256), each split writing its own FP32 slab; the slabs
+// chunks of at least 64), each split writing its own FP32 slab; the slabs
 // are then summed in order and the GEMM's epilogue applied (FP32 store into
 // C32, or SiLU' into g.C16).  No float atomics: a training step stays
 // bitwise reproducible.
 int mlp_split_gemm(nr_mlp* q, nr::MlpGemm g, int mode, float* C32, long ldc, hipStream_t s) {
-    constexpr int kTK = 32, kTile = 128, kMinChunk = 256;
+    constexpr int kTK = 32, kTile = 128, kMinChunk = 64;
     const int tiles = ((g.M + kTile - 1) / kTile) * ((g.N + kTile - 1) / kTile);
     int n_split = std::max(1, std::min((512 + tiles - 1) / tiles, g.K / kMinChunk));
     if (n_split <= 1) {
@@ -2031,7 +2047,8 @@ int mlp_hidden_forward(nr_mlp* q, int B, hipStream_t s) {
     return 0;
 }
 
-int mlp_input(nr_mlp* q, const double* th, int B, hipStream_t s) {
+int mlp_input(nr_mlp* q, const double* th, int B, hipStream_t s,
+              int* outside = nullptr) {
     nr::MlpInput in{};
     in.theta = th;
     in.B = B;
@@ -2040,7 +2057,7 @@ int mlp_input(nr_mlp* q, const double* th, int B, hipStream_t s) {
         in.hi[i] = q->hi[i];
     }
     in.x = q->x;
-    in.outside = q->outside;
+    in.outside = outside ? outside : q->outside;
     HIPCHK(nr::launch_mlp_input(in, s));
     return 0;
 }
@@ -2077,13 +2094,15 @@ int nr_mlp_create(int device, int hidden, int n_out, nr_mlp** out) {
     int rc;
     if ((rc = dalloc(&q->w, q->n_params)) || (rc = dalloc(&q->g, q->n_params)) ||
         (rc = dalloc(&q->m, q->n_params)) || (rc = dalloc(&q->v, q->n_params)) ||
-        (rc = dalloc(&q->w16, q->n_params)) || (rc = dalloc(&q->mean, n_out)) ||
+        (rc = dalloc(&q->w16, q->n_params)) || (rc = dalloc(&q->w16t, q->n_params)) ||
+        (rc = dalloc(&q->mean, n_out)) ||
         (rc = dalloc(&q->stdv, n_out))) {
         delete q;
         return rc;
     }
     (void)hipMemset(q->w, 0, sizeof(float) * q->n_params);
     (void)hipMemset(q->w16, 0, sizeof(nr::bf16) * q->n_params);
+    (void)hipMemset(q->w16t, 0, sizeof(nr::bf16) * q->n_params);
     (void)hipMemset(q->m, 0, sizeof(float) * q->n_params);
     (void)hipMemset(q->v, 0, sizeof(float) * q->n_params);
     *out = q;
@@ -2096,6 +2115,7 @@ void nr_mlp_destroy(nr_mlp* q) {
     (void)hipSetDevice(q->device);
     (void)hipStreamSynchronize(q->stream);
     dfree(&q->w); dfree(&q->g); dfree(&q->m); dfree(&q->v); dfree(&q->w16);
+    dfree(&q->w16t);
     dfree(&q->x); dfree(&q->dy); dfree(&q->dz[0]); dfree(&q->dz[1]);
     for (int l = 0; l < 3; ++l) { dfree(&q->h[l]); dfree(&q->z[l]); }
     dfree(&q->tile_loss); dfree(&q->part); dfree(&q->outside);
@@ -2118,6 +2138,9 @@ int nr_mlp_set_params(nr_mlp* q, const float* params, long n) {
     for (long i = 0; i < n; ++i) h16[i] = (nr::bf16)params[i];
     HIPCHK(hipMemcpy(q->w, params, sizeof(float) * n, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(q->w16, h16.data(), sizeof(nr::bf16) * n, hipMemcpyHostToDevice));
+    int rt;
+    if ((rt = mlp_transpose(q, q->stream))) return rt;
+    HIPCHK(hipStreamSynchronize(q->stream));
     HIPCHK(hipMemset(q->m, 0, sizeof(float) * n));
     HIPCHK(hipMemset(q->v, 0, sizeof(float) * n));
     q->step = 0;
@@ -2210,8 +2233,10 @@ int nr_mlp_train_step_dev(nr_mlp* q, const double* d_theta, const float* d_t,
     int upw = N;                  // its width
     for (int l = 2; l >= 0; --l) {
         nr::bf16* dzl = q->dz[l & 1];
-        // dZ_l = (up W_{l+1}) * SiLU'(Z_l), with W_{l+1} = (W^T_{l+1})^T
-        nr::MlpGemm gd = mg(up, upw, 1, q->w16 + q->off[l + 1], ldh, 1, B, H, upw);
+        // dZ_l = (up W_{l+1}) * SiLU'(Z_l): W_{l+1}(k, n) from the transposed
+        // copy [kp][nn], contiguous along the reduction index k
+        nr::MlpGemm gd = mg(up, upw, 1, q->w16t + q->off[l + 1], 1, q->nn[l + 1],
+                            B, H, upw);
         gd.aux = q->z[l];
         gd.ldaux = H;
         gd.C16 = dzl;
@@ -2241,6 +2266,7 @@ int nr_mlp_train_step_dev(nr_mlp* q, const double* d_theta, const float* d_t,
     ad.bc1 = 1.0f - powf(0.9f, (float)q->step);
     ad.bc2 = 1.0f - powf(0.999f, (float)q->step);
     HIPCHK(nr::launch_adam(ad, s));
+    if ((rc = mlp_transpose(q, s))) return rc;
     if ((rc = bridge_end(br))) return rc;
     if (loss) {
         const int tiles = ((B + 127) / 128) * ((N + 127) / 128);
@@ -2293,8 +2319,10 @@ int nr_mlp_nll_dev(nr_mlp* q, nr_ctx* c, const double* d_theta, int B,
     if ((rc = bridge_begin(br, stream, q->stream, q->ev_in, q->ev_out))) return rc;
     hipStream_t s = br.work;
     const int ldh = q->H + 8;
-    const int nnt = (q->n_out + 127) / 128;
-    if ((rc = mlp_input(q, d_theta, B, s))) return rc;
+    // bin groups per point tile: about two work-groups per compute unit
+    const int n_pt = (B + 127) / 128;
+    const int nnt = std::max(1, std::min((q->n_out + 127) / 128, (512 + n_pt - 1) / n_pt));
+    if ((rc = mlp_input(q, d_theta, B, s, d_outside))) return rc;
     if ((rc = mlp_hidden_forward(q, B, s))) return rc;
     nr::MlpGemm go = mg(q->h[2], ldh, 1, q->w16 + q->off[3], 1, ldh, B, q->n_out, ldh);
     go.mean = q->mean;
@@ -2308,15 +2336,14 @@ int nr_mlp_nll_dev(nr_mlp* q, nr_ctx* c, const double* d_theta, int B,
     f.theta = d_theta;
     f.n_pts = B;
     f.n_nt = nnt;
-    f.cdata = c->cdata;
+    // the partial sums are of mu - n ln mu: -2lnL = 2 (sum + sum lnGamma(n + 1))
+    f.cdata = c->lgsum;
     for (int i = 0; i < NR_NTHETA; ++i) {
         f.pull_mean[i] = c->pull_mean[i];
         f.pull_sigma[i] = c->pull_sigma[i];
     }
     f.nll = d_nll;
     HIPCHK(nr::launch_finalize(f, s));
-    if (d_outside)
-        HIPCHK(hipMemcpyAsync(d_outside, q->outside, sizeof(int) * B, hipMemcpyDeviceToDevice, s));
     return bridge_end(br);
 }
 

@@ -12,7 +12,8 @@ enum MlpMode {
     kMlpSilu = 1,      // C32 = z = acc; C16 = SiLU(z)     (hidden forward)
     kMlpMse = 2,       // r = acc - T; C16 = scale * 2r    (output, training)
     kMlpDSilu = 3,     // C16 = acc * SiLU'(Z)             (hidden backward)
-    kMlpNll = 4,       // mu = exp(mean + std * acc); deviance row partials
+    kMlpNll = 4,       // mu = exp(mean + std * acc); per point partial
+                       // sums of mu - n ln mu (its own kernel, k_mlp_nll)
     kMlpLogMu = 5,     // C32 = mean + std * acc           (log mu output)
 };
 
@@ -36,7 +37,7 @@ struct MlpGemm {
     const float* mean;  // [N] (Nll, LogMu)
     const float* stdv;  // [N]
     const double* nobs; // [N] data (Nll)
-    double* part;       // [M][n_nt] deviance partials (Nll)
+    double* part;       // [M][n_nt] partial sums of mu - n ln mu (Nll)
     int n_nt;
     // K split (Store32 only): work-group z sums k in [z k_chunk, (z+1)
     // k_chunk) into the slab C32 + z c_split; 0 = one pass over all of K
@@ -89,6 +90,9 @@ struct TargetArgs {
 hipError_t launch_mlp_gemm(int mode, const MlpGemm& g, hipStream_t s);
 hipError_t launch_mlp_ksum(const KSumArgs& a, hipStream_t s);
 hipError_t launch_mlp_input(const MlpInput& a, hipStream_t s);
+// dst[c][r] = src[r][c] for a rows x cols row-major BF16 matrix
+hipError_t launch_transpose_bf16(const bf16* src, bf16* dst, int rows, int cols,
+                                 hipStream_t s);
 hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
 hipError_t launch_targets(const TargetArgs& a, hipStream_t s);
 hipError_t launch_fill_ones_col(bf16* h, int B, int ld, int col, hipStream_t s);

@@ -65,7 +65,7 @@ template <int MODE>
 __global__ __launch_bounds__(kMlpThreads) void k_mlp_gemm(MlpGemm g) {
     __shared__ bf16 As[TM][LDK];
     __shared__ bf16 Bs[TN][LDK];
-    __shared__ double red[TM][2];
+    __shared__ double red[4];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int li = lane & 31, lh = lane >> 5;
@@ -116,30 +116,12 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_gemm(MlpGemm g) {
     // Output (i, j) of a 32x32 block: lane j + 32 * ((i / 4) % 2),
     // register (i / 8) * 4 + i % 4.
     double lsum = 0.0;
-    // fused likelihood: a lane always sees the same two columns, so their
-    // data terms are formed once; ln mu is the network output itself, so
-    // n ln(n/mu) = n ln n - n ln mu needs one exponential per output and no
-    // logarithm
-    double cn[2] = {0.0, 0.0}, nob[2] = {0.0, 0.0}, mn[2] = {0.0, 0.0}, sd[2] = {0.0, 0.0};
-    if (MODE == kMlpNll) {
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) {
-            const int n = n0 + wn * 64 + bj * 32 + li;
-            if (n < g.N) {
-                nob[bj] = g.nobs[n];
-                cn[bj] = nob[bj] > 0.0 ? nob[bj] * log(nob[bj]) - nob[bj] : 0.0;
-                mn[bj] = g.mean[n];
-                sd[bj] = g.stdv[n];
-            }
-        }
-    }
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int i = wm * 64 + bi * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
             const int m = m0 + i;
-            double rowpart = 0.0;
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) {
                 const int n = n0 + wn * 64 + bj * 32 + li;
@@ -159,35 +141,123 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_gemm(MlpGemm g) {
                     const float sg = 1.f / (1.f + __expf(-z));
                     g.C16[(long)m * g.ldc16 + n] = (bf16)(v * sg * (1.f + z * (1.f - sg)));
                 } else if (MODE == kMlpLogMu) {
-                    g.C32[(long)m * g.ldc + n] = g.mean[n] + g.stdv[n] * v;
-                } else if (MODE == kMlpNll) {
-                    // deviance mu - n + n ln(n / mu), ln mu kept in FP64
-                    const double lm = fma(sd[bj], (double)v, mn[bj]);
-                    const double mu = (double)__expf((float)lm);
-                    rowpart += mu + cn[bj] - nob[bj] * lm;
+                    g.C32[(long)m * g.ldc + n] = fmaf(g.stdv[n], v, g.mean[n]);
                 }
             }
-            if (MODE == kMlpNll) {
-#pragma unroll
-                for (int o = 16; o > 0; o >>= 1) rowpart += __shfl_xor(rowpart, o, 64);
-                if (li == 0) red[i][wn] = rowpart;
-            }
         }
-    }
-    if (MODE == kMlpNll) {
-        __syncthreads();
-        if (tid < TM && m0 + tid < g.M)
-            g.part[(long)(m0 + tid) * g.n_nt + blockIdx.x] = red[tid][0] + red[tid][1];
     }
     if (MODE == kMlpMse) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o, 64);
-        if (lane == 0) red[wave][0] = lsum;
+        if (lane == 0) red[wave] = lsum;
         __syncthreads();
         if (tid == 0)
             g.tile_loss[blockIdx.y * gridDim.x + blockIdx.x] =
-                red[0][0] + red[1][0] + red[2][0] + red[3][0];
+                red[0] + red[1] + red[2] + red[3];
     }
+}
+
+// Inference output layer fused with the Poisson likelihood: per point m and
+// bin n, ln mu = mean_n + std_n (W h_m)_n (FP32, as the log-mu output forms
+// it), mu = exp(ln mu), and the point's sum over all bins of mu - n_n ln mu
+// (FP64; the data terms lnGamma(n + 1) are added by the finishing kernel).
+// One work-group per 128 points and group of bins (gridDim.y groups, so
+// that small batches still fill the chip), persistent over its bins: the
+// points' hidden activations (all of K <= 272) stay in LDS for the launch,
+// and each wave takes 32 bins of every 128-bin step, with the weights of
+// those bins loaded straight from memory (L2-resident) into the registers
+// that feed the matrix instruction: 17 independent 16-byte loads per lane,
+// issued together, then 68 matrix instructions with no barrier.  The bins
+// are the instruction's row operand and the points its column operand, so
+// a lane holds 16 bins of one point in each 32 x 32 block (lane = point +
+// 32 * half, register r = bin (r / 4) * 8 + half * 4 + r % 4) and the sum
+// over bins stays in registers until the end.
+constexpr int kNllKS = 17;                  // K steps of 16: K <= 272
+constexpr int kNllLda = kNllKS * 16 + 8;    // A row stride in LDS (bf16)
+
+__global__ __launch_bounds__(kMlpThreads, 2) void k_mlp_nll(MlpGemm g) {
+    __shared__ bf16 As[TM][kNllLda];        // points x k
+    __shared__ double cbuf[4][3][32];       // per wave: its 32 bins' constants
+    __shared__ double red[4][TM];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 31, lh = lane >> 5;
+    const int m0 = blockIdx.x * TM;
+    constexpr int CH = kNllKS * 2;          // 16-byte chunks per row
+    for (int q = tid; q < TM * CH; q += kMlpThreads) {
+        const int row = q / CH, k = (q % CH) * 8, m = m0 + row;
+        const uint4 v = (m < g.M && k < g.K)
+                            ? *reinterpret_cast<const uint4*>(g.A + (long)m * g.sam + k)
+                            : make_uint4(0u, 0u, 0u, 0u);
+        *reinterpret_cast<uint4*>(&As[row][k]) = v;
+    }
+    __syncthreads();
+    double pp[4] = {0.0, 0.0, 0.0, 0.0};
+    const int nbt = (g.N + TN - 1) / TN;
+    const int bt0 = (int)((long)nbt * blockIdx.y / gridDim.y);
+    const int bt1 = (int)((long)nbt * (blockIdx.y + 1) / gridDim.y);
+    for (int bt = bt0; bt < bt1; ++bt) {
+        const int nl = bt * TN + wave * 32 + li;   // this lane's bin for loads
+        const bool okn = nl < g.N;
+        uint4 bf[kNllKS];
+#pragma unroll
+        for (int ks = 0; ks < kNllKS; ++ks) {
+            const int k = ks * 16 + lh * 8;
+            bf[ks] = (okn && k < g.K)
+                         ? *reinterpret_cast<const uint4*>(g.B + (long)nl * g.sbn + k)
+                         : make_uint4(0u, 0u, 0u, 0u);
+        }
+        const double cm = okn ? (double)g.mean[nl] : 0.0;
+        const double cs = okn ? (double)g.stdv[nl] : 0.0;
+        const double cn = okn ? g.nobs[nl] : 0.0;
+        f32x16 acc[4];
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[y][r] = 0.f;
+#pragma unroll
+        for (int ks = 0; ks < kNllKS; ++ks) {
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&bf[ks]);
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[y * 32 + li][ks * 16 + lh * 8]);
+                acc[y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b, a, acc[y], 0, 0, 0);
+            }
+        }
+        // the wave's 32 bins' constants, shared through its own LDS slots
+        if (lh == 0) {
+            cbuf[wave][0][li] = cm;
+            cbuf[wave][1][li] = cs;
+            cbuf[wave][2][li] = cn;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = (r >> 2) * 8 + lh * 4 + (r & 3);
+            if (bt * TN + wave * 32 + i >= g.N) continue;
+            const float mean = (float)cbuf[wave][0][i], sd = (float)cbuf[wave][1][i];
+            const double nob = cbuf[wave][2][i];
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const float lm = fmaf(sd, acc[y][r], mean);
+                const double mu = (double)__expf(lm);
+                pp[y] += fma(-nob, (double)lm, mu);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+#pragma unroll
+    for (int y = 0; y < 4; ++y) {
+        pp[y] += __shfl_xor(pp[y], 32, 64);
+        if (lh == 0) red[wave][y * 32 + li] = pp[y];
+    }
+    __syncthreads();
+    if (tid < TM && m0 + tid < g.M)
+        g.part[(long)(m0 + tid) * g.n_nt + blockIdx.y] =
+            red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
 }
 
 __global__ void k_mlp_input(MlpInput a) {
@@ -234,6 +304,14 @@ __global__ void k_ones_col(bf16* h, int B, int ld, int col) {
     for (int c = col + 1; c < ld; ++c) h[(long)p * ld + c] = (bf16)0.f;
 }
 
+__global__ void k_transpose_bf16(const bf16* __restrict__ src, bf16* __restrict__ dst,
+                                 int rows, int cols) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)rows * cols) return;
+    const long r = e / cols, c = e % cols;
+    dst[c * rows + r] = src[e];
+}
+
 // Sum of the K-split slabs of a GEMM, one element per thread, with the
 // epilogue of the split GEMM (plain FP32 store, or SiLU').
 __global__ __launch_bounds__(256) void k_mlp_ksum(KSumArgs a) {
@@ -273,10 +351,26 @@ hipError_t launch_mlp_gemm(int mode, const MlpGemm& g, hipStream_t s) {
         case kMlpSilu: hipLaunchKernelGGL(k_mlp_gemm<kMlpSilu>, grid, dim3(kMlpThreads), 0, s, g); break;
         case kMlpMse: hipLaunchKernelGGL(k_mlp_gemm<kMlpMse>, grid, dim3(kMlpThreads), 0, s, g); break;
         case kMlpDSilu: hipLaunchKernelGGL(k_mlp_gemm<kMlpDSilu>, grid, dim3(kMlpThreads), 0, s, g); break;
-        case kMlpNll: hipLaunchKernelGGL(k_mlp_gemm<kMlpNll>, grid, dim3(kMlpThreads), 0, s, g); break;
+        case kMlpNll:
+            // the whole reduction in LDS, k contiguous in both operands
+            // (n_nt bin groups, at most one per 128 bins)
+            if (g.K > kNllKS * 16 || g.sak != 1 || g.sbk != 1 || g.n_nt < 1 ||
+                g.n_nt > (g.N + TN - 1) / TN)
+                return hipErrorInvalidValue;
+            hipLaunchKernelGGL(k_mlp_nll, dim3((g.M + TM - 1) / TM, g.n_nt), dim3(kMlpThreads),
+                               0, s, g);
+            break;
         case kMlpLogMu: hipLaunchKernelGGL(k_mlp_gemm<kMlpLogMu>, grid, dim3(kMlpThreads), 0, s, g); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_bf16(const bf16* src, bf16* dst, int rows, int cols,
+                                 hipStream_t s) {
+    const long n = (long)rows * cols;
+    hipLaunchKernelGGL(k_transpose_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       src, dst, rows, cols);
     return hipGetLastError();
 }
 

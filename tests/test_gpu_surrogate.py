@@ -127,14 +127,13 @@ def test_surrogate_accuracy_and_fallback(trained, torch_dev):
     dvs = np.sum(mu_h - nobs + np.where(nobs > 0, nobs * (np.log(np.where(nobs > 0, nobs, 1)) - lm), 0.0), axis=1)
     ref = 2.0 * (dvs + cdata)
     fused = nll_s[:256].cpu().numpy()
-    # the two sides see ln mu and mu differently: the host's ln mu comes
-    # from the log-mu output, formed as mean + std * y in FP32 (2^-24 |ln mu|),
-    # while the fused epilogue forms ln mu in FP64 and mu = 2^(ln mu log2 e)
-    # in FP32 from ln mu rounded to FP32 (2^-24 |ln mu| each for that
-    # rounding and the scaled argument, ~2^-22 for the exponential and the
-    # result).  The deviance moves by (mu_j - n_j) per unit of relative
-    # change in mu_j or of change in ln mu_j, so the two -2lnL may differ by
-    # 2 sum_j |mu_j - n_j| (2^-22 |ln mu_j| + 2^-21), with margin
+    # both sides form ln mu = mean + std * y by the same FP32 fused
+    # multiply-add; the fused kernel then takes mu = 2^(ln mu log2 e) in FP32
+    # (2^-24 |ln mu| for the scaled argument, ~2^-22 for the exponential and
+    # the result) where the host takes an FP64 exponential.  The deviance
+    # moves by (mu_j - n_j) per unit of relative change in mu_j, so the two
+    # -2lnL may differ by 2 sum_j |mu_j - n_j| (2^-22 |ln mu_j| + 2^-21),
+    # with margin
     bound = 2.0 * np.sum(np.abs(mu_h - nobs) * (np.abs(lm) * 2.0 ** -22 + 2.0 ** -21), axis=1)
     assert np.all(np.abs(fused - ref) <= bound + 1e-9 * np.abs(ref) + 1e-6), \
         np.max(np.abs(fused - ref) - bound)

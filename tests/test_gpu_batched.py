@@ -161,7 +161,11 @@ def test_grouped_scan_shapes():
     for d, p in enumerate(probs):
         o = p["oracle"]
         th, nll_d, g_d = ths[d], nl[d].cpu().numpy(), gr[d].cpu().numpy()
-        assert np.array_equal(nll_d, outs[d]), d
+        # the likelihood-only call and the call with the gradient are tuned
+        # separately and may run different tile shapes, whose column-tile
+        # partial sums group the deviance differently: equal up to rounding
+        assert np.allclose(nll_d, outs[d], rtol=1e-12, atol=0.0), \
+            (d, float(np.max(np.abs(nll_d - outs[d]))))
         P = len(th)
         for i in sorted({0, P // 3, P - 1}):
             v, rg = o.nll_grad(th[i])

@@ -498,6 +498,47 @@ def gemm_counter_pass():
     log("[bench] GEMM counter pass done: 8 calls of 2 x 1024 x 4096 x 4096 flop")
 
 
+def mlp_counter_pass():
+    """The surrogate network's kernels alone, for matrix-core counters: a
+    7-256-256-256-4096 network (random weights; the work does not depend
+    on them), 8 training steps of 2048 points, then 8 inference calls of
+    65536 points through the fused output-layer likelihood kernel.  Data
+    and response are 4096 bins of a 512-row synthetic analysis (the network
+    never reads the response)."""
+    import torch
+    import synth
+    import paper_2607_00488_amd as nr
+    from paper_2607_00488_amd.surrogate import Surrogate, init_params
+    dev = torch.device("cuda:0")
+    g = synth.rng(2201)
+    n_t, n_reco = 512, 4096
+    R = (g.random((n_t, n_reco), dtype=np.float32) / n_reco).astype(np.float32)
+    ctx = nr.Context(0)
+    ctx.set_sources(synth.source_nodes(256), n_t)
+    ctx.set_response(R, n_sig=1.0e4)
+    ctx.set_data(g.poisson(10.0, n_reco).astype(np.float64), np.full(n_reco, 10.0))
+    lo, hi = synth.theta_box()
+    sur = Surrogate(n_reco, lo, hi, hidden=256, seed=2202)
+    sur.set_params(init_params(256, n_reco, 2203, out_scale=1.0))
+    nr.nr_mlp_set_output_norm(sur.h, np.full(n_reco, 2.0, np.float32),
+                              np.full(n_reco, 0.3, np.float32))
+    th = sur.sample_box(2048, 2204)
+    tg = torch.randn(2048, n_reco, dtype=torch.float32, device=dev,
+                     generator=torch.Generator(device=dev).manual_seed(2205))
+    s = torch.cuda.current_stream(dev)
+    for _ in range(8):
+        nr.nr_mlp_train_step_dev(sur.h, th.data_ptr(), tg.data_ptr(), 2048, 1e-4,
+                                 False, s.cuda_stream)
+    thi = sur.sample_box(1 << 16, 2206)
+    for _ in range(8):
+        sur.nll(ctx, thi)
+    torch.cuda.synchronize()
+    sur.close()
+    ctx.close()
+    log("[bench] MLP counter pass done: 8 training steps of 2048, 8 inference "
+        "calls of 65536 points")
+
+
 def tmpl_counter_pass():
     """The template form's evaluation kernels alone, for instruction
     counters: 65536 points over 4096 observed bins (the per-point cost does
@@ -596,6 +637,10 @@ def main():
                     help="short run for matrix-core counters: the batched "
                          "likelihood GEMM of 1024 points on a 4096 x 4096 "
                          "dataset (a shape of the 64-dataset scan), 8 calls")
+    ap.add_argument("--mlp-counter-pass", action="store_true",
+                    help="short run for matrix-core counters of the surrogate "
+                         "network: 8 training steps of 2048 points, 8 fused "
+                         "inference calls of 65536 points")
     ap.add_argument("--tmpl-counter-pass", action="store_true",
                     help="short run for instruction counters: the template "
                          "form's evaluation on 65536 points x 4096 bins, "
@@ -618,6 +663,9 @@ def main():
         return
     if args.tmpl_counter_pass:
         tmpl_counter_pass()
+        return
+    if args.mlp_counter_pass:
+        mlp_counter_pass()
         return
     p = build_plain(1)
     ctx, c = p["ctx"], p["cfg"]

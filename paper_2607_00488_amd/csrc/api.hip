@@ -215,6 +215,12 @@ struct nr_ctx {
     double *d_th = nullptr, *d_out = nullptr, *d_grad = nullptr;
     double *d_mu = nullptr, *d_w = nullptr;
     size_t cap_pts = 0, cap_mu = 0, cap_w = 0;
+    // pinned host staging of the synchronous likelihood entry points: the
+    // kernels read theta from it and write -2lnL and the gradient into it
+    // directly, so a call needs no copy between host and device
+    double *h_th = nullptr, *h_out = nullptr, *h_grad = nullptr;
+    double *hd_th = nullptr, *hd_out = nullptr, *hd_grad = nullptr;  // device views
+    size_t h_cap = 0;
     double* d_thsm = nullptr;
     double* d_tnll = nullptr;  // [1] output of timing-only launches
     double* d_nev = nullptr;   // [n_t] MC events per true recoil row
@@ -359,6 +365,40 @@ int choose_tiling(nr_ctx* c, int rows_req) {
     c->adj_grid = nr::adjoint_grid(c->n_t);
     if ((rc = dalloc(&c->d_jpart, (size_t)c->adj_grid * nr::kNBasis))) return rc;
     clear_graphs(c);
+    return 0;
+}
+
+void free_pinned(nr_ctx* c) {
+    if (c->h_cap) (void)hipDeviceSynchronize();  // no launch still reads them
+    for (double** p : {&c->h_th, &c->h_out, &c->h_grad}) {
+        if (*p) (void)hipHostFree(*p);
+        *p = nullptr;
+    }
+    c->hd_th = c->hd_out = c->hd_grad = nullptr;
+    c->h_cap = 0;
+}
+
+// Pinned, device-accessible host buffers for pts points (theta, -2lnL and
+// gradient of any form).
+int ensure_pinned(nr_ctx* c, size_t pts) {
+    if (pts <= c->h_cap) return 0;
+    free_pinned(c);
+    clear_graphs(c);  // cached graphs hold the old addresses
+    const size_t n = std::max(pts, (size_t)64);
+    struct Buf { double** h; double** d; size_t len; };
+    for (const Buf& b : {Buf{&c->h_th, &c->hd_th, n * nr::kMaxTheta},
+                         Buf{&c->h_out, &c->hd_out, n},
+                         Buf{&c->h_grad, &c->hd_grad, n * nr::kMaxTheta}}) {
+        hipError_t e = hipHostMalloc((void**)b.h, b.len * sizeof(double), hipHostMallocMapped);
+        if (e == hipSuccess) e = hipHostGetDevicePointer((void**)b.d, *b.h, 0);
+        if (e != hipSuccess) {
+            c->h_cap = n;  // free what exists
+            free_pinned(c);
+            return fail(NR_ENOMEM, "pinned staging of %zu bytes: %s", b.len * sizeof(double),
+                        hipGetErrorString(e));
+        }
+    }
+    c->h_cap = n;
     return 0;
 }
 
@@ -1174,6 +1214,7 @@ void nr_destroy(nr_ctx* c) {
     dfree(&c->d_bmu); dfree(&c->d_gctr);
     dfree(&c->d_trec); dfree(&c->d_tdp); dfree(&c->d_thp); dfree(&c->d_tred);
     dfree(&c->d_v[0]); dfree(&c->d_v[1]);
+    free_pinned(c);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     (void)hipStreamDestroy(c->stream);
@@ -1477,6 +1518,19 @@ static int eval_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
     if ((grad || w) && (rc = check_single(c))) return rc;
     if ((rc = check_theta(theta, n_pts, c->n_theta))) return rc;
     if ((rc = set_device(c))) return rc;
+    if (!mu && !w) {
+        // likelihood (and gradient): theta in and -2lnL out through pinned
+        // host memory the kernels read and write directly, no copies
+        if ((rc = ensure_pinned(c, n_pts))) return rc;
+        std::memcpy(c->h_th, theta, sizeof(double) * n_pts * c->n_theta);
+        rc = run_points(c, c->hd_th, n_pts, c->hd_out, grad ? c->hd_grad : nullptr,
+                        nullptr, nullptr, c->stream);
+        if (rc) return rc;
+        HIPCHK(hipStreamSynchronize(c->stream));
+        std::memcpy(nll, c->h_out, sizeof(double) * n_pts);
+        if (grad) std::memcpy(grad, c->h_grad, sizeof(double) * n_pts * NR_NTHETA);
+        return 0;
+    }
     const size_t mu_elems = mu ? (size_t)n_pts * c->n_reco : 0;
     const size_t w_elems = w ? (size_t)n_pts * c->n_rows : 0;
     if ((rc = ensure_stage(c, n_pts, mu_elems, w_elems))) return rc;
@@ -2631,6 +2685,19 @@ static int tmpl_sync(nr_ctx* c, const double* theta, int n_pts, double* nll,
     if ((rc = check_ready(c))) return rc;
     if ((rc = check_theta(theta, n_pts, c->n_theta))) return rc;
     if ((rc = set_device(c))) return rc;
+    if (!mu) {
+        // theta in and -2lnL out through pinned host memory, no copies
+        if ((rc = ensure_pinned(c, n_pts))) return rc;
+        if ((rc = ensure_tmpl(c, n_pts, grad != nullptr))) return rc;
+        std::memcpy(c->h_th, theta, sizeof(double) * n_pts * c->n_theta);
+        if ((rc = enqueue_tmpl(c, c->hd_th, n_pts, c->hd_out, grad ? c->hd_grad : nullptr,
+                               nullptr, c->stream)))
+            return rc;
+        HIPCHK(hipStreamSynchronize(c->stream));
+        std::memcpy(nll, c->h_out, sizeof(double) * n_pts);
+        if (grad) std::memcpy(grad, c->h_grad, sizeof(double) * n_pts * c->n_theta);
+        return 0;
+    }
     if ((rc = ensure_stage(c, n_pts, mu ? (size_t)n_pts * c->n_reco : 0, 0))) return rc;
     if ((rc = ensure_tmpl(c, n_pts, grad != nullptr))) return rc;
     HIPCHK(hipMemcpyAsync(c->d_th, theta, sizeof(double) * n_pts * c->n_theta,

@@ -247,6 +247,47 @@ def asimov_scan_form(p):
     return out
 
 
+def banded_form(ctx, R, tt, dense_out, stream):
+    """The same scan with band skipping on: the fold and the adjoint read
+    only the column bands of R that hold non-zero responses.  The results
+    are compared bit for bit with the dense scan just timed; the bytes a
+    banded fold must read at least are each row's non-zero band (in 16-byte
+    column groups) plus the per-row and per-bin inputs."""
+    import torch
+    nz = R != 0
+    any_nz = nz.any(axis=1)
+    n_reco = R.shape[1]
+    lo = np.where(any_nz, np.argmax(nz, axis=1), 0)
+    hi = np.where(any_nz, n_reco - np.argmax(nz[:, ::-1], axis=1), 0)
+    band_bytes = int(np.sum(np.where(any_nz, ((hi + 3) // 4 - lo // 4) * 16, 0)))
+    alg = band_bytes + 16 * R.shape[0] + 16 * n_reco
+    ctx.set_band_skipping(True)
+    out = torch.empty_like(dense_out)
+    ctx.eval_nll_dev(tt, out, stream=stream)          # capture + run
+    stream.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    ctx.eval_nll_dev(tt, out, stream=stream)
+    ev1.record(stream)
+    stream.synchronize()
+    dt = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1)
+    ctx.set_band_skipping(False)
+    n = tt.shape[0]
+    us = dev_ms * 1e3 / n
+    return dict(evals_per_s=round(n / dt, 1), points=n, us_per_eval=round(us, 2),
+                bitwise_equal_to_dense=bool(torch.equal(out, dense_out)),
+                band_fraction=round(band_bytes / (4.0 * R.size), 4),
+                band_bytes_per_eval=alg,
+                band_gbs=round(alg / (us * 1e-6) / 1e9, 1),
+                what="the headline scan with band skipping: each fold tile reads "
+                     "only the columns where its rows' responses are non-zero "
+                     "(exact zeros elsewhere); results bitwise those of the "
+                     "dense read")
+
+
 def surrogate_ceiling(ctx, sur, n_data, th_val, ks=(16, 32, 64)):
     """How far the trained network's -2lnL is from the exact one, and how
     far first-order corrections from exact linear functionals of mu would
@@ -780,6 +821,10 @@ def main():
                            fold_alone_us=round(fold_ms * 1e3, 2),
                            fold_plus_likelihood_us=round(fold_lik_ms * 1e3, 2)))
     forms = {}
+    forms["plain_banded"] = banded_form(ctx, p["R"], tt, out, stream)
+    log(f"[bench] plain with band skipping: "
+        f"{forms['plain_banded']['evals_per_s']:.0f} evals/s, bitwise equal: "
+        f"{forms['plain_banded']['bitwise_equal_to_dense']}")
     # the FP64 matrix-core rate the chip sustains on register operands: the
     # practical ceiling of the batched GEMM beside the data-sheet 78.6
     import paper_2607_00488_amd as nr

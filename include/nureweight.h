@@ -145,6 +145,22 @@ int nr_eval_mu(nr_ctx *ctx, const double *theta, int n_pts, double *mu);
 int nr_eval_nll_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
                     double *d_nll, double *d_grad, void *stream);
 
+/* Band skipping in the single-point path.  The conditional response
+ * R_ij = P(E_vis,j | T_i) of Sec. II.D (Eq. (visible_spectrum)) is non-zero
+ * only within a few resolution widths of the light an electron of recoil
+ * T_i makes, so every row of R, and every 128-row fold tile, has a column
+ * band outside which all entries are exact zeros (nr_set_response and
+ * nr_set_components record the bands).  With `on` non-zero the fold of
+ * Eq. (matrix_reweight) and the adjoint pass of the gradient read only the
+ * 16-byte column groups inside those bands and write zero partial sums for
+ * the rest.  The skipped terms are exact zeros and no sum changes order,
+ * so every result is bitwise the one of the full read.  Off by default:
+ * the full dense read of R, as the method is written.  Applies to
+ * nr_eval_nll, nr_eval_nll_grad, nr_eval_mu, nr_eval_nll_dev and
+ * nr_eval_nll_dev_noalloc; NR_EINVAL for a null context, NR_ESTATE before
+ * a response is set. */
+int nr_set_band_skipping(nr_ctx *ctx, int on);
+
 /* Size in bytes of the static workspace of nr_eval_nll_dev_noalloc, one per
  * device. */
 #define NR_NOALLOC_WORKSPACE_BYTES 16777216

@@ -25,7 +25,7 @@ NR_NOALLOC_WORKSPACE_BYTES = 16 << 20
 EXPORTS = (
     "nr_create", "nr_destroy", "nr_set_sources", "nr_set_response",
     "nr_set_data", "nr_eval_nll", "nr_eval_nll_grad", "nr_eval_mu",
-    "nr_eval_nll_dev", "nr_eval_nll_dev_noalloc", "nr_eval_weights", "nr_get_reference", "nr_stream",
+    "nr_eval_nll_dev", "nr_eval_nll_dev_noalloc", "nr_set_band_skipping", "nr_eval_weights", "nr_get_reference", "nr_stream",
     "nr_set_mc_events", "nr_eval_ess", "nr_set_components", "nr_num_theta",
     "nr_time_stage", "nr_set_fold_tiling", "nr_last_error",
     "nr_eval_nll_batched", "nr_eval_nll_grad_batched", "nr_eval_mu_batched",
@@ -111,6 +111,7 @@ def load():
     L.nr_eval_ess.argtypes = [P, pD, I, pD]
     L.nr_eval_nll_dev.argtypes = [P, P, I, P, P, P]
     L.nr_eval_nll_dev_noalloc.argtypes = [P, P, I, P, P, P]
+    L.nr_set_band_skipping.argtypes = [P, I]
     L.nr_get_reference.argtypes = [P, pD, pD]
     L.nr_stream.argtypes = [P]
     L.nr_stream.restype = P
@@ -316,6 +317,10 @@ def nr_eval_nll_dev(h, d_theta_ptr, n_pts, d_nll_ptr, d_grad_ptr=None,
                                   C.c_void_p(d_nll_ptr),
                                   C.c_void_p(d_grad_ptr or 0),
                                   C.c_void_p(stream_ptr or 0)))
+
+
+def nr_set_band_skipping(h, on):
+    _check(load().nr_set_band_skipping(h, 1 if on else 0))
 
 
 def nr_eval_nll_dev_noalloc(h, d_theta_ptr, n_pts, d_nll_ptr, d_grad_ptr=None,
@@ -608,6 +613,11 @@ class Context:
 
     def time_stage(self, stage, iters=100):
         return nr_time_stage(self.h, stage, iters)
+
+    def set_band_skipping(self, on=True):
+        """Read only the non-zero column bands of R in the single-point
+        path (bitwise the same results)."""
+        nr_set_band_skipping(self.h, on)
 
     def set_fold_tiling(self, rows_per_wg=0, use_graph=-1):
         nr_set_fold_tiling(self.h, rows_per_wg, use_graph)

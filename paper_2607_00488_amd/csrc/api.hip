@@ -189,6 +189,12 @@ struct nr_ctx {
     // response
     int n_reco = 0, ldr = 0;
     float* d_R = nullptr;
+    // per response row the float4 columns [lo, hi) holding its non-zero
+    // entries (host and device), and per fold tile the same for its rows;
+    // read by the fold and the adjoint only when band skipping is on
+    std::vector<int> rowband;
+    int *d_rowband = nullptr, *d_tileband = nullptr;
+    bool skip_zero = false;
     bool m_user = false;
     double n_sig = 0;
     std::vector<double> mrow;
@@ -342,6 +348,53 @@ int upload_mrow(nr_ctx* c) {
     return 0;
 }
 
+// Non-zero column band of every response row (float4 units, [lo, hi); an
+// all-zero row gets lo = hi = 0), from the host copy of the stacked rows.
+int set_row_bands(nr_ctx* c, const float* R, int n_rows, int n_cols, size_t ld) {
+    c->rowband.assign((size_t)2 * n_rows, 0);
+    for (int l = 0; l < n_rows; ++l) {
+        const float* r = R + (size_t)l * ld;
+        int lo = 0, hi = n_cols;
+        while (lo < n_cols && r[lo] == 0.0f) ++lo;
+        while (hi > lo && r[hi - 1] == 0.0f) --hi;
+        if (lo < hi) {
+            c->rowband[2 * (size_t)l] = lo / 4;
+            c->rowband[2 * (size_t)l + 1] = (hi + 3) / 4;
+        }
+    }
+    int rc;
+    if ((rc = dalloc(&c->d_rowband, c->rowband.size()))) return rc;
+    HIPCHK(hipMemcpy(c->d_rowband, c->rowband.data(), sizeof(int) * c->rowband.size(),
+                     hipMemcpyHostToDevice));
+    return 0;
+}
+
+// Band of every fold tile (the union of its rows' bands, clipped to the
+// tile's columns), in the fold's tile order cc * n_rb + rb.
+int set_tile_bands(nr_ctx* c) {
+    constexpr int kTile4 = 512;  // float4 columns per fold tile
+    std::vector<int> tb((size_t)2 * c->n_rb * c->n_fc);
+    for (int cc = 0; cc < c->n_fc; ++cc)
+        for (int rb = 0; rb < c->n_rb; ++rb) {
+            const int c0 = cc * kTile4, c1 = c0 + kTile4;
+            int lo = c1, hi = c0;
+            const int l1 = std::min(c->n_rows, (rb + 1) * c->rows_per_wg);
+            for (int l = rb * c->rows_per_wg; l < l1; ++l) {
+                const int a = c->rowband[2 * (size_t)l], b = c->rowband[2 * (size_t)l + 1];
+                if (a >= b) continue;
+                lo = std::min(lo, std::max(a, c0));
+                hi = std::max(hi, std::min(b, c1));
+            }
+            const size_t t = (size_t)cc * c->n_rb + rb;
+            tb[2 * t] = lo < hi ? lo : c0;
+            tb[2 * t + 1] = lo < hi ? hi : c0;
+        }
+    int rc;
+    if ((rc = dalloc(&c->d_tileband, tb.size()))) return rc;
+    HIPCHK(hipMemcpy(c->d_tileband, tb.data(), sizeof(int) * tb.size(), hipMemcpyHostToDevice));
+    return 0;
+}
+
 int choose_tiling(nr_ctx* c, int rows_req) {
     c->n_fc = (c->ldr / 4 + 511) / 512;   // fold tiles are 2048 columns wide
     c->n_cc = (c->n_reco + 63) / 64;      // reduction groups of 64 columns
@@ -364,6 +417,7 @@ int choose_tiling(nr_ctx* c, int rows_req) {
     if ((rc = dalloc(&c->d_chunk_gb, (size_t)2 * c->n_cc))) return rc;
     c->adj_grid = nr::adjoint_grid(c->n_t);
     if ((rc = dalloc(&c->d_jpart, (size_t)c->adj_grid * nr::kNBasis))) return rc;
+    if ((rc = set_tile_bands(c))) return rc;
     clear_graphs(c);
     return 0;
 }
@@ -534,6 +588,7 @@ nr::FoldArgs fold_args(nr_ctx* c, const double* thp, const double* v,
     fa.n_fc = c->n_fc;
     fa.n_cc = c->n_cc;
     fa.reverse = 0;
+    fa.band = c->skip_zero ? c->d_tileband : nullptr;
     // responses beyond twice the 256 MB Infinity Cache stream past it
     fa.stream_nt = (double)c->n_rows * c->ldr * sizeof(float) > 512.0e6;
     return fa;
@@ -639,6 +694,7 @@ int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
         aa.theta = thp(p);
         aa.gb = wk->gb;
         aa.jpart = wk->jpart;
+        aa.rowband = c->skip_zero ? c->d_rowband : nullptr;
         aa.out_grad = grad + (size_t)p * NR_NTHETA;
         for (int i = 0; i < NR_NTHETA; ++i) {
             aa.pull_mean[i] = c->pull_mean[i];
@@ -1214,6 +1270,7 @@ void nr_destroy(nr_ctx* c) {
     dfree(&c->d_bmu); dfree(&c->d_gctr);
     dfree(&c->d_trec); dfree(&c->d_tdp); dfree(&c->d_thp); dfree(&c->d_tred);
     dfree(&c->d_v[0]); dfree(&c->d_v[1]);
+    dfree(&c->d_rowband); dfree(&c->d_tileband);
     free_pinned(c);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
@@ -1412,6 +1469,7 @@ int nr_set_response(nr_ctx* c, const float* R, int n_t, int n_reco,
         HIPCHK(hipMemset(c->d_R, 0, sizeof(float) * (size_t)n_t * c->ldr));
     HIPCHK(hipMemcpy2D(c->d_R, sizeof(float) * c->ldr, R, sizeof(float) * n_reco,
                        sizeof(float) * n_reco, n_t, hipMemcpyHostToDevice));
+    if ((rc = set_row_bands(c, R, n_t, n_reco, n_reco))) return rc;
     if ((rc = dalloc(&c->d_mrow, n_t))) return rc;
     if ((rc = dalloc(&c->d_a, c->ldr))) return rc;
     c->m_user = m != nullptr;
@@ -1741,6 +1799,7 @@ int nr_set_components(nr_ctx* c, const nr_components* k, int n_reco) {
         HIPCHK(hipMemcpy(c->d_mask, k->mask, sizeof(double) * n_reco, hipMemcpyHostToDevice));
     }
     HIPCHK(hipMemcpy(c->d_R, Rs.data(), sizeof(float) * Rs.size(), hipMemcpyHostToDevice));
+    if ((rc = set_row_bands(c, Rs.data(), (int)n_rows, n_reco, ldr))) return rc;
     HIPCHK(hipMemcpy(c->d_mrow, mrow.data(), sizeof(double) * n_rows, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_bkg, bkg.data(), sizeof(double) * bkg.size(), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c->d_compoff, off.data(), sizeof(int) * (K + 1), hipMemcpyHostToDevice));
@@ -1805,6 +1864,17 @@ int nr_set_fold_tiling(nr_ctx* c, int rows_per_wg, int use_graph) {
         if ((rc = set_device(c))) return rc;
         HIPCHK(hipStreamSynchronize(c->stream));
         return choose_tiling(c, rows_per_wg);
+    }
+    return 0;
+}
+
+int nr_set_band_skipping(nr_ctx* c, int on) {
+    const ApiLock api_lock;
+    if (!c) return fail(NR_EINVAL, "null context");
+    if (!c->have_rsp) return fail(NR_ESTATE, "band skipping needs a response first");
+    if ((on != 0) != c->skip_zero) {
+        c->skip_zero = on != 0;
+        clear_graphs(c);  // cached graphs hold the other setting
     }
     return 0;
 }

@@ -86,6 +86,9 @@ struct FoldArgs {
     int n_cc;             // reduction groups (64 columns each)
     int reverse;          // fold: walk the tile's rows last to first
     int stream_nt;        // fold: read R without cache allocation
+    // fold: per tile (index cc * n_rb + rb) the float4 columns [lo, hi) that
+    // hold its rows' non-zero responses, or null (read every column)
+    const int* band;
 };
 
 // One launch of the single-point step kernel: nb_fold = n_rb * n_fc
@@ -113,6 +116,9 @@ struct AdjArgs {
     const double* theta;
     const double* gb;     // [1]
     double* jpart;        // [grid][kNBasis]
+    // per row the float4 columns [lo, hi) holding its non-zero responses,
+    // or null (read every column)
+    const int* rowband;
     double* out_grad;     // [7]
     double pull_mean[kNTheta];
     double pull_sigma[kNTheta];

@@ -224,7 +224,11 @@ __device__ void fold_role(const FoldArgs& a, int rb, int cc, double* smem) {
     const int tid = threadIdx.x;
     const int ld4 = a.ldr >> 2;
     const int c4 = cc * kFoldTile4 + tid;
-    const bool colok = c4 < ld4;
+    const bool incol = c4 < ld4;
+    // with band skipping, columns outside the tile's non-zero band hold
+    // exact zeros: their sums are zero without reading them
+    const int* bd = a.band ? a.band + 2 * ((size_t)cc * a.n_rb + rb) : nullptr;
+    const bool colok = incol && (!bd || (c4 >= bd[0] && c4 < bd[1]));
     const float4* __restrict__ Rp =
         reinterpret_cast<const float4*>(a.R) + (size_t)row0 * ld4 + c4;
     constexpr int U = kFoldUnroll;
@@ -240,7 +244,12 @@ __device__ void fold_role(const FoldArgs& a, int rb, int cc, double* smem) {
     }
     for (int q = tid; q < nrows; q += kStepThreads) vs[q] = a.v[row0 + q];
     __syncthreads();
-    if (!colok) return;
+    if (!incol) return;
+    if (!colok) {
+        double* z = a.colpart + (size_t)rb * a.ldr + 4 * c4;
+        z[0] = z[1] = z[2] = z[3] = 0.0;
+        return;
+    }
     double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
     while (full) {
 #pragma unroll
@@ -470,7 +479,15 @@ __global__ __launch_bounds__(kAdjThreads) void k_adjoint(AdjArgs a) {
          l += nwaves) {
         const float4* Rp = reinterpret_cast<const float4*>(a.R) + (size_t)l * ld4;
         double s = 0.0;
-        for (int c = lane; c < ld4; c += 64) {
+        // with band skipping only the 64-column groups that meet the row's
+        // non-zero band are read; each lane keeps its columns, and the
+        // skipped terms are exact zeros, so the sums are unchanged
+        int c0 = lane, c1 = ld4;
+        if (a.rowband) {
+            c0 = a.rowband[2 * (size_t)l] / 64 * 64 + lane;
+            c1 = a.rowband[2 * (size_t)l + 1];
+        }
+        for (int c = c0; c < c1; c += 64) {
             const float4 x = ld_stream(Rp + c);
             s = fma((double)x.x, av[4 * c + 0], s);
             s = fma((double)x.y, av[4 * c + 1], s);

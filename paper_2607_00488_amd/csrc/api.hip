@@ -186,6 +186,11 @@ struct nr_ctx {
     double *d_ssm = nullptr, *d_basis = nullptr;
     int *d_group = nullptr, *d_jmin = nullptr, *d_srcoff = nullptr;
     double* d_table[2] = {nullptr, nullptr};  // [n_nodes + n_src] double4, by parity
+    // node-scan work-groups: (source, 512-node chunk) pairs, and the chunk
+    // totals [n_src][max_chunks] double4, by parity
+    int nb_scan = 0, max_chunks = 1;
+    int* d_scanblk = nullptr;
+    double* d_ctot[2] = {nullptr, nullptr};
     // response
     int n_reco = 0, ldr = 0;
     float* d_R = nullptr;
@@ -485,6 +490,7 @@ int ensure_stage(nr_ctx* c, size_t pts, size_t mu_elems, size_t w_elems) {
 // library's static workspace (NULL = the context's).
 struct Work {
     double* table[2];   // [4 (n_nodes + n_src)] each
+    double* ctot[2];    // [4 n_src max_chunks] each
     double* v[2];       // [n_rows] each
     double* colpart;    // [2][n_rb][ldr]
     double* chunk_dev;  // [2][n_cc]
@@ -506,6 +512,8 @@ size_t carve_work(const nr_ctx* c, double* base, Work* w) {
     const size_t nt = (size_t)4 * (c->n_nodes + c->n_src);
     w->table[0] = take(nt);
     w->table[1] = take(nt);
+    w->ctot[0] = take((size_t)4 * c->n_src * c->max_chunks);
+    w->ctot[1] = take((size_t)4 * c->n_src * c->max_chunks);
     w->v[0] = take(c->n_rows);
     w->v[1] = take(c->n_rows);
     w->colpart = take((size_t)2 * c->n_rb * c->ldr);
@@ -529,6 +537,9 @@ nr::ScanArgs scan_args(nr_ctx* c, const double* d_theta, int par,
     a.theta = d_theta;
     a.ph = c->ph;
     a.table = reinterpret_cast<double4*>(wk ? wk->table[par] : c->d_table[par]);
+    a.blocks = c->d_scanblk;
+    a.ctot = reinterpret_cast<double4*>(wk ? wk->ctot[par] : c->d_ctot[par]);
+    a.max_chunks = c->max_chunks;
     return a;
 }
 
@@ -537,6 +548,9 @@ nr::RowArgs row_args(nr_ctx* c, int par, double* v, double* out_w,
                      const Work* wk = nullptr) {
     nr::RowArgs a{};
     a.table = reinterpret_cast<const double4*>(wk ? wk->table[par] : c->d_table[par]);
+    a.srcOff = c->d_srcoff;
+    a.ctot = reinterpret_cast<const double4*>(wk ? wk->ctot[par] : c->d_ctot[par]);
+    a.max_chunks = c->max_chunks;
     a.jmin = c->d_jmin;
     a.tc = c->d_tc;
     a.n_t = c->n_t;
@@ -608,7 +622,7 @@ int step(nr_ctx* c, const nr::FoldArgs* fold, const nr::RowArgs* rows,
     }
     if (scan) {
         a.scan = *scan;
-        a.nb_scan = c->n_src;
+        a.nb_scan = c->nb_scan;
     }
     if (fin) {
         a.fin = *fin;
@@ -633,7 +647,8 @@ int step(nr_ctx* c, const nr::FoldArgs* fold, const nr::RowArgs* rows,
 int enqueue_points(nr_ctx* c, const double* th, int n_pts, double* nll,
                    double* grad, double* mu, double* w, hipStream_t s,
                    const Work* wk = nullptr) {
-    const Work own{{c->d_table[0], c->d_table[1]}, {c->d_v[0], c->d_v[1]},
+    const Work own{{c->d_table[0], c->d_table[1]}, {c->d_ctot[0], c->d_ctot[1]},
+                   {c->d_v[0], c->d_v[1]},
                    c->d_colpart, c->d_chunk_dev, c->d_chunk_gb, c->d_a, c->d_gb,
                    c->d_jpart};
     if (!wk) wk = &own;
@@ -1271,6 +1286,7 @@ void nr_destroy(nr_ctx* c) {
     dfree(&c->d_trec); dfree(&c->d_tdp); dfree(&c->d_thp); dfree(&c->d_tred);
     dfree(&c->d_v[0]); dfree(&c->d_v[1]);
     dfree(&c->d_rowband); dfree(&c->d_tileband);
+    dfree(&c->d_scanblk); dfree(&c->d_ctot[0]); dfree(&c->d_ctot[1]);
     free_pinned(c);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
@@ -1386,6 +1402,26 @@ int nr_set_sources(nr_ctx* c, const nr_source* src, int n_src, int n_t,
         (rc = dalloc(&c->d_basis, (size_t)nr::kNBasis * n_t)) ||
         (rc = dalloc(&c->d_v[0], n_t)) || (rc = dalloc(&c->d_v[1], n_t)))
         return rc;
+    {
+        // one node-scan work-group per 512 nodes of each source
+        std::vector<int> blk;
+        c->max_chunks = 1;
+        for (int k = 0; k < n_src; ++k) {
+            const int nch = std::max(1, (c->src_n[k] + nr::kStepRows - 1) / nr::kStepRows);
+            c->max_chunks = std::max(c->max_chunks, nch);
+            for (int h = 0; h < nch; ++h) {
+                blk.push_back(k);
+                blk.push_back(h);
+            }
+        }
+        c->nb_scan = (int)blk.size() / 2;
+        if ((rc = dalloc(&c->d_scanblk, blk.size())) ||
+            (rc = dalloc(&c->d_ctot[0], (size_t)4 * n_src * c->max_chunks)) ||
+            (rc = dalloc(&c->d_ctot[1], (size_t)4 * n_src * c->max_chunks)))
+            return rc;
+        HIPCHK(hipMemcpy(c->d_scanblk, blk.data(), sizeof(int) * blk.size(),
+                         hipMemcpyHostToDevice));
+    }
     {
         std::vector<double> ie(c->n_nodes);
         for (int j = 0; j < c->n_nodes; ++j) ie[j] = 1.0 / c->hE[j];

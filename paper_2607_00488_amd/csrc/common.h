@@ -35,6 +35,9 @@ struct ScanArgs {
     const double* theta;   // device, 7 doubles
     Phys ph;
     double4* table;        // [n_nodes + n_src]
+    const int* blocks;     // [nb_scan][2]: source, chunk (0 = highest 512 nodes)
+    double4* ctot;         // [n_src][max_chunks] chunk totals
+    int max_chunks;
 };
 
 // Weights of one point from its node table, one thread per row of the
@@ -44,6 +47,9 @@ struct ScanArgs {
 // source.
 struct RowArgs {
     const double4* table;
+    const int* srcOff;     // [n_src+1]
+    const double4* ctot;   // [n_src][max_chunks] chunk totals of the node scan
+    int max_chunks;
     const int* jmin;      // [n_src][n_t] first reachable global node index
     const double* tc;     // [n_t] recoil-bin centres
     int n_t, n_comp;

@@ -92,10 +92,12 @@ static_assert(kStepRows == kStepThreads, "one recoil row per thread");
 // that reach T_l are those with index >= jmin(k, l), a suffix of the
 // E-ordered nodes.  So S_theta(T_l) = sum_k C_k(jmin(k, l)) . (1, T, T^2, 1/T)
 // with the suffix sums C_k(j) = sum_{i >= j} c_i: the same quadrature sum,
-// summed in another order.  One work-group per source builds C_k, 512
-// nodes at a time from the high-energy end: each wave scans its 64 nodes
-// with shuffles, the wave totals of a tile meet in LDS, and a carry holds
-// the sum of the tiles already done.  Table entry j + k holds C_k(j); the
+// summed in another order.  A source's nodes are split into chunks of 512
+// counted from the high-energy end, one work-group per chunk: each wave
+// scans its 64 nodes with shuffles and the wave totals of the chunk meet in
+// LDS.  Table entry j + k holds the suffix sum of node j within its chunk,
+// and the chunk's total goes to ctot[k][chunk]; the weights role adds the
+// totals of the chunks above (higher energies) when it reads an entry.  The
 // entry after the source's last node is zero (no reachable node).
 __device__ inline void suffix_scan_wave(double& x, int lane) {
 #pragma unroll
@@ -105,65 +107,53 @@ __device__ inline void suffix_scan_wave(double& x, int lane) {
     }
 }
 
-__device__ void scan_role(const ScanArgs& a, int k, double* smem) {
+__device__ void scan_role(const ScanArgs& a, int blk, double* smem) {
     double4* wt = reinterpret_cast<double4*>(smem);          // [8]
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int k = a.blocks[2 * blk], ch = a.blocks[2 * blk + 1];
     double th[5];
 #pragma unroll
     for (int i = 0; i < 5; ++i) th[i] = a.theta[i];
     const double f = a.srcGroup[k] ? a.theta[5] : 1.0;
     const int off = a.srcOff[k], end = a.srcOff[k + 1];
     double4* tab = a.table + k;  // entry j + k for global node j
-    if (threadIdx.x == 0) tab[end] = make_double4(0.0, 0.0, 0.0, 0.0);
-    double4 carry = make_double4(0.0, 0.0, 0.0, 0.0);
-    // node data of the next tile are loaded while this tile is scanned
-    int j = end - kStepThreads + (int)threadIdx.x;
-    double ie = 0.0, nw = 0.0, pe = 0.0;
-    if (j >= off) {
-        ie = a.nodeIE[j];
-        nw = a.nodeW[j];
-        pe = a.nodePe[j];
+    if (ch == 0 && threadIdx.x == 0) tab[end] = make_double4(0.0, 0.0, 0.0, 0.0);
+    // this chunk: nodes [hi - 512, hi) of the source; wave 7 holds the
+    // highest 64
+    const int hi = end - ch * kStepThreads;
+    const int j = hi - kStepThreads + (int)threadIdx.x;
+    const bool have = j >= off;
+    double4 c = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (have) {
+        const NodeCoef q = node_coef(a.nodeIE[j], a.nodeW[j] * f, a.nodePe[j], th, a.ph);
+        c = make_double4(q.a0, q.a1, q.a2, q.am);
     }
-    for (int hi = end; hi > off; hi -= kStepThreads) {
-        // node j = hi - 512 + tid; wave 7 holds the highest 64 nodes
-        const bool have = j >= off;
-        double4 c = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (have) {
-            const NodeCoef q = node_coef(ie, nw * f, pe, th, a.ph);
-            c = make_double4(q.a0, q.a1, q.a2, q.am);
-        }
-        const int jn = j - kStepThreads;
-        if (jn >= off) {
-            ie = a.nodeIE[jn];
-            nw = a.nodeW[jn];
-            pe = a.nodePe[jn];
-        }
-        suffix_scan_wave(c.x, lane);
-        suffix_scan_wave(c.y, lane);
-        suffix_scan_wave(c.z, lane);
-        suffix_scan_wave(c.w, lane);
-        if (lane == 0) wt[wave] = c;  // lane 0 holds the wave's total
-        __syncthreads();
-        double4 add = carry;
-        for (int w = kStepWaves - 1; w > wave; --w) {
-            const double4 t = wt[w];
-            add.x += t.x;
-            add.y += t.y;
-            add.z += t.z;
-            add.w += t.w;
-        }
-        if (have)
-            tab[j] = make_double4(c.x + add.x, c.y + add.y, c.z + add.z,
-                                  c.w + add.w);
+    suffix_scan_wave(c.x, lane);
+    suffix_scan_wave(c.y, lane);
+    suffix_scan_wave(c.z, lane);
+    suffix_scan_wave(c.w, lane);
+    if (lane == 0) wt[wave] = c;  // lane 0 holds the wave's total
+    __syncthreads();
+    double4 add = make_double4(0.0, 0.0, 0.0, 0.0);
+    for (int w = kStepWaves - 1; w > wave; --w) {
+        const double4 t = wt[w];
+        add.x += t.x;
+        add.y += t.y;
+        add.z += t.z;
+        add.w += t.w;
+    }
+    if (have)
+        tab[j] = make_double4(c.x + add.x, c.y + add.y, c.z + add.z, c.w + add.w);
+    if (threadIdx.x == 0) {
+        double4 tot = make_double4(0.0, 0.0, 0.0, 0.0);
         for (int w = kStepWaves - 1; w >= 0; --w) {
             const double4 t = wt[w];
-            carry.x += t.x;
-            carry.y += t.y;
-            carry.z += t.z;
-            carry.w += t.w;
+            tot.x += t.x;
+            tot.y += t.y;
+            tot.z += t.z;
+            tot.w += t.w;
         }
-        __syncthreads();
-        j = jn;
+        a.ctot[(size_t)k * a.max_chunks + ch] = tot;
     }
 }
 
@@ -179,7 +169,19 @@ __device__ void rows_role(const RowArgs& a, int blk) {
     double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
     for (int q = a.compOff[c]; q < a.compOff[c + 1]; ++q) {
         const int k = a.compSrc[q];
-        const double4 t = a.table[a.jmin[(size_t)k * a.n_t + l] + k];
+        const int jj = a.jmin[(size_t)k * a.n_t + l];
+        double4 t = a.table[jj + k];
+        // totals of the chunks above node jj's chunk (none for the empty
+        // entry at the source's end)
+        const int end = a.srcOff[k + 1];
+        const int nch = jj < end ? (end - 1 - jj) / kStepThreads : 0;
+        for (int h = 0; h < nch; ++h) {
+            const double4 u = a.ctot[(size_t)k * a.max_chunks + h];
+            t.x += u.x;
+            t.y += u.y;
+            t.z += u.z;
+            t.w += u.w;
+        }
         s.x += t.x;
         s.y += t.y;
         s.z += t.z;

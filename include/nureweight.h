@@ -153,12 +153,16 @@ int nr_eval_nll_dev(nr_ctx *ctx, const double *d_theta, int n_pts,
  * nr_set_components record the bands).  With `on` non-zero the fold of
  * Eq. (matrix_reweight) and the adjoint pass of the gradient read only the
  * 16-byte column groups inside those bands and write zero partial sums for
- * the rest.  The skipped terms are exact zeros and no sum changes order,
- * so every result is bitwise the one of the full read.  Off by default:
- * the full dense read of R, as the method is written.  Applies to
- * nr_eval_nll, nr_eval_nll_grad, nr_eval_mu, nr_eval_nll_dev and
- * nr_eval_nll_dev_noalloc; NR_EINVAL for a null context, NR_ESTATE before
- * a response is set. */
+ * the rest; in the batched forms every tile of the forward and adjoint
+ * matrix products reduces only over the K-steps of 16 whose response
+ * entries for it are not all zero.  The skipped terms are exact zeros and
+ * no sum changes order, so every result is bitwise the one of the full
+ * read (for the batched forms at the same tile shape; the tuner, which
+ * times the banded and the dense products separately, may pick another).
+ * Off by default: the full dense read of R, as the method is written.
+ * Applies to nr_eval_nll, nr_eval_nll_grad, nr_eval_mu, nr_eval_nll_dev,
+ * nr_eval_nll_dev_noalloc and the batched and grouped entry points;
+ * NR_EINVAL for a null context, NR_ESTATE before a response is set. */
 int nr_set_band_skipping(nr_ctx *ctx, int on);
 
 /* Size in bytes of the static workspace of nr_eval_nll_dev_noalloc, one per

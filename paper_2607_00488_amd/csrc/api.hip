@@ -841,6 +841,44 @@ nr::WgenArgs wgen_args(nr_ctx* c, const double* th, int P) {
     return w;
 }
 
+// K range of a GEMM tile: the whole reduction, or with band skipping the
+// K-steps whose response entries for the tile are not all zero.  Forward
+// tiles cover response columns [c0, c1) and reduce over its rows; adjoint
+// tiles cover rows [c0, c1) and reduce over its columns.  An empty range
+// leaves the tile's sums at zero, as the skipped products are.
+void tile_k_range(const nr_ctx* c, bool adjoint, int c0, int c1, int K, int* k0, int* k1) {
+    constexpr int BK = nr::kGemmBK;
+    if (!c->skip_zero) {
+        *k0 = 0;
+        *k1 = K;
+        return;
+    }
+    int lo = K, hi = 0;
+    if (!adjoint) {
+        for (int l = 0; l < c->n_t; ++l) {
+            const int a = 4 * c->rowband[2 * (size_t)l], b = 4 * c->rowband[2 * (size_t)l + 1];
+            if (a < b && a < c1 && b > c0) {
+                lo = std::min(lo, l);
+                hi = std::max(hi, l + 1);
+            }
+        }
+    } else {
+        for (int l = c0; l < std::min(c1, c->n_t); ++l) {
+            const int a = 4 * c->rowband[2 * (size_t)l], b = 4 * c->rowband[2 * (size_t)l + 1];
+            if (a < b) {
+                lo = std::min(lo, a);
+                hi = std::max(hi, b);
+            }
+        }
+    }
+    if (lo >= hi) {
+        *k0 = *k1 = 0;
+        return;
+    }
+    *k0 = lo / BK * BK;
+    *k1 = std::min(K, (hi + BK - 1) / BK * BK);
+}
+
 int build_plan(const MultiCall& mc, bool grad, int cfg, BatchPlan* pl) {
     const int TMt = nr::gemm_tile_m(cfg), TNt = nr::gemm_tile_n(cfg);
     std::vector<nr::GemmProb> pf(mc.n), pa(mc.n);
@@ -867,8 +905,12 @@ int build_plan(const MultiCall& mc, bool grad, int cfg, BatchPlan* pl) {
         f.mu = mc.mu ? mc.mu[d] : nullptr;
         pf[d] = f;
         const int mt = (P + TMt - 1) / TMt;
+        std::vector<int> kr(2 * (size_t)f.n_nt);
+        for (int j = 0; j < f.n_nt; ++j)
+            tile_k_range(c, false, j * TNt, (j + 1) * TNt, c->n_t, &kr[2 * j], &kr[2 * j + 1]);
         for (int i = 0; i < mt; ++i)
-            for (int j = 0; j < f.n_nt; ++j) tf.push_back({d, i, j, c->n_t});
+            for (int j = 0; j < f.n_nt; ++j)
+                tf.push_back({d, i, j, kr[2 * j + 1] - kr[2 * j], kr[2 * j], kr[2 * j + 1]});
         if (grad) {
             nr::GemmProb a{};
             a.At = c->d_bat;
@@ -882,8 +924,13 @@ int build_plan(const MultiCall& mc, bool grad, int cfg, BatchPlan* pl) {
             a.ldc = c->n_t;
             pa[d] = a;
             const int nt = (c->n_t + TNt - 1) / TNt;
+            std::vector<int> ka(2 * (size_t)nt);
+            for (int j = 0; j < nt; ++j)
+                tile_k_range(c, true, j * TNt, (j + 1) * TNt, c->n_reco, &ka[2 * j],
+                             &ka[2 * j + 1]);
             for (int i = 0; i < mt; ++i)
-                for (int j = 0; j < nt; ++j) ta.push_back({d, i, j, c->n_reco});
+                for (int j = 0; j < nt; ++j)
+                    ta.push_back({d, i, j, ka[2 * j + 1] - ka[2 * j], ka[2 * j], ka[2 * j + 1]});
         }
     }
     // longest tiles first: the persistent work-groups pull from this list
@@ -1034,8 +1081,8 @@ std::string shape_class(const MultiCall& mc, bool grad) {
     std::vector<std::string> parts;
     for (int d = 0; d < mc.n; ++d) {
         char b[96];
-        snprintf(b, sizeof(b), "%dx%dx%d", (mc.n_pts[d] + 63) / 64 * 64,
-                 mc.ctx[d]->n_reco, mc.ctx[d]->n_t);
+        snprintf(b, sizeof(b), "%dx%dx%d%s", (mc.n_pts[d] + 63) / 64 * 64,
+                 mc.ctx[d]->n_reco, mc.ctx[d]->n_t, mc.ctx[d]->skip_zero ? "b" : "");
         parts.push_back(b);
     }
     std::sort(parts.begin(), parts.end());

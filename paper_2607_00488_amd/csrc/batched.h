@@ -42,8 +42,14 @@ struct GemmProb {
     int pad;
 };
 
+// One output tile of a problem: its reduction runs over k in [k0, k1)
+// (the whole K, or with band skipping the K-steps of 16 whose response
+// entries for this tile are not all zero).
+constexpr int kGemmBK = 16;  // K step of the GEMM kernels
+
 struct GemmTile {
     int prob, mt, nt, cost;
+    int k0, k1;
 };
 
 struct FinalArgs {

@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_wgen(WgenArgs a) {
 // (BM/2) x (BN/2) = blocks of v_mfma_f64_16x16x4_f64.  R stays FP32 in HBM
 // and is widened to FP64 when staged into LDS.  The tile shape is a
 // template parameter; the host picks one per shape class by timing.
-constexpr int BK = 16;
+constexpr int BK = kGemmBK;
 constexpr int kGemmThreads = 256;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -238,12 +238,12 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
             }
         };
 
-        gload(0);
-        for (int k0 = 0; k0 < K; k0 += BK) {
+        gload(tl.k0);
+        for (int k0 = tl.k0; k0 < tl.k1; k0 += BK) {
             __syncthreads();
             sstore();
             __syncthreads();
-            if (k0 + BK < K) gload(k0 + BK);
+            if (k0 + BK < tl.k1) gload(k0 + BK);
 #pragma unroll
             for (int kk = 0; kk < BK; kk += 4) {
                 double a[BI], b[BJ];

@@ -10,7 +10,9 @@
  * p_ee[n]; float R[n_t][n_reco]; double n[n_reco], b[n_reco],
  * theta[n_pts][7].
  * Output: double nll[n_pts], grad[n_pts][7], nll_t[n_pts],
- * grad_t[n_pts][7]; int32 codes[5]. */
+ * grad_t[n_pts][7]; int32 codes[7]: five status codes of invalid calls,
+ * then 1 if the evaluations with band skipping equal the ones without bit
+ * for bit, then the status of band skipping asked for on a fresh context. */
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -72,7 +74,7 @@ int main(int argc, char** argv) {
     double* th = (double*)rd(f, sizeof(double) * n_pts * NR_NTHETA);
     fclose(f);
 
-    int codes[5];
+    int codes[7];
     nr_ctx* ctx = NULL;
     CHECK(nr_create(0, &ctx));
     codes[0] = nr_eval_nll(ctx, th, 1, n);                /* before set_*: ESTATE */
@@ -97,6 +99,22 @@ int main(int argc, char** argv) {
     double* grad_t = (double*)malloc(sizeof(double) * n_pts * NR_NTHETA);
     CHECK(nr_eval_nll_grad(ctx, th, n_pts, nll, grad));
     CHECK(nr_eval_nll_templates(ctx, th, n_pts, nll_t, grad_t));
+    {
+        /* the same evaluations reading only R's non-zero column bands */
+        double* nll_b = (double*)malloc(sizeof(double) * n_pts);
+        double* grad_b = (double*)malloc(sizeof(double) * n_pts * NR_NTHETA);
+        CHECK(nr_set_band_skipping(ctx, 1));
+        CHECK(nr_eval_nll_grad(ctx, th, n_pts, nll_b, grad_b));
+        CHECK(nr_set_band_skipping(ctx, 0));
+        codes[5] = memcmp(nll_b, nll, sizeof(double) * n_pts) == 0 &&
+                   memcmp(grad_b, grad, sizeof(double) * n_pts * NR_NTHETA) == 0;
+        free(nll_b);
+        free(grad_b);
+        nr_ctx* fresh = NULL;
+        CHECK(nr_create(0, &fresh));
+        codes[6] = nr_set_band_skipping(fresh, 1);  /* no response yet: ESTATE */
+        nr_destroy(fresh);
+    }
     double bad[NR_NTHETA], tmp = 0.0;
     memcpy(bad, th, sizeof bad);
     bad[2] = NAN;
@@ -110,7 +128,7 @@ int main(int argc, char** argv) {
     fwrite(grad, sizeof(double), (size_t)n_pts * NR_NTHETA, o);
     fwrite(nll_t, sizeof(double), n_pts, o);
     fwrite(grad_t, sizeof(double), (size_t)n_pts * NR_NTHETA, o);
-    fwrite(codes, sizeof(int), 5, o);
+    fwrite(codes, sizeof(int), 7, o);
     fclose(o);
     free(th);
     free(nll);

@@ -3,8 +3,8 @@
  * response and data (set twice), the pipelined single-point evaluations
  * with graph capture and replay, gradients, weights,
  * the batched and template forms, a grouped launch over two contexts, the
- * effective sample size, retiling, stage timing and the surrogate
- * network's parameter round trip.  Any invalid host access is reported by
+ * effective sample size, retiling, band skipping, stage timing and the
+ * surrogate network's parameter round trip.  Any invalid host access is reported by
  * the sanitizer and fails the run.  Input format of abi_driver.c (at
  * least 34 points).  The single-point spectra entry point is left out: a
  * host-side crash of it on a 16384 x 4096 context has no known cause. */
@@ -64,6 +64,12 @@ int main(int argc, char** argv) {
     CK(nr_eval_ess(c1, th, 3, mu));
     CK(nr_set_fold_tiling(c1, 64, 1));
     CK(nr_eval_nll(c1, th, n_pts, nll));
+    CK(nr_set_band_skipping(c1, 1));                       /* band and tile bands */
+    CK(nr_eval_nll_grad(c1, th, 9, nll, g));
+    CK(nr_eval_nll_grad_batched(c1, th, 33, nll, g));
+    CK(nr_set_fold_tiling(c1, 16, 1));                     /* tile bands rebuilt */
+    CK(nr_eval_nll(c1, th, n_pts, nll));
+    CK(nr_set_band_skipping(c1, 0));
     CK(nr_set_response(c1, R, n_t, n_reco, NULL, n_sig));   /* same shapes again */
     CK(nr_eval_nll(c1, th, 20, nll));
     double ms;

@@ -65,8 +65,9 @@ def test_c_caller_against_oracle(tmp_path):
     d = np.frombuffer(raw[:8 * (16 * P)], dtype="<f8")
     nll, grad = d[:P], d[P:8 * P].reshape(P, 7)
     nll_t, grad_t = d[8 * P:9 * P], d[9 * P:16 * P].reshape(P, 7)
-    codes = struct.unpack("<5i", raw[8 * 16 * P:])
-    assert codes == (nr.NR_ESTATE, nr.NR_EINVAL, 1, nr.NR_EINVAL, nr.NR_EINVAL)
+    codes = struct.unpack("<7i", raw[8 * 16 * P:])
+    assert codes == (nr.NR_ESTATE, nr.NR_EINVAL, 1, nr.NR_EINVAL, nr.NR_EINVAL,
+                     1, nr.NR_ESTATE)
     for i in range(P):
         v, rg = o.nll_grad(th[i])
         scale = np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())

@@ -288,6 +288,38 @@ def banded_form(ctx, R, tt, dense_out, stream):
                      "dense read")
 
 
+def seeded_fit_study(ctx, sur, S=64, gtols=(1e-2, 1e-4)):
+    """Where the network helps without its values being returned: it ranks
+    65 536 points of the box and the S best start exact L-BFGS fits (the
+    template form), against S uniform starts.  Every returned minimum is
+    exact; the gain is in exact likelihood calls."""
+    import torch
+    import synth
+    from paper_2607_00488_amd.autograd import lbfgs_fit
+    lo, hi = synth.theta_box()
+    ctx.build_templates()
+    out = {}
+    for gtol in gtols:
+        g = np.random.Generator(np.random.PCG64(5000))
+        starts = torch.tensor(g.uniform(lo, hi, (S, 7)), dtype=torch.float64,
+                              device=sur.dev)
+        _, f1, gn1, c1 = lbfgs_fit(ctx, starts, iters=300, gtol=gtol, form="templates")
+        cand = sur.sample_box(1 << 16, 6000)
+        nl, _ = sur.nll(ctx, cand)
+        best = cand[torch.argsort(nl)[:S]].contiguous()
+        _, f2, gn2, c2 = lbfgs_fit(ctx, best, iters=300, gtol=gtol, form="templates")
+        fmin = float(min(f1.min().item(), f2.min().item()))
+        out[f"gtol_{gtol:g}"] = dict(
+            uniform_starts_calls=c1, network_starts_calls=c2,
+            call_gain=round(c1 / c2, 3),
+            best_uniform=float(f1.min().item()), best_network=float(f2.min().item()),
+            at_best_uniform=float((f1 <= fmin + 0.01).double().mean().item()),
+            at_best_network=float((f2 <= fmin + 0.01).double().mean().item()))
+    out["what"] = (f"{S} exact L-BFGS fits (template form) from uniform box starts "
+                   f"against the {S} best of 65536 box points ranked by the network")
+    return out
+
+
 def surrogate_ceiling(ctx, sur, n_data, th_val, ks=(16, 32, 64)):
     """How far the trained network's -2lnL is from the exact one, and how
     far first-order corrections from exact linear functionals of mu would
@@ -394,6 +426,7 @@ def surrogate_form(ctx, train_seconds=20.0, n_data=None):
     sur.nll(ctx, th)
     torch.cuda.synchronize()
     t_net = time.perf_counter() - t1
+    seeded = seeded_fit_study(ctx, sur)
     out, ev = sur.evaluate(ctx, th, seed=1)              # warm the spot graph
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -421,6 +454,7 @@ def surrogate_form(ctx, train_seconds=20.0, n_data=None):
                    data_seconds=round(t_data, 2),
                    final_loss=info["losses"][-1][1] if info["losses"] else None),
         ceiling=ceiling,
+        seeded_fit=seeded,
         what="MLP 7-256-256-256-4096 SiLU on BF16 matrix cores; -2lnL "
              "with 1% exact spot checks, fallback to the exact batched "
              "method when a check misses by more than 0.1")

@@ -707,6 +707,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-components", action="store_true")
+    ap.add_argument("--no-banded", action="store_true",
+                    help="skip the band-skipping forms (a trace of the dense "
+                         "step kernel alone)")
     ap.add_argument("--surrogate-seconds", type=float, default=20.0)
     ap.add_argument("--gemm-counter-pass", action="store_true",
                     help="short run for matrix-core counters: the batched "
@@ -855,10 +858,11 @@ def main():
                            fold_alone_us=round(fold_ms * 1e3, 2),
                            fold_plus_likelihood_us=round(fold_lik_ms * 1e3, 2)))
     forms = {}
-    forms["plain_banded"] = banded_form(ctx, p["R"], tt, out, stream)
-    log(f"[bench] plain with band skipping: "
-        f"{forms['plain_banded']['evals_per_s']:.0f} evals/s, bitwise equal: "
-        f"{forms['plain_banded']['bitwise_equal_to_dense']}")
+    if not args.no_banded:
+        forms["plain_banded"] = banded_form(ctx, p["R"], tt, out, stream)
+        log(f"[bench] plain with band skipping: "
+            f"{forms['plain_banded']['evals_per_s']:.0f} evals/s, bitwise equal: "
+            f"{forms['plain_banded']['bitwise_equal_to_dense']}")
     # the FP64 matrix-core rate the chip sustains on register operands: the
     # practical ceiling of the batched GEMM beside the data-sheet 78.6
     import paper_2607_00488_amd as nr
@@ -895,26 +899,27 @@ def main():
         frac_of_probe=round(2.0 * 1024 * c.n_t * c.n_reco / dtb / 1e12 / probe, 3))
     log(f"[bench] grad batched: {1024 / dtg:.0f} evals/s; nll batched "
         f"{1024 / dtb:.0f} evals/s")
-    # the same two with band skipping: every GEMM tile reduces only over the
-    # K-steps where its response entries are not all zero (results equal to
-    # rounding: the tuner may pick another tile shape, bitwise equality at a
-    # fixed shape is tested)
-    _, nl_d, g_d = time_batched([ctx], [thg], reps=1, grad=True)
-    ctx.set_band_skipping(True)
-    dtgb, nl_b, g_b = time_batched([ctx], [thg], reps=3, grad=True)
-    dtbb, _, _ = time_batched([ctx], [thg], reps=3, grad=False)
-    ctx.set_band_skipping(False)
-    forms["batched_banded"] = dict(
-        evals_per_s=round(1024 / dtbb, 1), grad_evals_per_s=round(1024 / dtgb, 1),
-        points=1024, ms=round(dtbb * 1e3, 3), grad_ms=round(dtgb * 1e3, 3),
-        max_abs_dnll_vs_dense=float(np.max(np.abs(nl_b[0] - nl_d[0]))),
-        max_rel_dgrad_vs_dense=float(np.max(np.abs(g_b[0] - g_d[0])) /
-                                     np.max(np.abs(g_d[0]))),
-        what="the batched likelihood and gradient with band skipping: each "
-             "tile of the forward and adjoint GEMMs reduces only over the "
-             "K-steps of 16 where its response entries are not all zero")
-    log(f"[bench] batched with band skipping: {1024 / dtbb:.0f} evals/s, "
-        f"{1024 / dtgb:.0f} with gradient")
+    if not args.no_banded:
+        # the same two with band skipping: every GEMM tile reduces only over the
+        # K-steps where its response entries are not all zero (results equal to
+        # rounding: the tuner may pick another tile shape, bitwise equality at a
+        # fixed shape is tested)
+        _, nl_d, g_d = time_batched([ctx], [thg], reps=1, grad=True)
+        ctx.set_band_skipping(True)
+        dtgb, nl_b, g_b = time_batched([ctx], [thg], reps=3, grad=True)
+        dtbb, _, _ = time_batched([ctx], [thg], reps=3, grad=False)
+        ctx.set_band_skipping(False)
+        forms["batched_banded"] = dict(
+            evals_per_s=round(1024 / dtbb, 1), grad_evals_per_s=round(1024 / dtgb, 1),
+            points=1024, ms=round(dtbb * 1e3, 3), grad_ms=round(dtgb * 1e3, 3),
+            max_abs_dnll_vs_dense=float(np.max(np.abs(nl_b[0] - nl_d[0]))),
+            max_rel_dgrad_vs_dense=float(np.max(np.abs(g_b[0] - g_d[0])) /
+                                         np.max(np.abs(g_d[0]))),
+            what="the batched likelihood and gradient with band skipping: each "
+                 "tile of the forward and adjoint GEMMs reduces only over the "
+                 "K-steps of 16 where its response entries are not all zero")
+        log(f"[bench] batched with band skipping: {1024 / dtbb:.0f} evals/s, "
+            f"{1024 / dtgb:.0f} with gradient")
     forms["plain_config0"] = pc = plain_config0_form()
     log(f"[bench] plain at 512 x 256: {pc['evals_per_s']:.0f} evals/s "
         f"({pc['us_per_eval']:.2f} us/eval)")

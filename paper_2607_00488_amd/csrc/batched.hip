@@ -136,41 +136,106 @@ __global__ __launch_bounds__(256) void k_wgen(WgenArgs a) {
 
 // --------------------------------------------------------------- GEMM
 // Tiles of BM x BN outputs, K-steps of 16; four waves in 2 x 2, each
-// (BM/2) x (BN/2) = blocks of v_mfma_f64_16x16x4_f64.  R stays FP32 in HBM
-// and is widened to FP64 when staged into LDS.  The tile shape is a
+// (BM/2) x (BN/2) = blocks of v_mfma_f64_16x16x4_f64.  The tile shape is a
 // template parameter; the host picks one per shape class by timing.
+//
+// Operands reach LDS by gfx950's global-to-LDS copies: one instruction moves
+// 16 bytes per lane from any global address and writes them, in lane order,
+// as 1 KiB at a wave-uniform LDS base, without passing through registers.
+// The K-steps rotate through a ring of three stages, so each step waits
+// only for its own stage (copied two steps earlier) and has one barrier,
+// which also frees the stage read one step before for the next copy.  R
+// stays FP32 in LDS (half the bytes of FP64) and is widened when a wave
+// takes its fragment.  Lanes past an operand's edge copy a zero chunk.
+//
+// Within a K-step, MFMA sub-step s gives lane row (k) 4 * (lane / 16) + s,
+// and the wave's 16 x 16 blocks interleave their rows and columns so that
+// each lane's operands of one sub-step sit side by side in LDS: one 16-byte
+// read gives two A values (or four R values) instead of one each.
 constexpr int BK = kGemmBK;
 constexpr int kGemmThreads = 256;
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
+
+// Source of the chunks that lie past an operand's edge (never written).
+__device__ __align__(16) double g_zero_chunk[2];
+
+// Written as assembly so that the compiler does not track these copies:
+// with them in view it waited for every copy in flight before any LDS read
+// of the loop, which undoes the ring.  The waits are explicit instead.
+// (m0 is named as clobbered; the compiler keeps nothing in it here.)
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+// `lds` is the wave's LDS byte address (the same in every lane).
+__device__ inline void copy16_to_lds(const void* src, unsigned lds) {
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off"
+                 :
+                 : "v"(src), "s"(lds)
+                 : "memory", "m0");
+}
+#pragma clang diagnostic pop
+
+// 16-byte slot of (row n, k-chunk) in the adjoint's [n][16 k] stage of R:
+// rotated with n so that the 16 rows one read touches fall on distinct
+// banks (for 32 and for 64 four-byte banks alike).
+__device__ inline int adj_swz(int n) {
+    return 2 * ((n >> 2) & 1) + (((n >> 1) & 1) ^ ((n >> 3) & 1));
+}
+
+// s_waitcnt with vmcnt = N and lgkmcnt = 0 (expcnt left alone).
+template <int N>
+__device__ inline void wait_vm_lgkm0() {
+    static_assert(N >= 0 && N < 16, "vmcnt immediate");
+    __builtin_amdgcn_s_waitcnt(N | (7 << 4));
+}
 
 template <int MODE, int BM, int BN>
-__global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
+__global__ __launch_bounds__(kGemmThreads, BM * BN <= 8192 ? 3 : 2) void k_gemm(const GemmProb* probs,
                                                        const GemmTile* tiles,
                                                        int n_tiles,
                                                        unsigned* ctr) {
+    constexpr bool ADJ = MODE == kModeAdj;
     constexpr int WTM = BM / 2, WTN = BN / 2;   // wave tile
     constexpr int BI = WTM / 16, BJ = WTN / 16;  // 16x16 blocks per wave
-    constexpr int LDA = BM + 2, LDB = BN + 2;   // LDS row strides (doubles)
-    constexpr int EPI = WTN + 1;                 // epilogue staging stride
-    constexpr int NA = BM / 32;                  // double2 chunks per thread
-    constexpr int NB = BN / 64;                  // float4 chunks per thread
-    constexpr int MAIN = BK * (LDA + LDB), STAGE = 4 * 16 * EPI;
-    __shared__ double smem[MAIN > STAGE ? MAIN : STAGE];
+    constexpr int NIA = BM / 32, NIB = BN / 64;  // copies per wave and stage
+    constexpr int NI = NIA + NIB;
+    // forward R stage: [16][BN] floats in 1 KiB blocks of 256 / BN rows; with
+    // BN = 64 a 128-byte gap after each block puts rows 4 apart on other banks
+    constexpr int RPB = 256 / BN;
+    constexpr int PADB = (!ADJ && BN == 64) ? 32 : 0;  // floats
+    constexpr int A_DBL = BK * BM;
+    constexpr int B_FLT = (BN / 16) * (256 + PADB);
+    constexpr int SLOT = A_DBL * 8 + B_FLT * 4;
+    constexpr int EPI = WTN + 1;  // epilogue staging stride (doubles)
+    // ring slots: stage s + RING - 1 is copied during step s.  The adjoint's
+    // R chunks (64 bytes of each of 16 rows per copy) arrive later than the
+    // forward's contiguous rows; it prefetches one step deeper where LDS
+    // still leaves room for two work-groups per compute unit.
+    constexpr int RING = (ADJ && 4 * SLOT <= 65536) ? 4 : 3;
+    static_assert(BI % 2 == 0 && (ADJ || BJ == 2 || BJ == 4), "tile shape");
+    static_assert(4 * 16 * EPI * 8 <= RING * SLOT, "epilogue staging fits the ring");
+    static_assert(RING == 3 || RING == 4, "ring length");
+    __shared__ __align__(16) unsigned char ring[RING * SLOT];
     __shared__ double rowred[BM][2];
     __shared__ double rowred2[BM][2];
     __shared__ int s_tile;
-    double (*As)[LDA] = reinterpret_cast<double (*)[LDA]>(smem);
-    double (*Bs)[LDB] = reinterpret_cast<double (*)[LDB]>(smem + BK * LDA);
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int wm = wave >> 1, wn = wave & 1;
     const int li = lane & 15, lk = lane >> 4;
+    // held in scalar registers (not re-derived inside the loop)
+    const double* zp = g_zero_chunk;
+    asm volatile("" : "+s"(zp));
+    const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+    const unsigned ring_lds =
+        __builtin_amdgcn_readfirstlane((unsigned)(uintptr_t)(lds_void*)ring);
 
     for (;;) {
         if (tid == 0) s_tile = (int)atomicAdd(&ctr[0], 1u);
         __syncthreads();
-        const int t = s_tile;
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
         __syncthreads();
         if (t >= n_tiles) break;
         const GemmTile tl = tiles[t];
@@ -184,120 +249,186 @@ __global__ __launch_bounds__(kGemmThreads) void k_gemm(const GemmProb* probs,
 #pragma unroll
             for (int j = 0; j < BJ; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
 
-        double2 ra[NA];
-        float4 rb[NB];
-        auto gload = [&](int k0) {
+        const int kb = tl.k0;
+        const int nst = (tl.k1 - tl.k0 + BK - 1) / BK;
+        // Each copy instruction of a wave moves one 16-byte chunk per lane.
+        // Its source is lane-constant within the tile up to an advance of
+        // one stage per K-step, so the pointers are set up once here and
+        // stepped; a chunk past the operand's edge (a column beyond the
+        // stored width, a row beyond K) is taken from the zero chunk.
+        const char* src[NI];
+        long adv[NI];   // bytes per K-step (0 for a chunk that stays zero)
+        int c0[NI];     // chunk's K coordinate at the tile's first step
+        int lim[NI];    // its K coordinate must stay below this
 #pragma unroll
-            for (int i = 0; i < NA; ++i) {  // A^T: BK x BM doubles, M contiguous
-                const int q = tid + i * kGemmThreads;
-                const int kk = q / (BM / 2), c2 = q % (BM / 2);
-                const int k = k0 + kk, m = m0 + 2 * c2;
-                ra[i] = (k < K && m < pr.lda)
-                            ? ld_global(reinterpret_cast<const double2*>(pr.At + (size_t)k * pr.lda + m))
-                            : make_double2(0.0, 0.0);
-            }
+        for (int q = 0; q < NIA; ++q) {  // A^T: [16][BM] doubles, M contiguous
+            const int e = 2 * ((wave + 4 * q) * 64 + lane);
+            const int kk = e / BM, m = m0 + e % BM;
+            const bool ok = m < pr.lda;
+            src[q] = ok ? (const char*)(pr.At + (size_t)(kb + kk) * pr.lda + m) : (const char*)zp;
+            adv[q] = ok ? (long)BK * pr.lda * 8 : 0;
+            c0[q] = kb + kk;
+            lim[q] = K;
+        }
 #pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                const int q = tid + i * kGemmThreads;
-                if (MODE != kModeAdj) {  // B[k][n] = R[k][n], N contiguous
-                    const int kk = q / (BN / 4), c4 = q % (BN / 4);
-                    const int k = k0 + kk, n = n0 + 4 * c4;
-                    rb[i] = (k < K && n < pr.ldb)
-                                ? ld_global(reinterpret_cast<const float4*>(pr.B + (size_t)k * pr.ldb + n))
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
-                } else {  // B[k][n] = R[n][k], K contiguous
-                    const int nn = q >> 2, k4 = q & 3;
-                    const int n = n0 + nn, k = k0 + 4 * k4;
-                    rb[i] = (n < pr.N && k < pr.ldb)
-                                ? ld_global(reinterpret_cast<const float4*>(pr.B + (size_t)n * pr.ldb + k))
-                                : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
+        for (int q = 0; q < NIB; ++q) {
+            const int I = wave + 4 * q;
+            if constexpr (!ADJ) {  // R[k][n], N contiguous: [16][BN]
+                const int e = 4 * (I * 64 + lane);
+                const int kk = e / BN, n = n0 + e % BN;
+                const bool ok = n < pr.ldb;
+                src[NIA + q] = ok ? (const char*)(pr.B + (size_t)(kb + kk) * pr.ldb + n)
+                                  : (const char*)zp;
+                adv[NIA + q] = ok ? (long)BK * pr.ldb * 4 : 0;
+                c0[NIA + q] = kb + kk;
+                lim[NIA + q] = K;
+            } else {  // R[n][k], K contiguous: [BN][16] in rotated chunks
+                const int c = I * 64 + lane;
+                const int nl = c >> 2, k4 = (c & 3) ^ adj_swz(c >> 2);
+                const int n = n0 + nl;
+                const bool ok = n < pr.N;
+                src[NIA + q] = ok ? (const char*)(pr.B + (size_t)n * pr.ldb + kb + 4 * k4)
+                                  : (const char*)zp;
+                adv[NIA + q] = ok ? (long)BK * 4 : 0;
+                c0[NIA + q] = kb + 4 * k4;
+                lim[NIA + q] = pr.ldb;
             }
+        }
+        // LDS byte address of each copy's 1 KiB in slot 0 (wave-uniform)
+        auto lds_of = [&](int q) -> unsigned {
+            return q < NIA ? ring_lds + (unsigned)((wave_u + 4 * q) * 1024)
+                           : ring_lds + (unsigned)(A_DBL * 8 +
+                                                   (wave_u + 4 * (q - NIA)) * (1024 + 4 * PADB));
         };
-        auto sstore = [&]() {
+        // copy q of stage st (K-steps from the tile's first) into ring slot `slot`
+        auto issue_one = [&](int slot, int st, int q) {
+            const char* p = c0[q] + st * BK < lim[q] ? src[q] : (const char*)zp;
+            copy16_to_lds(p, lds_of(q) + (unsigned)(slot * SLOT));
+            src[q] += adv[q];
+        };
+        auto issue = [&](int slot, int st) {
 #pragma unroll
-            for (int i = 0; i < NA; ++i) {
-                const int q = tid + i * kGemmThreads;
-                const int kk = q / (BM / 2), c2 = q % (BM / 2);
-                *reinterpret_cast<double2*>(&As[kk][2 * c2]) = ra[i];
-            }
-#pragma unroll
-            for (int i = 0; i < NB; ++i) {
-                const int q = tid + i * kGemmThreads;
-                if (MODE != kModeAdj) {
-                    const int kk = q / (BN / 4), c4 = q % (BN / 4);
-                    double* d = &Bs[kk][4 * c4];
-                    d[0] = rb[i].x; d[1] = rb[i].y; d[2] = rb[i].z; d[3] = rb[i].w;
-                } else {
-                    const int nn = q >> 2, k4 = q & 3;
-                    Bs[4 * k4 + 0][nn] = rb[i].x;
-                    Bs[4 * k4 + 1][nn] = rb[i].y;
-                    Bs[4 * k4 + 2][nn] = rb[i].z;
-                    Bs[4 * k4 + 3][nn] = rb[i].w;
-                }
-            }
+            for (int q = 0; q < NI; ++q) issue_one(slot, st, q);
         };
 
-        gload(tl.k0);
-        for (int k0 = tl.k0; k0 < tl.k1; k0 += BK) {
-            __syncthreads();
-            sstore();
-            __syncthreads();
-            if (k0 + BK < tl.k1) gload(k0 + BK);
+        // nothing of this tile's set-up left in flight: the loop's explicit
+        // waits then count only the ring's copies
+        __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
-            for (int kk = 0; kk < BK; kk += 4) {
-                double a[BI], b[BJ];
+        for (int st = 0; st < RING - 1; ++st)
+            if (st < nst) issue(st, st);
+        // one K-step on the stage in slot `cur`; stage s + 2 goes into the
+        // slot stage s - 1 used
+        auto step = [&](int cur, int s) {
+            // this stage is in; the later ones already issued may still fly
+            if (RING == 4 && s + 2 < nst)
+                wait_vm_lgkm0<(RING == 4 ? 2 * NI : NI)>();
+            else if (s + 1 < nst)
+                wait_vm_lgkm0<NI>();
+            else
+                wait_vm_lgkm0<0>();
+            asm volatile("s_barrier" ::: "memory");
+            const double* SA = reinterpret_cast<const double*>(ring + cur * SLOT);
+            const float* SB = reinterpret_cast<const float*>(ring + cur * SLOT + A_DBL * 8);
+            double2 fa[4][BI / 2];
+            float fb[4][BJ];
 #pragma unroll
-                for (int x = 0; x < BI; ++x) a[x] = As[kk + lk][wm * WTM + x * 16 + li];
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int row = 4 * lk + s4;
 #pragma unroll
-                for (int y = 0; y < BJ; ++y) b[y] = Bs[kk + lk][wn * WTN + y * 16 + li];
+                for (int h = 0; h < BI / 2; ++h)
+                    fa[s4][h] = *reinterpret_cast<const double2*>(
+                        SA + row * BM + wm * WTM + 32 * h + 2 * li);
+                if constexpr (!ADJ) {
+                    const float* rp = SB + (row / RPB) * (256 + PADB) + (row % RPB) * BN +
+                                      wn * WTN + BJ * li;
+                    if constexpr (BJ == 4) {
+                        const float4 v = *reinterpret_cast<const float4*>(rp);
+                        fb[s4][0] = v.x; fb[s4][1] = v.y; fb[s4][2] = v.z; fb[s4][3] = v.w;
+                    } else {
+                        const float2 v = *reinterpret_cast<const float2*>(rp);
+                        fb[s4][0] = v.x; fb[s4][1] = v.y;
+                    }
+                }
+            }
+            if constexpr (ADJ) {
 #pragma unroll
-                for (int x = 0; x < BI; ++x)
+                for (int y = 0; y < BJ; ++y) {
+                    const int nl = wn * WTN + 16 * y + li;
+                    const float4 v = *reinterpret_cast<const float4*>(
+                        SB + 4 * (4 * nl + (lk ^ adj_swz(nl))));
+                    fb[0][y] = v.x; fb[1][y] = v.y; fb[2][y] = v.z; fb[3][y] = v.w;
+                }
+            }
+            // the next stage's copies go out between the sub-steps' matrix
+            // instructions rather than in one burst ahead of them
+            const bool more = s + RING - 1 < nst;
+            const int nslot = cur == 0 ? RING - 1 : cur - 1;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+#pragma unroll
+                for (int x = 0; x < BI; ++x) {
+                    const double a = (x & 1) ? fa[s4][x >> 1].y : fa[s4][x >> 1].x;
 #pragma unroll
                     for (int y = 0; y < BJ; ++y)
-                        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x], b[y], acc[x][y], 0, 0, 0);
+                        acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                            a, (double)fb[s4][y], acc[x][y], 0, 0, 0);
+                }
+                if (more) {
+#pragma unroll
+                    for (int q = s4; q < NI; q += 4) issue_one(nslot, s + RING - 1, q);
+                }
             }
+        };
+        // unrolled by the ring's length so that every slot offset is a constant
+        for (int s = 0; s < nst; s += RING) {
+            step(0, s);
+            if (s + 1 < nst) step(1, s + 1);
+            if (s + 2 < nst) step(2, s + 2);
+            if (RING == 4 && s + 3 < nst) step(3, s + 3);
         }
 
         // ---- epilogue.  Output (i, j) of a 16x16 block sits in lane
-        // j + 16 * (i % 4), register i / 4.
-        if (MODE == kModeAdj) {
+        // j + 16 * (i % 4), register i / 4; block x's row i is tile row
+        // wm * WTM + 32 * (x / 2) + 2 * i + x % 2.
+        if constexpr (ADJ) {
 #pragma unroll
             for (int bi = 0; bi < BI; ++bi)
 #pragma unroll
                 for (int bj = 0; bj < BJ; ++bj)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int p = m0 + wm * WTM + bi * 16 + lk + 4 * r;
+                        const int p = m0 + wm * WTM + 32 * (bi >> 1) + 2 * (lk + 4 * r) + (bi & 1);
                         const int col = n0 + wn * WTN + bj * 16 + li;
                         if (p < pr.M && col < pr.N)
                             *gmem(pr.C + (size_t)p * pr.ldc + col) = acc[bi][bj][r];
                     }
         } else {
-            // one 16-row strip of each wave at a time through LDS; four lanes
-            // share a row and take a quarter of the wave's columns each
-            double* stage = smem + wave * 16 * EPI;
+            // one 16-row strip of each wave at a time through the (now idle)
+            // ring; four lanes share a row and take a quarter of the wave's
+            // columns each, in column order
+            double* stage = reinterpret_cast<double*>(ring) + wave * 16 * EPI;
             constexpr int CQ = WTN / 4;
 #pragma unroll
             for (int bi = 0; bi < BI; ++bi) {
                 __syncthreads();
 #pragma unroll
-                for (int bj = 0; bj < BJ; ++bj)
+                for (int y = 0; y < BJ; ++y)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        stage[(lk + 4 * r) * EPI + bj * 16 + li] = acc[bi][bj][r];
+                        stage[(lk + 4 * r) * EPI + BJ * li + y] = acc[bi][y][r];
                 __syncthreads();
                 const int r16 = lane >> 2, cs = lane & 3;
-                const int i = wm * WTM + bi * 16 + r16;
+                const int i = wm * WTM + 32 * (bi >> 1) + 2 * r16 + (bi & 1);
                 const int p = m0 + i;
                 double dsum = 0.0, gsum = 0.0;
                 if (p < pr.M) {
-                    const double fb = *gmem(pr.theta + (size_t)p * kNTheta + 6);
+                    const double fbk = *gmem(pr.theta + (size_t)p * kNTheta + 6);
                     for (int q = 0; q < CQ; ++q) {
                         const int col = n0 + wn * WTN + cs * CQ + q;
                         if (col >= pr.N) break;
                         const double bj_ = *gmem(pr.b + col);
-                        const double mu = fb * bj_ + stage[r16 * EPI + cs * CQ + q];
+                        const double mu = fbk * bj_ + stage[r16 * EPI + cs * CQ + q];
                         const double nj = *gmem(pr.n + col);
                         double d;
                         if (nj > 0.0)

@@ -167,25 +167,42 @@ __device__ void rows_role(const RowArgs& a, int blk) {
     if (r >= a.n_comp * a.n_t) return;
     const int c = r / a.n_t, l = r - c * a.n_t;
     double4 s = make_double4(0.0, 0.0, 0.0, 0.0);
-    for (int q = a.compOff[c]; q < a.compOff[c + 1]; ++q) {
-        const int k = a.compSrc[q];
-        const int jj = a.jmin[(size_t)k * a.n_t + l];
-        double4 t = a.table[jj + k];
-        // totals of the chunks above node jj's chunk (none for the empty
-        // entry at the source's end)
-        const int end = a.srcOff[k + 1];
-        const int nch = jj < end ? (end - 1 - jj) / kStepThreads : 0;
-        for (int h = 0; h < nch; ++h) {
-            const double4 u = a.ctot[(size_t)k * a.max_chunks + h];
-            t.x += u.x;
-            t.y += u.y;
-            t.z += u.z;
-            t.w += u.w;
+    // Sources in groups of G: the node indices of a group, then its table
+    // entries, are loaded together rather than one source after another
+    // (each step is a dependent load; in sequence they set this role's
+    // time).  The sums keep their order.
+    constexpr int G = 8;
+    const int q0 = a.compOff[c], q1 = a.compOff[c + 1];
+    for (int g0 = q0; g0 < q1; g0 += G) {
+        int kk[G], jj[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) kk[u] = g0 + u < q1 ? a.compSrc[g0 + u] : -1;
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+            jj[u] = kk[u] >= 0 ? a.jmin[(size_t)kk[u] * a.n_t + l] : 0;
+        double4 t[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+            t[u] = kk[u] >= 0 ? a.table[jj[u] + kk[u]] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            if (kk[u] < 0) continue;
+            // totals of the chunks above node jj's chunk (none for the empty
+            // entry at the source's end)
+            const int end = a.srcOff[kk[u] + 1];
+            const int nch = jj[u] < end ? (end - 1 - jj[u]) / kStepThreads : 0;
+            for (int h = 0; h < nch; ++h) {
+                const double4 v = a.ctot[(size_t)kk[u] * a.max_chunks + h];
+                t[u].x += v.x;
+                t[u].y += v.y;
+                t[u].z += v.z;
+                t[u].w += v.w;
+            }
+            s.x += t[u].x;
+            s.y += t[u].y;
+            s.z += t[u].z;
+            s.w += t[u].w;
         }
-        s.x += t.x;
-        s.y += t.y;
-        s.z += t.z;
-        s.w += t.w;
     }
     const double T = a.tc[l];
     const double S = fma(T, fma(T, s.z, s.y), s.x) + s.w / T;

@@ -2535,14 +2535,25 @@ int nr_mlp_nll_dev(nr_mlp* q, nr_ctx* c, const double* d_theta, int B,
     const int n_pt = (B + 127) / 128;
     const int nnt = std::max(1, std::min((q->n_out + 127) / 128, (512 + n_pt - 1) / n_pt));
     if ((rc = mlp_input(q, d_theta, B, s, d_outside))) return rc;
-    if ((rc = mlp_hidden_forward(q, B, s))) return rc;
     nr::MlpGemm go = mg(q->h[2], ldh, 1, q->w16 + q->off[3], 1, ldh, B, q->n_out, ldh);
     go.mean = q->mean;
     go.stdv = q->stdv;
     go.nobs = c->d_n;
     go.part = q->part;
     go.n_nt = nnt;
-    HIPCHK(nr::launch_mlp_gemm(nr::kMlpNll, go, s));
+    if (q->H == nr::kFusedHidden) {
+        // the whole network in one launch, activations kept in LDS
+        nr::MlpHidden hd{};
+        hd.x = q->x;
+        for (int l = 0; l < 3; ++l) {
+            hd.w[l] = q->w16 + q->off[l];
+            hd.k[l] = q->kp[l];
+        }
+        HIPCHK(nr::launch_mlp_nll_fused(go, hd, s));
+    } else {
+        if ((rc = mlp_hidden_forward(q, B, s))) return rc;
+        HIPCHK(nr::launch_mlp_gemm(nr::kMlpNll, go, s));
+    }
     nr::FinalArgs f{};
     f.part = q->part;
     f.theta = d_theta;

@@ -87,7 +87,22 @@ struct TargetArgs {
     float* t;             // [P][N] standardised log mu
 };
 
+// The hidden layers for the fused inference kernel: input x [M][32]
+// (normalised theta, 1, zeros) and three layers of kFusedHidden outputs
+// with weights W_l [kFusedHidden][k_l], k_0 = 32 and k_1 = k_2 =
+// kFusedHidden + 8 (the inputs, the bias column, zeros).
+constexpr int kFusedHidden = 256;
+struct MlpHidden {
+    const bf16* x;
+    const bf16* w[3];
+    int k[3];
+};
+
 hipError_t launch_mlp_gemm(int mode, const MlpGemm& g, hipStream_t s);
+// The whole network and the likelihood partials in one launch (kMlpNll's
+// output with the hidden layers formed in LDS); g as for kMlpNll except
+// that g.A is not read.
+hipError_t launch_mlp_nll_fused(const MlpGemm& g, const MlpHidden& h, hipStream_t s);
 hipError_t launch_mlp_ksum(const KSumArgs& a, hipStream_t s);
 hipError_t launch_mlp_input(const MlpInput& a, hipStream_t s);
 // dst[c][r] = src[r][c] for a rows x cols row-major BF16 matrix

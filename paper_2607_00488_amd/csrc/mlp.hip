@@ -17,7 +17,14 @@ constexpr int TM = 128, TN = 128, TK = 32;
 constexpr int kMlpThreads = 256;
 constexpr int LDK = TK + 8;  // LDS row stride (bf16): rows stay 16-byte aligned
 
-__device__ inline float silu(float z) { return z / (1.f + __expf(-z)); }
+// SiLU(z) = z sigma(z) with the hardware reciprocal (one rounding of
+// ~1 ulp) in place of an IEEE division: the result is rounded to BF16
+// (2^-8 relative) right after, and the division's ten instructions per
+// value were a third of the fused network kernel's hidden-layer time.
+// z -> -inf gives z * rcp(inf) = -0, as the division would.
+__device__ inline float silu(float z) {
+    return z * __builtin_amdgcn_rcpf(1.f + __expf(-z));
+}
 
 // Loads one 128 x 32 operand tile (rows = m or n, k contiguous in LDS).
 // kc: the operand is k-contiguous in memory (16-byte chunks along k);
@@ -175,7 +182,73 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_gemm(MlpGemm g) {
 constexpr int kNllKS = 17;                  // K steps of 16: K <= 272
 constexpr int kNllLda = kNllKS * 16 + 8;    // A row stride in LDS (bf16)
 
-__global__ __launch_bounds__(kMlpThreads, 2) void k_mlp_nll(MlpGemm g) {
+// One hidden layer of the fused inference kernel, in place on the LDS
+// activation tile: wave w forms outputs [64 w, 64 w + 64) of all 128 points
+// (weights of its outputs as the row operand, straight from L2 into
+// registers four K-steps ahead; activations as the column operand from
+// LDS), then, once every wave has read the layer's input, writes SiLU of
+// them back as BF16.  A lane holds four consecutive outputs of one point
+// per register quad, stored as one 8-byte write.  The products and their
+// K order are those of the unfused layer GEMM.
+template <int NKS>
+__device__ __forceinline__ void hidden_layer(bf16 (*As)[kNllLda], const bf16* __restrict__ W, int K,
+                                    int wave, int li, int lh) {
+    f32x16 acc[4][2];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
+    constexpr int D = NKS < 4 ? NKS : 4;  // weight loads in flight (K-steps)
+    uint4 ring[D][2];
+    auto wload = [&](int ks, uint4 out[2]) {
+        const int k = ks * 16 + lh * 8;
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            const int o = wave * 64 + y * 32 + li;
+            out[y] = k < K ? *reinterpret_cast<const uint4*>(W + (long)o * K + k)
+                           : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+#pragma unroll
+    for (int ks = 0; ks < D; ++ks) wload(ks, ring[ks]);
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+        const uint4 w0 = ring[ks % D][0], w1 = ring[ks % D][1];
+        if (ks + D < NKS) wload(ks + D, ring[ks % D]);
+        const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&w0);
+        const bf16x8 b1 = *reinterpret_cast<const bf16x8*>(&w1);
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[x * 32 + li][ks * 16 + lh * 8]);
+            acc[x][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0, a, acc[x][0], 0, 0, 0);
+            acc[x][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1, a, acc[x][1], 0, 0, 0);
+        }
+    }
+    __syncthreads();  // every wave has read this layer's input
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                // outputs 8 q + 4 lh + e of block y, point x * 32 + li
+                bf16 v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = (bf16)silu(acc[x][y][4 * q + e]);
+                *reinterpret_cast<uint2*>(&As[x * 32 + li][wave * 64 + y * 32 + 8 * q + 4 * lh]) =
+                    *reinterpret_cast<const uint2*>(v);
+            }
+    __syncthreads();
+}
+
+// FUSED: the kernel first forms the points' activations itself from the
+// network input through the three hidden layers (the whole network in one
+// launch, nothing but theta's encoding read and the partial sums written);
+// otherwise it loads the last hidden layer's activations from g.A.
+template <bool FUSED>
+__global__ __launch_bounds__(kMlpThreads, 2) void k_mlp_nll(MlpGemm g, MlpHidden hd) {
     __shared__ bf16 As[TM][kNllLda];        // points x k
     __shared__ double cbuf[4][3][32];       // per wave: its 32 bins' constants
     __shared__ double red[4][TM];
@@ -183,14 +256,31 @@ __global__ __launch_bounds__(kMlpThreads, 2) void k_mlp_nll(MlpGemm g) {
     const int li = lane & 31, lh = lane >> 5;
     const int m0 = blockIdx.x * TM;
     constexpr int CH = kNllKS * 2;          // 16-byte chunks per row
-    for (int q = tid; q < TM * CH; q += kMlpThreads) {
-        const int row = q / CH, k = (q % CH) * 8, m = m0 + row;
-        const uint4 v = (m < g.M && k < g.K)
-                            ? *reinterpret_cast<const uint4*>(g.A + (long)m * g.sam + k)
-                            : make_uint4(0u, 0u, 0u, 0u);
-        *reinterpret_cast<uint4*>(&As[row][k]) = v;
+    if constexpr (FUSED) {
+        // the tile: inputs in columns 0..31, the bias input (1) at column
+        // kFusedHidden, zeros elsewhere
+        for (int q = tid; q < TM * (kNllLda / 8); q += kMlpThreads) {
+            const int row = q / (kNllLda / 8), k = (q % (kNllLda / 8)) * 8, m = m0 + row;
+            uint4 v = make_uint4(0u, 0u, 0u, 0u);
+            if (k < 32 && m < g.M) v = *reinterpret_cast<const uint4*>(hd.x + (long)m * 32 + k);
+            *reinterpret_cast<uint4*>(&As[row][k]) = v;
+        }
+        __syncthreads();
+        if (tid < TM) As[tid][kFusedHidden] = (bf16)1.f;
+        __syncthreads();
+        hidden_layer<2>(As, hd.w[0], hd.k[0], wave, li, lh);
+        hidden_layer<kNllKS>(As, hd.w[1], hd.k[1], wave, li, lh);
+        hidden_layer<kNllKS>(As, hd.w[2], hd.k[2], wave, li, lh);
+    } else {
+        for (int q = tid; q < TM * CH; q += kMlpThreads) {
+            const int row = q / CH, k = (q % CH) * 8, m = m0 + row;
+            const uint4 v = (m < g.M && k < g.K)
+                                ? *reinterpret_cast<const uint4*>(g.A + (long)m * g.sam + k)
+                                : make_uint4(0u, 0u, 0u, 0u);
+            *reinterpret_cast<uint4*>(&As[row][k]) = v;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     double pp[4] = {0.0, 0.0, 0.0, 0.0};
     const int nbt = (g.N + TN - 1) / TN;
     const int bt0 = (int)((long)nbt * blockIdx.y / gridDim.y);
@@ -357,12 +447,22 @@ hipError_t launch_mlp_gemm(int mode, const MlpGemm& g, hipStream_t s) {
             if (g.K > kNllKS * 16 || g.sak != 1 || g.sbk != 1 || g.n_nt < 1 ||
                 g.n_nt > (g.N + TN - 1) / TN)
                 return hipErrorInvalidValue;
-            hipLaunchKernelGGL(k_mlp_nll, dim3((g.M + TM - 1) / TM, g.n_nt), dim3(kMlpThreads),
-                               0, s, g);
+            hipLaunchKernelGGL(k_mlp_nll<false>, dim3((g.M + TM - 1) / TM, g.n_nt),
+                               dim3(kMlpThreads), 0, s, g, MlpHidden{});
             break;
         case kMlpLogMu: hipLaunchKernelGGL(k_mlp_gemm<kMlpLogMu>, grid, dim3(kMlpThreads), 0, s, g); break;
         default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_nll_fused(const MlpGemm& g, const MlpHidden& h, hipStream_t s) {
+    if (g.K > kNllKS * 16 || g.sak != 1 || g.sbk != 1 || g.n_nt < 1 || g.N % 8 ||
+        g.n_nt > (g.N + TN - 1) / TN || g.M % 8 || h.k[0] != 32 ||
+        h.k[1] != kFusedHidden + 8 || h.k[2] != kFusedHidden + 8 || g.K != kFusedHidden + 8)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_mlp_nll<true>, dim3((g.M + TM - 1) / TM, g.n_nt), dim3(kMlpThreads),
+                       0, s, g, h);
     return hipGetLastError();
 }
 

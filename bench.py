@@ -577,7 +577,7 @@ def mlp_counter_pass():
     """The surrogate network's kernels alone, for matrix-core counters: a
     7-256-256-256-4096 network (random weights; the work does not depend
     on them), 8 training steps of 2048 points, then 8 inference calls of
-    65536 points through the fused output-layer likelihood kernel.  Data
+    65536 points through the fused network-and-likelihood kernel.  Data
     and response are 4096 bins of a 512-row synthetic analysis (the network
     never reads the response)."""
     import torch

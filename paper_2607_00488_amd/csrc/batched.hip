@@ -108,10 +108,26 @@ __device__ inline void basis_dcoef(const double* th, const Phys& ph,
 // K-major layout the GEMM streams.  One thread per point, a strip of rows
 // per work-group row; the basis row is wave-uniform.
 constexpr int kWgenRows = 32;
+constexpr int kWgenCols = kNBasis + 2;  // the basis, S_SM and m of a row
 
 __global__ __launch_bounds__(256) void k_wgen(WgenArgs a) {
+    // The work-group's strip of rows (basis values, S_SM, m) is staged in
+    // LDS once; every lane then reads the same entries (broadcast).  Read
+    // from memory inside the per-row loop they were a chain of dependent
+    // round trips per row.
+    __shared__ double strip[kWgenRows][kWgenCols];
     const int p = blockIdx.x * 256 + threadIdx.x;
     const int l0 = blockIdx.y * kWgenRows;
+    const int nrow = min(kWgenRows, a.n_t - l0);
+    for (int q = threadIdx.x; q < kWgenRows * kWgenCols; q += 256) {
+        const int col = q / kWgenRows, r = q % kWgenRows, l = l0 + r;
+        double v = 0.0;
+        if (r < nrow)
+            v = col < kNBasis ? a.basis[(size_t)col * a.n_t + l]
+                              : (col == kNBasis ? a.ssm[l] : a.mrow[l]);
+        strip[r][col] = v;
+    }
+    __syncthreads();
     if (p >= a.ldw) return;
     double c[kNBasis];
     const bool ok = p < a.n_pts;
@@ -122,15 +138,13 @@ __global__ __launch_bounds__(256) void k_wgen(WgenArgs a) {
     } else {
         for (int b = 0; b < kNBasis; ++b) c[b] = 0.0;
     }
-    const int l1 = min(l0 + kWgenRows, a.n_t);
-    for (int l = l0; l < l1; ++l) {
+    for (int r = 0; r < nrow; ++r) {
         double s = 0.0;
 #pragma unroll
-        for (int b = 0; b < kNBasis; ++b)
-            s = fma(c[b], a.basis[(size_t)b * a.n_t + l], s);
-        const double ssm = a.ssm[l];
+        for (int b = 0; b < kNBasis; ++b) s = fma(c[b], strip[r][b], s);
+        const double ssm = strip[r][kNBasis];
         const double w = ssm > 0.0 ? s / ssm : 1.0;
-        a.wt[(size_t)l * a.ldw + p] = ok ? a.mrow[l] * w : 0.0;
+        a.wt[(size_t)(l0 + r) * a.ldw + p] = ok ? strip[r][kNBasis + 1] * w : 0.0;
     }
 }
 

@@ -63,7 +63,7 @@ struct FinalArgs {
 };
 
 struct ContractArgs {
-    const double* U; // [n_pts][ldu]
+    double* U;       // [n_pts][ldu]; its chunks' first columns take the partial sums
     int ldu, n_t, n_pts, n_nt;
     const double* ssm;
     const double* mrow;

@@ -509,44 +509,118 @@ __global__ void k_finalize(FinalArgs a) {
 
 // Gradient per point from the adjoint U[p][l] = sum_j a_pj R_lj:
 // grad_i = sum_l U_pl (m_l / S_SM(T_l)) sum_b dc_ib I_b(T_l) + [i = f_bkg]
-// sum_j a_pj b_j + pull term.  One work-group per point.
-__global__ __launch_bounds__(256) void k_adj_contract(ContractArgs a) {
-    __shared__ double jsh[4][kNBasis];
-    const int p = blockIdx.x;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    double J[kNBasis];
-    for (int b = 0; b < kNBasis; ++b) J[b] = 0.0;
-    for (int l = tid; l < a.n_t; l += 256) {
-        const double ssm = a.ssm[l];
-        if (!(ssm > 0.0)) continue;
-        const double u = a.U[(size_t)p * a.ldu + l] * (a.mrow[l] / ssm);
-#pragma unroll
-        for (int b = 0; b < kNBasis; ++b) J[b] = fma(u, a.basis[(size_t)b * a.n_t + l], J[b]);
+// sum_j a_pj b_j + pull term.
+// The contraction J[p][b] = sum_l U[p][l] v_l I_b(T_l), v_l = m_l / S_SM(T_l)
+// (0 where S_SM = 0), is itself a product of U (points x rows) with the
+// weighted basis (rows x 20): FP64 matrix instructions over blocks of 16
+// points and chunks of kCtrChunk rows, the four waves of a work-group on
+// quarters of its chunk.  With several chunks, each work-group leaves its
+// 16 x 20 partial sums in the first 20 columns of its own chunk of U (rows
+// only it reads, already consumed) and k_adj_final adds them per point in
+// chunk order; a single chunk finishes in place.
+constexpr int kCtrChunk = 1024;
+
+__host__ __device__ inline int ctr_chunks(int n_t) {
+    return n_t >= 2 * kCtrChunk ? n_t / kCtrChunk : 1;
+}
+
+// d(-2lnL)/d theta of point p from its contracted basis sums J (Eqs.
+// (logL), (reweight_factor): the chain through c_b(theta) and f_bkg) plus
+// the pulls.
+__device__ inline void contract_finish(const ContractArgs& a, int p, const double J[kNBasis]) {
+    double th[kNTheta];
+    for (int i = 0; i < kNTheta; ++i) th[i] = a.theta[(size_t)p * kNTheta + i];
+    double dc[kNTheta][kNBasis];
+    basis_dcoef(th, a.ph, dc);
+    double gb = 0.0;
+    for (int q = 0; q < a.n_nt; ++q) gb += a.part_gb[(size_t)p * a.n_nt + q];
+    for (int i = 0; i < kNTheta; ++i) {
+        double g = 0.0;
+        for (int b = 0; b < kNBasis; ++b) g += dc[i][b] * J[b];
+        if (i == 6) g += gb;
+        if (a.pull_sigma[i] > 0.0)
+            g += 2.0 * (th[i] - a.pull_mean[i]) / (a.pull_sigma[i] * a.pull_sigma[i]);
+        a.grad[(size_t)p * kNTheta + i] = g;
     }
-    for (int b = 0; b < kNBasis; ++b) {
-        const double s = wave_sum64(J[b]);
-        if (lane == 0) jsh[wave][b] = s;
+}
+
+__global__ __launch_bounds__(256) void k_adj_contract(ContractArgs a) {
+    __shared__ double red[4][16][kNBasis];
+    const int pb = blockIdx.x, ch = blockIdx.y, nch = gridDim.y;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int c0 = ch * kCtrChunk;
+    const int c1 = ch == nch - 1 ? a.n_t : c0 + kCtrChunk;
+    const int len = c1 - c0;
+    const int q0 = c0 + (int)((long)len * wave / 4), q1 = c0 + (int)((long)len * (wave + 1) / 4);
+    const int p = pb * 16 + li;  // this lane's row of the point operand
+    v4d acc[2] = {(v4d){0.0, 0.0, 0.0, 0.0}, (v4d){0.0, 0.0, 0.0, 0.0}};
+    // MFMA sub-step e gives lane row l + 4 (lane / 16) + e of the 16-row
+    // step; the next step's loads are issued before this step's arithmetic
+    struct Step { double u[4], b0[4], b1[4], sm[4], m[4]; };
+    auto load = [&](int l, Step& t) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int r = l + 4 * lk + e;
+            const bool ok = r < q1;
+            t.sm[e] = ok ? a.ssm[r] : 0.0;
+            t.m[e] = ok ? a.mrow[r] : 0.0;
+            t.u[e] = ok && p < a.n_pts ? a.U[(size_t)p * a.ldu + r] : 0.0;
+            t.b0[e] = ok ? a.basis[(size_t)li * a.n_t + r] : 0.0;
+            t.b1[e] = ok && 16 + li < kNBasis ? a.basis[(size_t)(16 + li) * a.n_t + r] : 0.0;
+        }
+    };
+    Step cur, nxt;
+    if (q0 < q1) load(q0, cur);
+    for (int l = q0; l < q1; l += 16) {
+        if (l + 16 < q1) load(l + 16, nxt);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const double v = cur.sm[e] > 0.0 ? cur.m[e] / cur.sm[e] : 0.0;
+            acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.u[e], cur.b0[e] * v, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(cur.u[e], cur.b1[e] * v, acc[1], 0, 0, 0);
+        }
+        cur = nxt;
+    }
+    // output (i, j) of a block: lane j + 16 (i % 4), register i / 4; here
+    // i is the point and j the basis index within block y
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = 16 * y + li;
+            if (b < kNBasis) red[wave][4 * r + lk][b] = acc[y][r];
+        }
+    __syncthreads();
+    // the four quarters in order; every wave has read its rows of U
+    for (int q = tid; q < 16 * kNBasis; q += 256) {
+        const int i = q / kNBasis, b = q % kNBasis, pp = pb * 16 + i;
+        const double J = red[0][i][b] + red[1][i][b] + red[2][i][b] + red[3][i][b];
+        if (nch > 1 && pp < a.n_pts) a.U[(size_t)pp * a.ldu + c0 + b] = J;
+        red[0][i][b] = J;
+    }
+    if (nch > 1) return;
+    __syncthreads();
+    if (tid < 16 && pb * 16 + tid < a.n_pts) contract_finish(a, pb * 16 + tid, red[0][tid]);
+}
+
+// The chunk partials of each point, added in chunk order (one lane per
+// point and basis index, so that a point's 20 partials of a chunk are one
+// contiguous read), then the gradient.
+constexpr int kFinPts = 256 / kNBasis;  // points per work-group
+
+__global__ __launch_bounds__(256) void k_adj_final(ContractArgs a, int nch) {
+    __shared__ double js[kFinPts][kNBasis];
+    const int t = threadIdx.x, i = t / kNBasis, b = t % kNBasis;
+    const int p = blockIdx.x * kFinPts + i;
+    if (i < kFinPts && p < a.n_pts) {
+        double J = 0.0;
+        for (int ch = 0; ch < nch; ++ch) J += a.U[(size_t)p * a.ldu + ch * kCtrChunk + b];
+        js[i][b] = J;
     }
     __syncthreads();
-    if (tid == 0) {
-        double Jt[kNBasis];
-        for (int b = 0; b < kNBasis; ++b)
-            Jt[b] = jsh[0][b] + jsh[1][b] + jsh[2][b] + jsh[3][b];
-        double th[kNTheta];
-        for (int i = 0; i < kNTheta; ++i) th[i] = a.theta[(size_t)p * kNTheta + i];
-        double dc[kNTheta][kNBasis];
-        basis_dcoef(th, a.ph, dc);
-        double gb = 0.0;
-        for (int q = 0; q < a.n_nt; ++q) gb += a.part_gb[(size_t)p * a.n_nt + q];
-        for (int i = 0; i < kNTheta; ++i) {
-            double g = 0.0;
-            for (int b = 0; b < kNBasis; ++b) g += dc[i][b] * Jt[b];
-            if (i == 6) g += gb;
-            if (a.pull_sigma[i] > 0.0)
-                g += 2.0 * (th[i] - a.pull_mean[i]) / (a.pull_sigma[i] * a.pull_sigma[i]);
-            a.grad[(size_t)p * kNTheta + i] = g;
-        }
-    }
+    const int pf = blockIdx.x * kFinPts + t;
+    if (t < kFinPts && pf < a.n_pts) contract_finish(a, pf, js[t]);
 }
 
 // ------------------------------------------------------------ templates
@@ -946,7 +1020,11 @@ hipError_t launch_finalize(const FinalArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_adj_contract(const ContractArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_adj_contract, dim3(a.n_pts), dim3(256), 0, s, a);
+    const int nch = ctr_chunks(a.n_t);
+    hipLaunchKernelGGL(k_adj_contract, dim3((a.n_pts + 15) / 16, nch), dim3(256), 0, s, a);
+    if (nch > 1)
+        hipLaunchKernelGGL(k_adj_final, dim3((a.n_pts + kFinPts - 1) / kFinPts), dim3(256), 0, s,
+                           a, nch);
     return hipGetLastError();
 }
 

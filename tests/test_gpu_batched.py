@@ -63,6 +63,31 @@ def test_batched_gradient_config0(cfg0):
         assert np.all(np.abs(g[i] - ref) <= 1e-4 * scale + 1e-6), (i, g[i], ref)
 
 
+@pytest.mark.parametrize("n_t", [2047, 3001])
+def test_gradient_contraction_chunks(n_t):
+    """The gradient's contraction over response rows runs in chunks of 1024
+    rows once there are at least 2048, the last chunk taking the remainder:
+    2047 rows finish in one chunk, 3001 in two (1024 and 1977 rows, not a
+    multiple of the 16-row steps).  Against the oracle's analytic gradient,
+    and against the single-point path's adjoint (other code) on every point."""
+    p = inputs(n_t, 200, 48, 300_000, 7401 + n_t, 7402 + n_t)
+    ctx = gpu_context(p)
+    o = p["oracle"]
+    th = synth.theta_prior(37, 7403)
+    th[:, 5:7] = synth.rng(7404).uniform(0.8, 1.2, (len(th), 2))
+    log(f"[gpu] batched gradient contraction, {n_t} rows")
+    nll, g = ctx.eval_nll_grad_batched(th)
+    for i in (0, 13, 36):
+        v, ref = o.nll_grad(th[i])
+        assert abs(nll[i] - v) <= 1e-3
+        scale = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+        assert np.all(np.abs(g[i] - ref) <= 1e-4 * scale + 1e-6), (i, g[i], ref)
+    _, gp = ctx.eval_nll_grad(th)
+    scale = np.maximum(np.abs(gp), 1e-6 * np.abs(gp).max())
+    assert np.all(np.abs(g - gp) <= 1e-9 * scale), np.max(np.abs(g - gp) / scale)
+    ctx.close()
+
+
 SHAPES = [  # n_t, n_reco, n_e, n_pts: tile edges in every dimension
     (256, 128, 64, 128),
     (300, 77, 40, 131),

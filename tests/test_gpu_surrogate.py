@@ -216,3 +216,40 @@ def test_network_seeded_fits(trained, torch_dev):
     # the network's starts find the exact minimum the uniform starts find
     assert abs(b2 - b1) <= 1e-6 * abs(b1) + 1e-6
     assert c2 < c1
+
+
+@pytest.mark.parametrize("H", [256, 128])
+def test_network_likelihood_ragged_batches(torch_dev, H):
+    """The network's -2lnL at batch sizes that are not multiples of the
+    kernels' 128-point tiles, for the whole-network kernel (256 hidden
+    units: hidden layers formed in LDS) and for the layer-by-layer path
+    (other widths), against -2lnL formed on the host from the network's
+    own log mu, with the bound of the FP32 exponential (no pulls here)."""
+    torch, dev = torch_dev
+    import math
+    from paper_2607_00488_amd.surrogate import Surrogate, init_params
+    import paper_2607_00488_amd as nr
+    p = config_inputs(0)
+    ctx = gpu_context(p)
+    lo, hi = synth.theta_box()
+    N = p["n_reco"]
+    s = Surrogate(N, lo, hi, hidden=H, seed=4101)
+    s.set_params(init_params(H, N, 4102, out_scale=1.0))
+    nr.nr_mlp_set_output_norm(s.h, np.full(N, 2.0, np.float32), np.full(N, 0.3, np.float32))
+    nobs = p["n"]
+    cdata = float(np.sum(nobs - np.where(nobs > 0, nobs * np.log(np.where(nobs > 0, nobs, 1)), 0)
+                         + np.array([math.lgamma(x + 1.0) for x in nobs])))
+    for B in (8, 136, 1000):
+        th = s.sample_box(B, 4103 + B)
+        got, outside = s.nll(ctx, th)
+        lm = s.logmu(th).cpu().numpy().astype(np.float64)
+        mu_h = np.exp(lm)
+        dvs = np.sum(mu_h - nobs + np.where(nobs > 0, nobs * (np.log(np.where(nobs > 0, nobs, 1)) - lm), 0.0), axis=1)
+        ref = 2.0 * (dvs + cdata)
+        bound = 2.0 * np.sum(np.abs(mu_h - nobs) * (np.abs(lm) * 2.0 ** -22 + 2.0 ** -21), axis=1)
+        d = np.abs(got.cpu().numpy() - ref)
+        log(f"[gpu] network -2lnL, {H} hidden, B = {B}: max |d| {d.max():.3g}")
+        assert not outside.any()
+        assert np.all(d <= bound + 1e-9 * np.abs(ref) + 1e-6), np.max(d - bound)
+    s.close()
+    ctx.close()

@@ -156,9 +156,10 @@ __global__ __launch_bounds__(256) void k_wgen(WgenArgs a) {
 // Operands reach LDS by gfx950's global-to-LDS copies: one instruction moves
 // 16 bytes per lane from any global address and writes them, in lane order,
 // as 1 KiB at a wave-uniform LDS base, without passing through registers.
-// The K-steps rotate through a ring of three stages, so each step waits
-// only for its own stage (copied two steps earlier) and has one barrier,
-// which also frees the stage read one step before for the next copy.  R
+// The K-steps rotate through a ring of three stages (four for the adjoint
+// where LDS allows), so each step waits only for its own stage (copied two
+// or three steps earlier) and has one barrier, which also frees the stage
+// read one step before for the next copy.  R
 // stays FP32 in LDS (half the bytes of FP64) and is widened when a wave
 // takes its fragment.  Lanes past an operand's edge copy a zero chunk.
 //
@@ -205,11 +206,11 @@ __device__ inline void wait_vm_lgkm0() {
     __builtin_amdgcn_s_waitcnt(N | (7 << 4));
 }
 
+// The tiles of 8192 outputs ask the compiler for register use that lets
+// three work-groups share a compute unit, the 128 x 128 tile two.
 template <int MODE, int BM, int BN>
-__global__ __launch_bounds__(kGemmThreads, BM * BN <= 8192 ? 3 : 2) void k_gemm(const GemmProb* probs,
-                                                       const GemmTile* tiles,
-                                                       int n_tiles,
-                                                       unsigned* ctr) {
+__global__ __launch_bounds__(kGemmThreads, BM * BN <= 8192 ? 3 : 2)
+void k_gemm(const GemmProb* probs, const GemmTile* tiles, int n_tiles, unsigned* ctr) {
     constexpr bool ADJ = MODE == kModeAdj;
     constexpr int WTM = BM / 2, WTN = BN / 2;   // wave tile
     constexpr int BI = WTM / 16, BJ = WTN / 16;  // 16x16 blocks per wave

@@ -5,6 +5,7 @@
 #include "mlp.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace nr {
 
@@ -171,16 +172,21 @@ __global__ __launch_bounds__(kMlpThreads) void k_mlp_gemm(MlpGemm g) {
 // One work-group per 128 points and group of bins (gridDim.y groups, so
 // that small batches still fill the chip), persistent over its bins: the
 // points' hidden activations (all of K <= 272) stay in LDS for the launch,
-// and each wave takes 32 bins of every 128-bin step, with the weights of
+// and each wave takes 64 bins of every 256-bin step, with the weights of
 // those bins loaded straight from memory (L2-resident) into the registers
-// that feed the matrix instruction: 17 independent 16-byte loads per lane,
-// issued together, then 68 matrix instructions with no barrier.  The bins
-// are the instruction's row operand and the points its column operand, so
-// a lane holds 16 bins of one point in each 32 x 32 block (lane = point +
-// 32 * half, register r = bin (r / 4) * 8 + half * 4 + r % 4) and the sum
-// over bins stays in registers until the end.
+// that feed the matrix instruction, four K-steps ahead in a ring that runs
+// on into the next step (its first loads are in flight while the wave forms
+// this step's exponentials).  Each activation fragment read from LDS feeds
+// two matrix instructions (136 per step, no barrier).  The bins are the
+// instruction's row operand and the points its column operand, so a lane
+// holds 16 bins of one point in each 32 x 32 block (lane = point + 32 *
+// half, register r = bin (r / 4) * 8 + half * 4 + r % 4) and the sum over
+// bins stays in registers until the end.
 constexpr int kNllKS = 17;                  // K steps of 16: K <= 272
 constexpr int kNllLda = kNllKS * 16 + 8;    // A row stride in LDS (bf16)
+constexpr int kOutBins = 64;                // bins per wave and step
+constexpr int kOutStep = 4 * kOutBins;      // bins per work-group and step
+constexpr int kOutRing = 4;                 // weight K-steps in flight
 
 // One hidden layer of the fused inference kernel, in place on the LDS
 // activation tile: wave w forms outputs [64 w, 64 w + 64) of all 128 points
@@ -202,13 +208,13 @@ __device__ __forceinline__ void hidden_layer(bf16 (*As)[kNllLda], const bf16* __
             for (int r = 0; r < 16; ++r) acc[x][y][r] = 0.f;
     constexpr int D = NKS < 4 ? NKS : 4;  // weight loads in flight (K-steps)
     uint4 ring[D][2];
+    // k clamped into the row: columns past K meet the tile's zero columns
     auto wload = [&](int ks, uint4 out[2]) {
-        const int k = ks * 16 + lh * 8;
+        const int k = min(ks * 16 + lh * 8, K - 8);
 #pragma unroll
         for (int y = 0; y < 2; ++y) {
             const int o = wave * 64 + y * 32 + li;
-            out[y] = k < K ? *reinterpret_cast<const uint4*>(W + (long)o * K + k)
-                           : make_uint4(0u, 0u, 0u, 0u);
+            out[y] = *reinterpret_cast<const uint4*>(W + (long)o * K + k);
         }
     };
 #pragma unroll
@@ -250,7 +256,8 @@ __device__ __forceinline__ void hidden_layer(bf16 (*As)[kNllLda], const bf16* __
 template <bool FUSED>
 __global__ __launch_bounds__(kMlpThreads, 2) void k_mlp_nll(MlpGemm g, MlpHidden hd) {
     __shared__ bf16 As[TM][kNllLda];        // points x k
-    __shared__ double cbuf[4][3][32];       // per wave: its 32 bins' constants
+    __shared__ float2 cms[4][kOutBins];     // per wave: its bins' (mean, std)
+    __shared__ double cnb[4][kOutBins];     // per wave: its bins' counts
     __shared__ double red[4][TM];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 31, lh = lane >> 5;
@@ -282,62 +289,110 @@ __global__ __launch_bounds__(kMlpThreads, 2) void k_mlp_nll(MlpGemm g, MlpHidden
         __syncthreads();
     }
     double pp[4] = {0.0, 0.0, 0.0, 0.0};
-    const int nbt = (g.N + TN - 1) / TN;
+    const int nbt = (g.N + kOutStep - 1) / kOutStep;
     const int bt0 = (int)((long)nbt * blockIdx.y / gridDim.y);
     const int bt1 = (int)((long)nbt * (blockIdx.y + 1) / gridDim.y);
-    for (int bt = bt0; bt < bt1; ++bt) {
-        const int nl = bt * TN + wave * 32 + li;   // this lane's bin for loads
+    // weight fragment of K-step ks of block x of step bt: bin bt kOutStep +
+    // 64 wave + 32 x + li, k = 16 ks + 8 lh, both clamped into the matrix
+    // (no predicated loads): columns past K meet the tile's zero columns,
+    // and a row past the bins (or past the last step, never used) feeds
+    // only terms whose constants below make them zero
+    auto wload = [&](int bt, int x, int ks) {
+        const int k = min(ks * 16 + lh * 8, g.K - 8);
+        const int n = min(bt * kOutStep + wave * kOutBins + x * 32 + li, g.N - 1);
+        return *reinterpret_cast<const uint4*>(g.B + (long)n * g.sbn + k);
+    };
+    // lane l's bin of step bt: its constants, neutral past the bins (ln mu
+    // = -200 gives mu = 0 in FP32, with n = 0: a zero term)
+    float cm, cs;
+    double cn;
+    auto cload = [&](int bt) {
+        const int nl = bt * kOutStep + wave * kOutBins + lane;
         const bool okn = nl < g.N;
-        uint4 bf[kNllKS];
+        cm = okn ? g.mean[nl] : -200.f;
+        cs = okn ? g.stdv[nl] : 0.f;
+        cn = okn ? g.nobs[nl] : 0.0;
+    };
+    // the wave's 64 bins' constants, shared through its own LDS slots
+    // (every lane has read the previous step's)
+    auto cstore = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        cms[wave][lane] = make_float2(cm, cs);
+        cnb[wave][lane] = cn;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    f32x16 acc[2][4];
+    // the four points' terms of register r of block x: -n ln mu exactly in
+    // FP64 (an integer count times an FP32 value), mu summed in FP32 over
+    // four registers (three roundings of at most 2^-24 of the partial sum,
+    // below the exponential's own error) before it joins the FP64 sum
+    float ms[4] = {0.f, 0.f, 0.f, 0.f};
+    auto epi_row = [&](int x, int r) {
+        const int i = x * 32 + (r >> 2) * 8 + lh * 4 + (r & 3);
+        const float2 c = cms[wave][i];
+        const double nob = cnb[wave][i];
 #pragma unroll
-        for (int ks = 0; ks < kNllKS; ++ks) {
-            const int k = ks * 16 + lh * 8;
-            bf[ks] = (okn && k < g.K)
-                         ? *reinterpret_cast<const uint4*>(g.B + (long)nl * g.sbn + k)
-                         : make_uint4(0u, 0u, 0u, 0u);
+        for (int y = 0; y < 4; ++y) {
+            const float lm = fmaf(c.y, acc[x][y][r], c.x);
+            ms[y] = (r & 3) ? ms[y] + __expf(lm) : __expf(lm);
+            pp[y] = fma(-nob, (double)lm, pp[y]);
+            if ((r & 3) == 3) pp[y] += (double)ms[y];
         }
-        const double cm = okn ? (double)g.mean[nl] : 0.0;
-        const double cs = okn ? (double)g.stdv[nl] : 0.0;
-        const double cn = okn ? g.nobs[nl] : 0.0;
-        f32x16 acc[4];
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[y][r] = 0.f;
+    };
+    // Half a step: the 68 matrix instructions of block X of step bt, with
+    // the exponentials of the other block (finished by the previous half
+    // step) interleaved, one register row per K-step, so that the wave's
+    // own vector instructions run while its matrix instructions execute.
+    // Weight fragments stream through a ring kOutRing K-steps deep whose
+    // stages run (bt, 0, 0..16), (bt, 1, 0..16), (bt + 1, 0, 0..16), ...
+    uint4 wr[kOutRing];
+    const f32x16 zero = {};
+    auto half = [&](int bt, auto xc, auto ec) {
+        constexpr int X = decltype(xc)::value;
+        constexpr bool EPI = decltype(ec)::value;
 #pragma unroll
         for (int ks = 0; ks < kNllKS; ++ks) {
-            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&bf[ks]);
+            const bf16x8 b = *reinterpret_cast<const bf16x8*>(&wr[0]);
+#pragma unroll
+            for (int q = 0; q + 1 < kOutRing; ++q) wr[q] = wr[q + 1];
+            const int ahead = ks + kOutRing;
+            if (ahead < kNllKS)
+                wr[kOutRing - 1] = wload(bt, X, ahead);
+            else
+                wr[kOutRing - 1] = X == 0 ? wload(bt, 1, ahead - kNllKS)
+                                          : wload(bt + 1, 0, ahead - kNllKS);
 #pragma unroll
             for (int y = 0; y < 4; ++y) {
                 const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[y * 32 + li][ks * 16 + lh * 8]);
-                acc[y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b, a, acc[y], 0, 0, 0);
+                acc[X][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b, a, ks == 0 ? zero : acc[X][y],
+                                                                   0, 0, 0);
             }
+            if (EPI && ks < 16) epi_row(1 - X, ks);
         }
-        // the wave's 32 bins' constants, shared through its own LDS slots
-        if (lh == 0) {
-            cbuf[wave][0][li] = cm;
-            cbuf[wave][1][li] = cs;
-            cbuf[wave][2][li] = cn;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    using X0 = std::integral_constant<int, 0>;
+    using X1 = std::integral_constant<int, 1>;
+    using Epi = std::true_type;
+    using NoEpi = std::false_type;
+    if (bt0 < bt1) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int i = (r >> 2) * 8 + lh * 4 + (r & 3);
-            if (bt * TN + wave * 32 + i >= g.N) continue;
-            const float mean = (float)cbuf[wave][0][i], sd = (float)cbuf[wave][1][i];
-            const double nob = cbuf[wave][2][i];
-#pragma unroll
-            for (int y = 0; y < 4; ++y) {
-                const float lm = fmaf(sd, acc[y][r], mean);
-                const double mu = (double)__expf(lm);
-                pp[y] += fma(-nob, (double)lm, mu);
-            }
+        for (int q = 0; q < kOutRing; ++q) wr[q] = wload(bt0, 0, q);
+        cload(bt0);
+        half(bt0, X0{}, NoEpi{});
+        cstore();
+        half(bt0, X1{}, Epi{});              // block 0 of step bt0
+        for (int bt = bt0 + 1; bt < bt1; ++bt) {
+            cload(bt);
+            half(bt, X0{}, Epi{});           // block 1 of step bt - 1
+            cstore();
+            half(bt, X1{}, Epi{});           // block 0 of step bt
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+        for (int r = 0; r < 16; ++r) epi_row(1, r);  // block 1 of the last step
     }
 #pragma unroll
     for (int y = 0; y < 4; ++y) {
@@ -444,7 +499,7 @@ hipError_t launch_mlp_gemm(int mode, const MlpGemm& g, hipStream_t s) {
         case kMlpNll:
             // the whole reduction in LDS, k contiguous in both operands
             // (n_nt bin groups, at most one per 128 bins)
-            if (g.K > kNllKS * 16 || g.sak != 1 || g.sbk != 1 || g.n_nt < 1 ||
+            if (g.K > kNllKS * 16 || g.K < 8 || g.sak != 1 || g.sbk != 1 || g.n_nt < 1 ||
                 g.n_nt > (g.N + TN - 1) / TN)
                 return hipErrorInvalidValue;
             hipLaunchKernelGGL(k_mlp_nll<false>, dim3((g.M + TM - 1) / TM, g.n_nt),

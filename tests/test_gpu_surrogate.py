@@ -225,21 +225,33 @@ def test_network_seeded_fits(trained, torch_dev):
     assert c2 < c1
 
 
-@pytest.mark.parametrize("H", [256, 128])
-def test_network_likelihood_ragged_batches(torch_dev, H):
+@pytest.mark.parametrize("H,N", [(256, None), (128, None), (256, 4000), (128, 4000)])
+def test_network_likelihood_ragged_batches(torch_dev, H, N):
     """The network's -2lnL at batch sizes that are not multiples of the
     kernels' 128-point tiles, for the whole-network kernel (256 hidden
     units: hidden layers formed in LDS) and for the layer-by-layer path
     (other widths), against -2lnL formed on the host from the network's
-    own log mu, with the bound of the FP32 exponential (no pulls here)."""
+    own log mu, with the bound of the FP32 exponential (no pulls here).
+    At the parity binning (256 bins) and at 4000 bins, which ends in part
+    of a 256-bin step: there the last waves' bins lie past the end and one
+    wave has none at all."""
     torch, dev = torch_dev
     import math
     from paper_2607_00488_amd.surrogate import Surrogate, init_params
     import paper_2607_00488_amd as nr
-    p = config_inputs(0)
-    ctx = gpu_context(p)
+    if N is None:
+        p = config_inputs(0)
+        ctx = gpu_context(p)
+        N = p["n_reco"]
+    else:
+        g = synth.rng(4100)
+        R = (g.random((64, N), dtype=np.float32) / N).astype(np.float32)
+        p = {"n": g.poisson(10.0, N).astype(np.float64)}
+        ctx = nr.Context(0)
+        ctx.set_sources(synth.source_nodes(64), 64)
+        ctx.set_response(R, n_sig=1e4)
+        ctx.set_data(p["n"], np.full(N, 10.0))
     lo, hi = synth.theta_box()
-    N = p["n_reco"]
     s = Surrogate(N, lo, hi, hidden=H, seed=4101)
     s.set_params(init_params(H, N, 4102, out_scale=1.0))
     nr.nr_mlp_set_output_norm(s.h, np.full(N, 2.0, np.float32), np.full(N, 0.3, np.float32))
@@ -255,7 +267,7 @@ def test_network_likelihood_ragged_batches(torch_dev, H):
         ref = 2.0 * (dvs + cdata)
         bound = exp_bound(mu_h, lm)
         d = np.abs(got.cpu().numpy() - ref)
-        log(f"[gpu] network -2lnL, {H} hidden, B = {B}: max |d| {d.max():.3g}")
+        log(f"[gpu] network -2lnL, {H} hidden, {N} bins, B = {B}: max |d| {d.max():.3g}")
         assert not outside.any()
         assert np.all(d <= bound + 1e-9 * np.abs(ref) + 1e-6), np.max(d - bound)
     s.close()

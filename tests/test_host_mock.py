@@ -46,25 +46,41 @@ def mock_lib(tmp_path_factory):
         names |= {ln.split()[-1] for ln in nm.stdout.splitlines() if "__hip_fatbin_" in ln}
     fat = d / "fatbins.c"
     fat.write_text("".join(f"char {n}[64];\n" for n in sorted(names)))
-    mock_o = str(d / "mock_hip.o")
-    subprocess.run([HIPCC] + FLAGS + ["-c", os.path.join(HERE, "c", "mock_hip.cpp"),
-                                      "-o", mock_o], check=True, capture_output=True)
     fat_o = str(d / "fatbins.o")
     subprocess.run([CLANGXX, "-x", "c", "-fPIC", "-c", str(fat), "-o", fat_o], check=True)
-    lib = str(d / "libnureweight_mock.so")
-    # -Bsymbolic: the library's own HIP calls bind to the stand-in
-    subprocess.run([CLANGXX, "-shared", "-fsanitize=address", "-shared-libasan",
-                    "-Wl,-Bsymbolic", "-o", lib] + objs + [mock_o, fat_o], check=True)
-    return lib, rt[0]
+    libs = {}
+    for tag, extra in (("", []), ("_short", ["-DMOCK_SHORT_ALLOC"])):
+        mock_o = str(d / f"mock_hip{tag}.o")
+        subprocess.run([HIPCC] + FLAGS + extra + ["-c", os.path.join(HERE, "c", "mock_hip.cpp"),
+                                                  "-o", mock_o], check=True, capture_output=True)
+        lib = str(d / f"libnureweight_mock{tag}.so")
+        # -Bsymbolic: the library's own HIP calls bind to the stand-in
+        subprocess.run([CLANGXX, "-shared", "-fsanitize=address", "-shared-libasan",
+                        "-Wl,-Bsymbolic", "-o", lib] + objs + [mock_o, fat_o], check=True)
+        libs[tag] = lib
+    return libs, rt[0]
+
+
+def run_sequence(lib, rt, which):
+    env = dict(os.environ, LD_PRELOAD=rt,
+               ASAN_OPTIONS="detect_leaks=0:abort_on_error=0:exitcode=23")
+    return subprocess.run([sys.executable, os.path.join(HERE, "host_mock_sequence.py"), lib,
+                           which], capture_output=True, text=True, timeout=600, env=env)
 
 
 @pytest.mark.parametrize("which", ["broad", "paper"])
 def test_host_code_on_cpu_stand_in(mock_lib, which):
-    lib, rt = mock_lib
-    env = dict(os.environ, LD_PRELOAD=rt,
-               ASAN_OPTIONS="detect_leaks=0:abort_on_error=0:exitcode=23")
-    r = subprocess.run([sys.executable, os.path.join(HERE, "host_mock_sequence.py"), lib, which],
-                       capture_output=True, text=True, timeout=600, env=env)
+    libs, rt = mock_lib
+    r = run_sequence(libs[""], rt, which)
     sys.stdout.write(r.stdout[-3000:] + r.stderr[-6000:])
     assert "AddressSanitizer" not in r.stderr
     assert r.returncode == 0 and "mock sequence done" in r.stdout
+
+
+def test_stand_in_reports_a_short_buffer(mock_lib):
+    """The harness is live: with device allocations 8 bytes short, the
+    first upload into one is reported."""
+    libs, rt = mock_lib
+    r = run_sequence(libs["_short"], rt, "broad")
+    assert r.returncode == 23, r.stdout[-2000:] + r.stderr[-2000:]
+    assert "AddressSanitizer: heap-buffer-overflow" in r.stderr

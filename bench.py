@@ -580,6 +580,38 @@ def gemm_counter_pass():
     log("[bench] GEMM counter pass done: 8 calls of 2 x 1024 x 4096 x 4096 flop")
 
 
+def grad_counter_pass():
+    """The batched likelihood and gradient alone, for hardware counters:
+    1024 points on the 16384 x 4096 shapes of the single-point benchmark
+    (the dense products read every entry, so a response histogrammed from
+    fewer events does the same work), eight calls after the tuner has
+    picked its tiles: the weights, the forward product with its Poisson
+    epilogue, the adjoint product and the gradient contraction."""
+    import torch
+    import synth
+    import paper_2607_00488_amd as nr
+    dev = torch.device("cuda:0")
+    src = synth.source_nodes(2048)
+    rsp = synth.response_mc(16384, 4096, 4_000_000, seed=2301, keep_counts=False)
+    ctx = nr.Context(0)
+    ctx.set_sources(src, 16384)
+    ctx.set_response(rsp.R, n_sig=1.0e4)
+    b = np.full(4096, 10.0)
+    ctx.set_data(b, b)
+    th = synth.theta_prior(1024, 2302)
+    tt = torch.tensor(th, dtype=torch.float64, device=dev)
+    nl = torch.empty(1024, dtype=torch.float64, device=dev)
+    gr = torch.empty(1024, 7, dtype=torch.float64, device=dev)
+    nr.eval_nll_multi_dev([ctx], [tt], [nl], [gr])   # tunes and captures
+    torch.cuda.synchronize()
+    for _ in range(8):
+        nr.eval_nll_multi_dev([ctx], [tt], [nl], [gr])
+    torch.cuda.synchronize()
+    ctx.close()
+    log("[bench] gradient counter pass done: 8 calls of 1024 points at 16384 x 4096, "
+        "2 x 2 x 1024 x 16384 x 4096 flop in the two products")
+
+
 def mlp_counter_pass():
     """The surrogate network's kernels alone, for matrix-core counters: a
     7-256-256-256-4096 network (random weights; the work does not depend
@@ -722,6 +754,9 @@ def main():
                     help="short run for matrix-core counters: the batched "
                          "likelihood GEMM of 1024 points on a 4096 x 4096 "
                          "dataset (a shape of the 64-dataset scan), 8 calls")
+    ap.add_argument("--grad-counter-pass", action="store_true",
+                    help="short run for matrix-core counters of the batched "
+                         "gradient: 8 calls of 1024 points at 16384 x 4096")
     ap.add_argument("--mlp-counter-pass", action="store_true",
                     help="short run for matrix-core counters of the surrogate "
                          "network: 8 training steps of 2048 points, 8 fused "
@@ -751,6 +786,9 @@ def main():
         return
     if args.mlp_counter_pass:
         mlp_counter_pass()
+        return
+    if args.grad_counter_pass:
+        grad_counter_pass()
         return
     p = build_plain(1)
     ctx, c = p["ctx"], p["cfg"]

@@ -553,16 +553,38 @@ __global__ __launch_bounds__(256) void k_adj_contract(ContractArgs a) {
     const int c0 = ch * kCtrChunk;
     const int c1 = ch == nch - 1 ? a.n_t : c0 + kCtrChunk;
     const int len = c1 - c0;
-    const int q0 = c0 + (int)((long)len * wave / 4), q1 = c0 + (int)((long)len * (wave + 1) / 4);
+    // quarters start on multiples of four rows (16-byte aligned pairs below)
+    const int q0 = c0 + ((int)((long)len * wave / 4) & ~3);
+    const int q1 = wave == 3 ? c1 : c0 + ((int)((long)len * (wave + 1) / 4) & ~3);
     const int p = pb * 16 + li;  // this lane's row of the point operand
     v4d acc[2] = {(v4d){0.0, 0.0, 0.0, 0.0}, (v4d){0.0, 0.0, 0.0, 0.0}};
     // MFMA sub-step e gives lane row l + 4 (lane / 16) + e of the 16-row
-    // step; the next step's loads are issued before this step's arithmetic
+    // step; the next step's loads are issued before this step's arithmetic.
+    // A lane's four rows are consecutive: with even row strides they are
+    // read as 16-byte pairs (every row offset of a lane is even), else, and
+    // for a group that runs past the quarter, one by one.
+    const bool pairs = a.ldu % 2 == 0 && a.n_t % 2 == 0;
     struct Step { double u[4], b0[4], b1[4], sm[4], m[4]; };
+    auto pair4 = [](const double* src, double out[4]) {
+        const double2 x = *reinterpret_cast<const double2*>(src);
+        const double2 y = *reinterpret_cast<const double2*>(src + 2);
+        out[0] = x.x; out[1] = x.y; out[2] = y.x; out[3] = y.y;
+    };
     auto load = [&](int l, Step& t) {
+        const int r0 = l + 4 * lk;
+        if (pairs && r0 + 3 < q1) {
+            pair4(a.ssm + r0, t.sm);
+            pair4(a.mrow + r0, t.m);
+            if (p < a.n_pts) pair4(a.U + (size_t)p * a.ldu + r0, t.u);
+            else t.u[0] = t.u[1] = t.u[2] = t.u[3] = 0.0;
+            pair4(a.basis + (size_t)li * a.n_t + r0, t.b0);
+            if (16 + li < kNBasis) pair4(a.basis + (size_t)(16 + li) * a.n_t + r0, t.b1);
+            else t.b1[0] = t.b1[1] = t.b1[2] = t.b1[3] = 0.0;
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const int r = l + 4 * lk + e;
+            const int r = r0 + e;
             const bool ok = r < q1;
             t.sm[e] = ok ? a.ssm[r] : 0.0;
             t.m[e] = ok ? a.mrow[r] : 0.0;

@@ -63,13 +63,16 @@ def test_batched_gradient_config0(cfg0):
         assert np.all(np.abs(g[i] - ref) <= 1e-4 * scale + 1e-6), (i, g[i], ref)
 
 
-@pytest.mark.parametrize("n_t", [2047, 3001])
+@pytest.mark.parametrize("n_t", [2047, 3001, 3002])
 def test_gradient_contraction_chunks(n_t):
     """The gradient's contraction over response rows runs in chunks of 1024
     rows once there are at least 2048, the last chunk taking the remainder:
     2047 rows finish in one chunk, 3001 in two (1024 and 1977 rows, not a
-    multiple of the 16-row steps).  Against the oracle's analytic gradient,
-    and against the single-point path's adjoint (other code) on every point."""
+    multiple of the 16-row steps).  With an even row count (3002) the rows
+    are read in 16-byte pairs, and the last chunk ends in part of a group
+    of four rows, which is read row by row.  Against the oracle's analytic
+    gradient, and against the single-point path's adjoint (other code) on
+    every point."""
     p = inputs(n_t, 200, 48, 300_000, 7401 + n_t, 7402 + n_t)
     ctx = gpu_context(p)
     o = p["oracle"]

@@ -320,9 +320,11 @@ def seeded_fit_study(ctx, sur, S=64, gtols=(1e-2, 1e-4)):
     return out
 
 
-# Matrix flop per point of the 7-256-256-256-4096 network: each layer's
-# inputs plus the bias column (K = 8, 257, 257, 257), no K padding.
-MLP_FLOP_PER_POINT = 2 * (8 * 256 + 2 * 257 * 256 + 257 * 4096)
+def mlp_flop_per_point(n_out, hidden=256):
+    """Matrix flop per point of the 7-H-H-H-n_out network: each layer's
+    inputs plus the bias column (K = 8, H + 1, H + 1, H + 1), no K padding
+    (2.37 MFLOP at H = 256, n_out = 4096)."""
+    return 2 * (8 * hidden + 2 * (hidden + 1) * hidden + (hidden + 1) * n_out)
 
 
 def surrogate_ceiling(ctx, sur, n_data, th_val, ks=(16, 32, 64)):
@@ -452,7 +454,7 @@ def surrogate_form(ctx, train_seconds=20.0, n_data=None):
         exact_batched_evals_per_s=round(B / t_exact, 1),
         gain_vs_exact_batched=round(t_exact / t_eval, 3),
         network_only_evals_per_s=round(B / t_net, 1),
-        network_tflops_bf16=round(B * MLP_FLOP_PER_POINT / t_net / 1e12, 2),
+        network_tflops_bf16=round(B * mlp_flop_per_point(ctx.n_reco) / t_net / 1e12, 2),
         val_abs_dnll=dict(median=q(0.5), q90=q(0.9), max=float(d.max()),
                           frac_le_0p1=float(np.mean(d <= 0.1)),
                           frac_le_1=float(np.mean(d <= 1.0))),

@@ -272,3 +272,45 @@ def test_network_likelihood_ragged_batches(torch_dev, H, N):
         assert np.all(d <= bound + 1e-9 * np.abs(ref) + 1e-6), np.max(d - bound)
     s.close()
     ctx.close()
+
+
+def test_network_likelihood_full_batch(torch_dev):
+    """The whole-network likelihood kernel at the surrogate form's
+    inference shape and launch (65 536 points, 4096 bins: one group of bins
+    per work-group, all 16 steps of 256 bins), on 96 sampled points against
+    -2lnL formed on the host from the network's own log mu."""
+    torch, dev = torch_dev
+    import math
+    from paper_2607_00488_amd.surrogate import Surrogate, init_params
+    import paper_2607_00488_amd as nr
+    N, B = 4096, 1 << 16
+    g = synth.rng(4201)
+    R = (g.random((256, N), dtype=np.float32) / N).astype(np.float32)
+    nobs = g.poisson(30.0, N).astype(np.float64)
+    ctx = nr.Context(0)
+    ctx.set_sources(synth.source_nodes(64), 256)
+    ctx.set_response(R, n_sig=1e4)
+    ctx.set_data(nobs, np.full(N, 10.0))
+    lo, hi = synth.theta_box()
+    s = Surrogate(N, lo, hi, hidden=256, seed=4202)
+    s.set_params(init_params(256, N, 4203, out_scale=1.0))
+    nr.nr_mlp_set_output_norm(s.h, np.full(N, 3.0, np.float32), np.full(N, 0.2, np.float32))
+    th = s.sample_box(B, 4204)
+    log(f"[gpu] network -2lnL at {B} points x {N} bins")
+    got, outside = s.nll(ctx, th)
+    got = got.cpu().numpy()
+    assert not outside.cpu().numpy().any()
+    idx = np.sort(synth.rng(4205).choice(B, 96, replace=False))
+    lm = s.logmu(th[torch.as_tensor(idx, device=dev)]).cpu().numpy().astype(np.float64)
+    mu_h = np.exp(lm)
+    cdata = float(np.sum(nobs - np.where(nobs > 0, nobs * np.log(np.where(nobs > 0, nobs, 1)), 0)
+                         + np.array([math.lgamma(x + 1.0) for x in nobs])))
+    dvs = np.sum(mu_h - nobs + np.where(nobs > 0, nobs * (np.log(np.where(nobs > 0, nobs, 1)) - lm), 0.0),
+                 axis=1)
+    ref = 2.0 * (dvs + cdata)
+    d = np.abs(got[idx] - ref)
+    bound = exp_bound(mu_h, lm)
+    log(f"[gpu] full batch: max |d| {d.max():.3g}, max d / bound {np.max(d / bound):.3g}")
+    assert np.all(d <= bound + 1e-9 * np.abs(ref) + 1e-6), np.max(d - bound)
+    s.close()
+    ctx.close()

@@ -80,7 +80,8 @@ def build_plain(cfg_id=1):
     mu_sm = ctx.eval_mu(synth.theta_sm())[0]
     n = synth.poisson_data(mu_sm, s["data"])
     ctx.set_data(n, b)
-    return dict(cfg=c, seeds=s, src=src, R=rsp.R, b=b, n=n, ctx=ctx)
+    return dict(cfg=c, seeds=s, src=src, R=rsp.R, b=b, n=n, ctx=ctx,
+                row_events=rsp.row_events)
 
 
 def build_batched(n_datasets=64):
@@ -245,6 +246,30 @@ def asimov_scan_form(p):
                    "f_8B and f_bkg profiled by batched L-BFGS (31 fits "
                    "advanced together), 90% CL interval at 2.706")
     return out
+
+
+def ess_form(ctx, row_events, seed, n_pts=40):
+    """The effective-sample-size diagnostic at the benchmark's shapes: per
+    point the node table and weights, then one non-temporal pass over R
+    forming both sums per observed bin.  Host-timed call of n_pts points
+    (the spectra come back to the host), after one warm call."""
+    import synth
+    ctx.set_mc_events(np.asarray(row_events, dtype=np.float64))
+    th = synth.theta_prior(n_pts, seed)
+    ctx.eval_ess(th[:2])
+    t0 = time.perf_counter()
+    ess = ctx.eval_ess(th)
+    dt = time.perf_counter() - t0
+    n_t, n_reco = ctx.n_t, ctx.n_reco
+    alg = 4 * n_t * n_reco + 16 * n_t + 8 * n_reco   # R, n w and n w^2, ESS out
+    return dict(evals_per_s=round(n_pts / dt, 1), points=n_pts,
+                us_per_eval=round(dt / n_pts * 1e6, 2),
+                gbs=round(alg * n_pts / dt / 1e9, 1),
+                frac_hbm=round(alg * n_pts / dt / 1e9 / 8000.0, 3),
+                finite=bool(np.all(np.isfinite(ess))),
+                what="ESS_j = (sum_l N_lj w_l)^2 / sum_l N_lj w_l^2 per observed bin "
+                     "(N_lj = R_lj n_l), one streaming pass over R per point; "
+                     "host-timed, copies and the final synchronisation included")
 
 
 def banded_form(ctx, R, tt, dense_out, stream):
@@ -975,6 +1000,9 @@ def main():
         f"({tf['grad_evals_per_s']:.0f} with gradient), fold "
         f"{tf['template_fold_ms']:.1f} ms once, max |d| vs plain "
         f"{tf['max_abs_dnll_vs_plain']:.2e}")
+    forms["ess"] = ef = ess_form(ctx, p["row_events"], p["seeds"]["theta"] + 9)
+    log(f"[bench] ESS diagnostic: {ef['evals_per_s']:.0f} evals/s "
+        f"({ef['us_per_eval']:.1f} us/eval, {ef['gbs']:.0f} GB/s)")
     forms["asimov_scan"] = sc = asimov_scan_form(p)
     log(f"[bench] Asimov scan (31 values, nuisances profiled): batched "
         f"{sc['batched']['seconds']:.3f} s warm / {sc['batched']['first_seconds']:.2f} s "

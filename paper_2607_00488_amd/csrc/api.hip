@@ -1774,7 +1774,7 @@ int nr_eval_ess(nr_ctx* c, const double* theta, int n_pts, double* ess) {
         ea.colpart = c->d_colpart;
         ea.rows_per_wg = c->rows_per_wg;
         ea.n_rb = c->n_rb;
-        ea.n_cc = (c->ldr / 4 + 63) / 64;  // the ESS fold's own 256-column tiles
+        ea.n_cc = nr::ess_col_tiles(c->ldr);  // the ESS fold's own column tiles
         ea.out = c->d_mu + (size_t)p * c->n_reco;
         HIPCHK(nr::launch_ess(ea, c->stream));
     }

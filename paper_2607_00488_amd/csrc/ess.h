@@ -14,6 +14,9 @@ struct EssArgs {
     double* out;          // [n_reco] ESS_j
 };
 
+// Column tiles of the ESS fold for a response row of ldr floats (n_cc).
+int ess_col_tiles(int ldr);
+
 hipError_t launch_ess(const EssArgs& a, hipStream_t s);
 
 }  // namespace nr

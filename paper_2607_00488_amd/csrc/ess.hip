@@ -20,17 +20,18 @@ __device__ inline float4 ld_stream4(const float4* p) {
 
 constexpr int kEssThreads = 512;
 constexpr int kEssWaves = kEssThreads / 64;
-constexpr int kEssCols = 256;
-constexpr int kEssUnroll = 4;
+constexpr int kEssCols = kEssWaves * 256;  // columns per tile: 256 per wave
+constexpr int kEssUnroll = 8;              // rows in flight per wave
 constexpr int kEssMaxRows = 2048;
 
-// Tile (rb, cc): rows [rb*rows, +rows), columns [cc*256, +256) of R, four
-// rows in flight per wave; u_l = n_l w_l and u2_l = n_l w_l^2 in LDS; FP64
-// products and sums; the two column partial sums of the tile go to
-// colpart[0] and colpart[1].
+// Tile (rb, cc): rows [rb*rows, +rows), columns [cc*2048, +2048) of R.  Each
+// wave takes 256 columns of every row, so the work-group reads each row as
+// one 8 KB run, kEssUnroll rows in flight per wave; u_l = n_l w_l and
+// u2_l = n_l w_l^2 in LDS; FP64 products and sums.  A lane's four columns'
+// two partial sums go to colpart[0] and colpart[1] directly (no other wave
+// touches its columns).
 __global__ __launch_bounds__(kEssThreads) void k_ess_fold(EssArgs a) {
     __shared__ double u1[kEssMaxRows], u2[kEssMaxRows];
-    __shared__ double red[2][kEssWaves][kEssCols + 1];
     const int rb = blockIdx.x % a.n_rb, cc = blockIdx.x / a.n_rb;
     const int row0 = rb * a.rows_per_wg;
     int nrows = a.n_t - row0;
@@ -43,83 +44,85 @@ __global__ __launch_bounds__(kEssThreads) void k_ess_fold(EssArgs a) {
     }
     __syncthreads();
     const int ld4 = a.ldr >> 2;
-    const int c4 = cc * 64 + lane;
+    const int c4 = cc * (kEssCols / 4) + wave * 64 + lane;
+    if (c4 >= ld4) return;
     double s[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
-    if (c4 < ld4) {
-        const float4* __restrict__ Rp =
-            reinterpret_cast<const float4*>(a.R) + (size_t)row0 * ld4 + c4;
-        int r = wave;
-        for (; r + kEssWaves * (kEssUnroll - 1) < nrows; r += kEssWaves * kEssUnroll) {
-            float4 x[kEssUnroll];
+    const float4* __restrict__ Rp =
+        reinterpret_cast<const float4*>(a.R) + (size_t)row0 * ld4 + c4;
+    auto acc = [&](const float4 x, int r) {
+        const double v = u1[r], v2 = u2[r];
+        s[0][0] = fma((double)x.x, v, s[0][0]);
+        s[0][1] = fma((double)x.y, v, s[0][1]);
+        s[0][2] = fma((double)x.z, v, s[0][2]);
+        s[0][3] = fma((double)x.w, v, s[0][3]);
+        s[1][0] = fma((double)x.x, v2, s[1][0]);
+        s[1][1] = fma((double)x.y, v2, s[1][1]);
+        s[1][2] = fma((double)x.z, v2, s[1][2]);
+        s[1][3] = fma((double)x.w, v2, s[1][3]);
+    };
+    int r = 0;
+    for (; r + kEssUnroll <= nrows; r += kEssUnroll) {
+        float4 x[kEssUnroll];
 #pragma unroll
-            for (int q = 0; q < kEssUnroll; ++q)
-                x[q] = ld_stream4(Rp + (size_t)(r + q * kEssWaves) * ld4);
+        for (int q = 0; q < kEssUnroll; ++q) x[q] = ld_stream4(Rp + (size_t)(r + q) * ld4);
 #pragma unroll
-            for (int q = 0; q < kEssUnroll; ++q) {
-                const double v = u1[r + q * kEssWaves], v2 = u2[r + q * kEssWaves];
-                s[0][0] = fma((double)x[q].x, v, s[0][0]);
-                s[0][1] = fma((double)x[q].y, v, s[0][1]);
-                s[0][2] = fma((double)x[q].z, v, s[0][2]);
-                s[0][3] = fma((double)x[q].w, v, s[0][3]);
-                s[1][0] = fma((double)x[q].x, v2, s[1][0]);
-                s[1][1] = fma((double)x[q].y, v2, s[1][1]);
-                s[1][2] = fma((double)x[q].z, v2, s[1][2]);
-                s[1][3] = fma((double)x[q].w, v2, s[1][3]);
-            }
-        }
-        for (; r < nrows; r += kEssWaves) {
-            const float4 z = ld_stream4(Rp + (size_t)r * ld4);
-            const double v = u1[r], v2 = u2[r];
-            s[0][0] = fma((double)z.x, v, s[0][0]);
-            s[0][1] = fma((double)z.y, v, s[0][1]);
-            s[0][2] = fma((double)z.z, v, s[0][2]);
-            s[0][3] = fma((double)z.w, v, s[0][3]);
-            s[1][0] = fma((double)z.x, v2, s[1][0]);
-            s[1][1] = fma((double)z.y, v2, s[1][1]);
-            s[1][2] = fma((double)z.z, v2, s[1][2]);
-            s[1][3] = fma((double)z.w, v2, s[1][3]);
-        }
+        for (int q = 0; q < kEssUnroll; ++q) acc(x[q], r + q);
     }
+    for (; r < nrows; ++r) acc(ld_stream4(Rp + (size_t)r * ld4), r);
 #pragma unroll
     for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) red[k][wave][4 * lane + i] = s[k][i];
-    __syncthreads();
-    if (tid < 2 * kEssCols) {
-        const int k = tid / kEssCols, ci = tid % kEssCols;
-        const int col = cc * kEssCols + ci;
-        if (col < a.ldr) {
-            double t = 0.0;
-            for (int w = 0; w < kEssWaves; ++w) t += red[k][w][ci];
-            a.colpart[((size_t)k * a.n_rb + rb) * a.ldr + col] = t;
-        }
-    }
+        for (int i = 0; i < 4; ++i)
+            a.colpart[((size_t)k * a.n_rb + rb) * a.ldr + 4 * c4 + i] = s[k][i];
 }
 
-// ESS_j from the row-tile partials (added in row-tile order); 0 for a bin
-// that no weighted event reaches.
-__global__ __launch_bounds__(256) void k_ess_finish(EssArgs a) {
-    const int col = blockIdx.x * 256 + threadIdx.x;
-    if (col >= a.n_reco) return;
+// ESS_j from the row-tile partials; 0 for a bin that no weighted event
+// reaches.  64 columns per work-group, 8 waves each adding every 8th
+// row-tile partial of its columns (all its loads in flight together), the
+// eight sums then combined in wave order: a fixed order, so the result is
+// reproducible.
+constexpr int kEssFinCols = 64;
+constexpr int kEssFinParts = 8;
+
+__global__ __launch_bounds__(kEssFinCols * kEssFinParts) void k_ess_finish(EssArgs a) {
+    __shared__ double part[2][kEssFinParts][kEssFinCols];
+    const int ci = threadIdx.x % kEssFinCols, q = threadIdx.x / kEssFinCols;
+    const int col = blockIdx.x * kEssFinCols + ci;
     double s1 = 0.0, s2 = 0.0;
-    for (int rb = 0; rb < a.n_rb; ++rb) {
-        s1 += a.colpart[(size_t)rb * a.ldr + col];
-        s2 += a.colpart[((size_t)a.n_rb + rb) * a.ldr + col];
+    if (col < a.n_reco) {
+        for (int rb = q; rb < a.n_rb; rb += kEssFinParts) {
+            s1 += a.colpart[(size_t)rb * a.ldr + col];
+            s2 += a.colpart[((size_t)a.n_rb + rb) * a.ldr + col];
+        }
     }
-    a.out[col] = s2 > 0.0 ? s1 * s1 / s2 : 0.0;
+    part[0][q][ci] = s1;
+    part[1][q][ci] = s2;
+    __syncthreads();
+    if (q == 0 && col < a.n_reco) {
+        double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kEssFinParts; ++k) {
+            t1 += part[0][k][ci];
+            t2 += part[1][k][ci];
+        }
+        a.out[col] = t2 > 0.0 ? t1 * t1 / t2 : 0.0;
+    }
 }
 
 }  // namespace
 
+int ess_col_tiles(int ldr) { return (ldr / 4 + kEssCols / 4 - 1) / (kEssCols / 4); }
+
 hipError_t launch_ess(const EssArgs& a, hipStream_t s) {
     if (a.rows_per_wg <= 0 || a.rows_per_wg > kEssMaxRows || a.n_rb <= 0 ||
-        a.n_cc != (a.ldr / 4 + 63) / 64 ||
+        a.n_cc != ess_col_tiles(a.ldr) ||
         (size_t)a.n_rb * a.rows_per_wg < (size_t)a.n_t)
         return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_ess_fold, dim3(a.n_rb * a.n_cc), dim3(kEssThreads), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_ess_finish, dim3((a.n_reco + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_ess_finish, dim3((a.n_reco + kEssFinCols - 1) / kEssFinCols),
+                       dim3(kEssFinCols * kEssFinParts), 0, s, a);
     return hipGetLastError();
 }
 

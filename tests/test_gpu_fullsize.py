@@ -203,3 +203,23 @@ def test_response_beyond_2g_elements():
     log(f"[gpu] beyond 2^31 elements: max |d(-2lnL)| {worst:.2e} over 3 forms x {len(th)} points")
     ctx.close()
     o.close()
+
+
+def test_ess_paper_scale(cfg1):
+    """The effective-sample-size diagnostic at the paper-scale shapes (two
+    2048-column tiles of the fold per row block, 128 row blocks), every bin
+    of three points against the oracle's definition."""
+    from oracle.diagnostics import ess
+    p, ctx = cfg1
+    o = p["oracle"]
+    ctx.set_mc_events(p["row_events"].astype(np.float64))
+    th = np.vstack([synth.theta_sm()[None], synth.theta_corners()[[31]],
+                    synth.theta_prior(1, 3011, f_range=(0.8, 1.2))])
+    log("[gpu] paper scale ESS, 3 points")
+    got = ctx.eval_ess(th)
+    w = np.vstack([o.weights(t) for t in th])
+    ref = ess(p["R"], p["row_events"], w)
+    scale = np.maximum(ref, 1e-6 * ref.max())
+    worst = float(np.max(np.abs(got - ref) / scale))
+    log(f"[gpu] paper scale ESS: max rel diff {worst:.2e}")
+    assert worst <= 1e-9

@@ -494,11 +494,32 @@ void k_gemm(const GemmProb* probs, const GemmTile* tiles, int n_tiles, unsigned*
 
 // -2lnL per point: sum of the column-tile deviance partials, data constant,
 // pulls (Eq. (logL)).
+// x[0] + x[1] + ... + x[n - 1] in index order; with n even (so that every
+// row of a [P][n] array starts 16-byte aligned) eight values at a time as
+// 16-byte pairs, all in flight before the additions.
+__device__ inline double row_sum(const double* x, int n) {
+    double s = 0.0;
+    int q = 0;
+    if ((n & 1) == 0) {
+        for (; q + 8 <= n; q += 8) {
+            double2 v[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = reinterpret_cast<const double2*>(x + q)[i];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                s += v[i].x;
+                s += v[i].y;
+            }
+        }
+    }
+    for (; q < n; ++q) s += x[q];
+    return s;
+}
+
 __global__ void k_finalize(FinalArgs a) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= a.n_pts) return;
-    double d = 0.0;
-    for (int q = 0; q < a.n_nt; ++q) d += a.part[(size_t)p * a.n_nt + q];
+    const double d = row_sum(a.part + (size_t)p * a.n_nt, a.n_nt);
     double pulls = 0.0;
     for (int i = 0; i < kNTheta; ++i)
         if (a.pull_sigma[i] > 0.0) {
@@ -533,8 +554,7 @@ __device__ inline void contract_finish(const ContractArgs& a, int p, const doubl
     for (int i = 0; i < kNTheta; ++i) th[i] = a.theta[(size_t)p * kNTheta + i];
     double dc[kNTheta][kNBasis];
     basis_dcoef(th, a.ph, dc);
-    double gb = 0.0;
-    for (int q = 0; q < a.n_nt; ++q) gb += a.part_gb[(size_t)p * a.n_nt + q];
+    const double gb = row_sum(a.part_gb + (size_t)p * a.n_nt, a.n_nt);
     for (int i = 0; i < kNTheta; ++i) {
         double g = 0.0;
         for (int b = 0; b < kNBasis; ++b) g += dc[i][b] * J[b];
